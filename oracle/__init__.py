@@ -1,0 +1,140 @@
+"""CPU oracle of the Gigapixel hot path (agent step + egocentric raster).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg
+of the benchmark may use this package; the product path never does.  It
+shares no code with the HIP library.  The arithmetic lives in gp_oracle.c
+(plain C, binary32 with explicit fmaf, int64 coverage); this module only
+compiles it with gcc and marshals numpy arrays through ctypes.
+"""
+from __future__ import annotations
+
+import concurrent.futures as _cf
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gp_oracle.c")
+_LIB = os.path.join(_HERE, "libgp_oracle.so")
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fPIC", "-shared", "-Wall"]
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile gp_oracle.c into libgp_oracle.so next to it."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Scene(C.Structure):
+    _fields_ = [("n_agents", C.c_int), ("n_roads", C.c_int),
+                ("agent_state", C.c_void_p), ("agent_dims", C.c_void_p),
+                ("agent_color", C.c_void_p), ("road_xy", C.c_void_p),
+                ("road_color", C.c_void_p)]
+
+
+class _Camera(C.Structure):
+    _fields_ = [("width", C.c_int), ("height", C.c_int),
+                ("focal_px", C.c_float), ("cam_height", C.c_float),
+                ("z_near", C.c_float), ("z_far", C.c_float),
+                ("palette", C.c_void_p)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = C.CDLL(_LIB)
+        L.gpo_sincos.argtypes = [C.c_float, C.POINTER(C.c_float), C.POINTER(C.c_float)]
+        L.gpo_step.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_float, C.c_void_p]
+        L.gpo_render_view.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.c_int, C.c_float,
+                                      C.c_float, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.POINTER(C.c_longlong)]
+        L.gpo_render_view.restype = C.c_longlong
+        L.gpo_cover_tri.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def sincos(t: float):
+    s, c = C.c_float(), C.c_float()
+    lib().gpo_sincos(C.c_float(t), C.byref(s), C.byref(c))
+    return np.float32(s.value), np.float32(c.value)
+
+
+def step(state: np.ndarray, dims: np.ndarray, act: np.ndarray, dt: float = 0.1):
+    """One kinematic step; returns (new_state [n,4], cos/sin psi [n,2]); inputs untouched."""
+    st = np.ascontiguousarray(state, dtype=np.float32).copy()
+    dm = np.ascontiguousarray(dims, dtype=np.float32)
+    ac = np.ascontiguousarray(act, dtype=np.float32)
+    cs = np.empty((st.shape[0], 2), dtype=np.float32)
+    lib().gpo_step(st.shape[0], _ptr(st), _ptr(dm), _ptr(ac), C.c_float(dt), _ptr(cs))
+    return st, cs
+
+
+def cover_tri(X, Y, W: int, H: int, count=None) -> np.ndarray:
+    """Add the coverage of one snapped triangle (1/256 px units) to count [H, W] (uint8)."""
+    x = np.ascontiguousarray(X, dtype=np.int32)
+    y = np.ascontiguousarray(Y, dtype=np.int32)
+    if count is None:
+        count = np.zeros((H, W), dtype=np.uint8)
+    lib().gpo_cover_tri(_ptr(x), _ptr(y), W, H, _ptr(count))
+    return count
+
+
+class View:
+    """Output of one rendered view."""
+
+    def __init__(self, rgb, depth, primid, n_tri, n_frag):
+        self.rgb, self.depth, self.primid = rgb, depth, primid
+        self.n_tri, self.n_frag = n_tri, n_frag
+
+
+def render_view(state, dims, agent_color, road_xy, road_color, camera, palette,
+                ego: int, cam_dir=(1.0, 0.0)) -> View:
+    """Render one ego view.  `camera` has width, height, focal_px, cam_height, z_near, z_far."""
+    st = np.ascontiguousarray(state, dtype=np.float32)
+    dm = np.ascontiguousarray(dims, dtype=np.float32)
+    ac = np.ascontiguousarray(agent_color, dtype=np.uint8)
+    rx = np.ascontiguousarray(road_xy, dtype=np.float32).reshape(-1, 4, 2)
+    rc = np.ascontiguousarray(road_color, dtype=np.uint8)
+    pal = np.ascontiguousarray(palette, dtype=np.uint8).reshape(256, 3)
+    sc = _Scene(st.shape[0], rx.shape[0], _ptr(st), _ptr(dm), _ptr(ac), _ptr(rx), _ptr(rc))
+    W, H = int(camera.width), int(camera.height)
+    cm = _Camera(W, H, camera.focal_px, camera.cam_height, camera.z_near, camera.z_far, _ptr(pal))
+    key = np.empty(H * W, dtype=np.uint64)
+    rgb = np.empty((H, W, 3), dtype=np.uint8)
+    depth = np.empty((H, W), dtype=np.float32)
+    prim = np.empty((H, W), dtype=np.int32)
+    nf = C.c_longlong(0)
+    nt = lib().gpo_render_view(C.byref(sc), C.byref(cm), int(ego), C.c_float(cam_dir[0]),
+                               C.c_float(cam_dir[1]), _ptr(key), _ptr(rgb), _ptr(depth),
+                               _ptr(prim), C.byref(nf))
+    return View(rgb, depth, prim, int(nt), int(nf.value))
+
+
+def render_scene_view(scene, camera, palette, ego: int, cam: int = 0) -> View:
+    """Render view (ego, cam) of a scenegen.Scene-like object."""
+    return render_view(scene.agent_state, scene.agent_dims, scene.agent_color, scene.road_xy,
+                       scene.road_color, camera, palette, ego, camera.cam_dirs[cam])
+
+
+def render_views(items, camera, palette, threads: int = 1):
+    """Render a list of (scene, ego, cam) items; threads > 1 runs views concurrently
+    (ctypes releases the GIL during each call)."""
+    fn = lambda it: render_scene_view(it[0], camera, palette, it[1], it[2])
+    if threads <= 1:
+        return [fn(it) for it in items]
+    with _cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(fn, items))

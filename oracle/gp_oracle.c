@@ -1,0 +1,484 @@
+/*
+ * CPU oracle for the Gigapixel hot path: the kinematic agent step and the
+ * per-agent egocentric raster of a bounding-box world.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the tests, the smoke check and the CPU baseline leg of
+ * the benchmark do.  It shares no source with the HIP library.
+ *
+ * What it follows (Gigapixel paper):
+ *   - Sec. 3.1: state S_t = (A_t, M, L_t); agents are cuboids, lane polylines
+ *     are thin planar strips; each agent gets an ego-centric perspective view.
+ *   - App. A, "High-Throughput Batched Rendering": one world (view) per ego
+ *     agent, cuboids and planes, per-instance colour (agents blue),
+ *     configurable resolution and camera set.
+ *   - App. A, "Action Space and Dynamics": kinematic bicycle model with the
+ *     wheelbase at 60% of the vehicle length, clipped acceleration, speed and
+ *     steering.  App. B, student table: dt = 0.1 s.
+ * The paper fixes no numeric conventions of the raster (fill rule, snapping,
+ * depth, ties) nor the dynamics constants; the readings taken here are listed
+ * in the design notes of the repository and restated beside each function.
+ *
+ * Precision: every decision in the method (vertex snap, coverage, depth test,
+ * winner) is taken in IEEE binary32, the precision of the kernels; the
+ * oracle therefore computes in binary32 with every fused multiply-add written
+ * as fmaf, correctly rounded division, and no contraction
+ * (-ffp-contract=off, no fast-math).  Coverage uses exact int64 arithmetic.
+ *
+ * Algorithm shape: plain definition.  For each view, every primitive is
+ * transformed, clipped, projected and split into triangles; every pixel
+ * sample inside a triangle's bounding box is tested; each pixel keeps the
+ * fragment with the largest total-order key.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+/* ------------------------------------------------------------- constants */
+#define PIO2_HI   1.57079637e+00f   /* binary32 nearest to pi/2            */
+#define PIO2_LO  -4.37113883e-08f   /* binary32 nearest to pi/2 - PIO2_HI  */
+#define TWO_OVER_PI 0.636619747f
+#define PI_F      3.14159274f
+#define TWO_PI_F  6.28318548f
+
+/* dynamics constants: the paper names clipping but gives no values */
+#define ACC_MIN  -6.0f
+#define ACC_MAX   3.0f
+#define STEER_MAX 0.5f
+#define V_MIN     0.0f
+#define V_MAX    30.0f
+#define WHEELBASE_FRAC 0.6f          /* App. A: wheelbase = 60% of length */
+
+/* --------------------------------------------------------------- sincos
+ * sin and cos of t for |t| <= 4 (larger t still gives a deterministic,
+ * slightly less accurate value).  Written from the mathematics:
+ *   - Cody-Waite reduction t = k*pi/2 + r, with pi/2 split in two binary32
+ *     terms, k = round-half-even(t * 2/pi);
+ *   - Taylor polynomials on |r| <= pi/4, evaluated by Horner with fmaf:
+ *       sin r = r + r^3 (-1/3! + r^2 (1/5! + r^2 (-1/7! + r^2 / 9!)))
+ *       cos r = 1 + r^2 (-1/2! + r^2 (1/4! + r^2 (-1/6! + r^2 (1/8! - r^2/10!))))
+ *   - quadrant k mod 4 selects (+-sin r, +-cos r).
+ */
+void gpo_sincos(float t, float *s_out, float *c_out)
+{
+    float kf = rintf(t * TWO_OVER_PI);
+    float r = fmaf(-kf, PIO2_HI, t);
+    r = fmaf(-kf, PIO2_LO, r);
+    float r2 = r * r;
+    float ps = fmaf(r2, 2.75573188e-06f, -1.98412701e-04f);
+    ps = fmaf(r2, ps, 8.33333377e-03f);
+    ps = fmaf(r2, ps, -1.66666672e-01f);
+    float sr = fmaf(r * r2, ps, r);
+    float pc = fmaf(r2, -2.75573200e-07f, 2.48015876e-05f);
+    pc = fmaf(r2, pc, -1.38888892e-03f);
+    pc = fmaf(r2, pc, 4.16666679e-02f);
+    pc = fmaf(r2, pc, -0.5f);
+    float cr = fmaf(r2, pc, 1.0f);
+    int q = ((int)kf) & 3;
+    float s, c;
+    switch (q) {
+    case 0: s = sr;  c = cr;  break;
+    case 1: s = cr;  c = -sr; break;
+    case 2: s = -sr; c = -cr; break;
+    default: s = -cr; c = sr; break;
+    }
+    *s_out = s;
+    *c_out = c;
+}
+
+static float clampf(float x, float lo, float hi) { return fminf(fmaxf(x, lo), hi); }
+
+/* ----------------------------------------------------------- agent step
+ * Kinematic bicycle, semi-implicit Euler, reference point at the box centre.
+ * state [n][4] = x, y, psi, v  (updated in place); dims [n][3] = L, W, H;
+ * act [n][2] = accel, steer.  cs_out [n][2] = cos psi, sin psi (optional).
+ *   a = clamp(accel, -6, 3); delta = clamp(steer, -0.5, 0.5)
+ *   v' = clamp(v + a dt, 0, 30)
+ *   kappa = sin(delta) / (cos(delta) * 0.6 L)        (App. A wheelbase)
+ *   psi' = psi + v' dt kappa, wrapped once into (-pi, pi]
+ *   x' = x + v' dt cos psi',  y' = y + v' dt sin psi'
+ */
+void gpo_step(int n, float *state, const float *dims, const float *act, float dt, float *cs_out)
+{
+    for (int i = 0; i < n; ++i) {
+        float x = state[4 * i + 0], y = state[4 * i + 1];
+        float psi = state[4 * i + 2], v = state[4 * i + 3];
+        float L = dims[3 * i + 0];
+        float a = clampf(act[2 * i + 0], ACC_MIN, ACC_MAX);
+        float delta = clampf(act[2 * i + 1], -STEER_MAX, STEER_MAX);
+        float v1 = clampf(fmaf(a, dt, v), V_MIN, V_MAX);
+        float sd, cd;
+        gpo_sincos(delta, &sd, &cd);
+        float kappa = sd / (cd * (WHEELBASE_FRAC * L));
+        float vdt = v1 * dt;
+        float psi1 = fmaf(vdt, kappa, psi);
+        if (psi1 > PI_F)
+            psi1 = psi1 - TWO_PI_F;
+        else if (psi1 <= -PI_F)
+            psi1 = psi1 + TWO_PI_F;
+        float sp, cp;
+        gpo_sincos(psi1, &sp, &cp);
+        state[4 * i + 0] = fmaf(vdt, cp, x);
+        state[4 * i + 1] = fmaf(vdt, sp, y);
+        state[4 * i + 2] = psi1;
+        state[4 * i + 3] = v1;
+        if (cs_out) {
+            cs_out[2 * i + 0] = cp;
+            cs_out[2 * i + 1] = sp;
+        }
+    }
+}
+
+/* ----------------------------------------------------------- rendering */
+
+typedef struct {
+    int n_agents, n_roads;
+    const float *agent_state;     /* [n_agents][4] x, y, psi, v */
+    const float *agent_dims;      /* [n_agents][3] L, W, H */
+    const uint8_t *agent_color;   /* [n_agents] */
+    const float *road_xy;         /* [n_roads][4][2] */
+    const uint8_t *road_color;    /* [n_roads] */
+} gpo_scene;
+
+typedef struct {
+    int width, height;
+    float focal_px, cam_height, z_near, z_far;
+    const uint8_t *palette;       /* [256][3] */
+} gpo_camera;
+
+typedef struct { float x, y, z; } v3;
+
+/* one view's camera: position, forward (fx, fy) in the ground plane */
+typedef struct {
+    float px, py, fx, fy, h;
+    float f, cx, cy, F256, CX256, CY256, G;
+    float z_near, z_far;
+    int W, H;
+} view_t;
+
+/* world point relative to the camera (dx, dy, Z) -> camera space:
+ * x right, y up, z forward (planar depth) */
+static v3 to_cam(const view_t *vw, float dx, float dy, float Z)
+{
+    v3 p;
+    p.z = fmaf(dx, vw->fx, dy * vw->fy);
+    p.x = fmaf(dx, vw->fy, -(dy * vw->fx));
+    p.y = Z - vw->h;
+    return p;
+}
+
+/* world direction -> camera space (same rotation, no translation) */
+static v3 dir_to_cam(const view_t *vw, float nx, float ny, float nz)
+{
+    v3 n;
+    n.z = fmaf(nx, vw->fx, ny * vw->fy);
+    n.x = fmaf(nx, vw->fy, -(ny * vw->fx));
+    n.y = nz;
+    return n;
+}
+
+/* -- clipping: Sutherland-Hodgman against one half-space at a time.
+ * Planes, in order: z >= near, z <= far, and the guard band |x|, |y| <= G z
+ * that keeps snapped coordinates below 2^29 subpixels.  Output order: walk
+ * the input vertices; keep a vertex that is inside; if the edge to the next
+ * vertex crosses the plane, emit the crossing.  The crossing is always
+ * computed from the inside endpoint towards the outside one, so an edge shared
+ * by two primitives is cut at the same point. */
+#define MAXV 12
+
+static float plane_dist(int plane, const view_t *vw, v3 p)
+{
+    switch (plane) {
+    case 0: return p.z - vw->z_near;
+    case 1: return vw->z_far - p.z;
+    case 2: return fmaf(vw->G, p.z, p.x);
+    case 3: return fmaf(vw->G, p.z, -p.x);
+    case 4: return fmaf(vw->G, p.z, p.y);
+    default: return fmaf(vw->G, p.z, -p.y);
+    }
+}
+
+static v3 crossing(int plane, const view_t *vw, v3 in, v3 out, float din, float dout)
+{
+    v3 r;
+    float t = din / (din - dout);
+    r.x = fmaf(t, out.x - in.x, in.x);
+    r.y = fmaf(t, out.y - in.y, in.y);
+    r.z = fmaf(t, out.z - in.z, in.z);
+    if (plane == 0) r.z = vw->z_near;
+    if (plane == 1) r.z = vw->z_far;
+    return r;
+}
+
+static int clip_plane(int plane, const view_t *vw, const v3 *in, int n, v3 *out)
+{
+    int m = 0;
+    for (int i = 0; i < n; ++i) {
+        v3 a = in[i], b = in[(i + 1) % n];
+        float da = plane_dist(plane, vw, a), db = plane_dist(plane, vw, b);
+        int ia = da >= 0.0f, ib = db >= 0.0f;
+        if (ia) out[m++] = a;
+        if (ia && !ib) out[m++] = crossing(plane, vw, a, b, da, db);
+        if (!ia && ib) out[m++] = crossing(plane, vw, b, a, db, da);
+    }
+    return m;
+}
+
+static int clip_polygon(const view_t *vw, v3 *poly, int n)
+{
+    v3 tmp[MAXV];
+    for (int plane = 0; plane < 6 && n > 0; ++plane) {
+        n = clip_plane(plane, vw, poly, n, tmp);
+        memcpy(poly, tmp, sizeof(v3) * (size_t)n);
+    }
+    return n;
+}
+
+/* -- per-pixel resolve state */
+typedef struct {
+    uint64_t *key;     /* [H*W] */
+    const view_t *vw;
+    long long frags;   /* fragments that passed coverage and invz > 0 */
+} target_t;
+
+static uint32_t f32_bits(float f) { uint32_t u; memcpy(&u, &f, 4); return u; }
+
+/* Is sample (Sx, Sy) inside the triangle?  Vertices in 1/256 pixel, positive
+ * orientation.  Edge k runs from vertex k to k+1;
+ * E_k = (X1-X0)(Sy-Y0) - (Y1-Y0)(Sx-X0).  Inside iff every E_k > 0, or
+ * E_k == 0 on a top edge (dY == 0, dX > 0) or a left edge (dY < 0). */
+static int covers(const int32_t *X, const int32_t *Y, int64_t Sx, int64_t Sy)
+{
+    for (int k = 0; k < 3; ++k) {
+        int64_t dX = (int64_t)X[(k + 1) % 3] - X[k], dY = (int64_t)Y[(k + 1) % 3] - Y[k];
+        int64_t E = dX * (Sy - Y[k]) - dY * (Sx - X[k]);
+        int top_left = (dY < 0) || (dY == 0 && dX > 0);
+        if (!(E > 0 || (E == 0 && top_left))) return 0;
+    }
+    return 1;
+}
+
+/* Test hook: add 1 to count[j*W + i] for every pixel sample the triangle
+ * covers (vertices in any orientation; zero area covers nothing). */
+void gpo_cover_tri(const int32_t *Xin, const int32_t *Yin, int W, int H, uint8_t *count)
+{
+    int32_t X[3] = {Xin[0], Xin[1], Xin[2]}, Y[3] = {Yin[0], Yin[1], Yin[2]};
+    int64_t area2 = ((int64_t)X[1] - X[0]) * ((int64_t)Y[2] - Y[0])
+                  - ((int64_t)X[2] - X[0]) * ((int64_t)Y[1] - Y[0]);
+    if (area2 == 0) return;
+    if (area2 < 0) {
+        int32_t sx = X[1], sy = Y[1];
+        X[1] = X[2]; Y[1] = Y[2]; X[2] = sx; Y[2] = sy;
+    }
+    for (int j = 0; j < H; ++j)
+        for (int i = 0; i < W; ++i)
+            if (covers(X, Y, 256 * (int64_t)i + 128, 256 * (int64_t)j + 128))
+                count[j * W + i]++;
+}
+
+/* Coverage of one triangle with vertices (X[k], Y[k]) in 1/256 pixel,
+ * oriented so that twice its signed area is positive.  Sample of pixel (i, j)
+ * is (256 i + 128, 256 j + 128), row 0 at the top.  Every covered sample with
+ * 1/z > 0 is a fragment; the pixel keeps the largest key
+ * (1/z bits, class, inverted primitive index). */
+static void raster_tri(target_t *t, const int32_t *X, const int32_t *Y,
+                       float A, float B, float C, uint32_t cls, uint32_t prim)
+{
+    const view_t *vw = t->vw;
+    int64_t xmin = X[0], xmax = X[0], ymin = Y[0], ymax = Y[0];
+    for (int k = 1; k < 3; ++k) {
+        if (X[k] < xmin) xmin = X[k];
+        if (X[k] > xmax) xmax = X[k];
+        if (Y[k] < ymin) ymin = Y[k];
+        if (Y[k] > ymax) ymax = Y[k];
+    }
+    /* pixels whose sample can lie in the bounding box */
+    int64_t i0 = (xmin - 128 + 255) >> 8;        /* ceil((xmin-128)/256) */
+    int64_t i1 = (xmax - 128) >> 8;              /* floor((xmax-128)/256) */
+    int64_t j0 = (ymin - 128 + 255) >> 8;
+    int64_t j1 = (ymax - 128) >> 8;
+    if (i0 < 0) i0 = 0;
+    if (j0 < 0) j0 = 0;
+    if (i1 > vw->W - 1) i1 = vw->W - 1;
+    if (j1 > vw->H - 1) j1 = vw->H - 1;
+    for (int64_t j = j0; j <= j1; ++j) {
+        for (int64_t i = i0; i <= i1; ++i) {
+            if (!covers(X, Y, 256 * i + 128, 256 * j + 128)) continue;
+            float du = ((float)i + 0.5f) - vw->cx;
+            float dv = ((float)j + 0.5f) - vw->cy;
+            float invz = fmaf(A, du, fmaf(B, dv, C));
+            if (!(invz > 0.0f)) continue;
+            t->frags++;
+            uint64_t key = ((uint64_t)f32_bits(invz) << 32) | ((uint64_t)cls << 31)
+                         | (uint64_t)(0x7FFFFFFFu - prim);
+            uint64_t *slot = &t->key[j * vw->W + i];
+            if (key > *slot) *slot = key;
+        }
+    }
+}
+
+/* Clip, project, snap and raster one planar polygon (a box face or a road
+ * quad).  nc = camera-space normal, p0 = a point of the face (camera space).
+ * Boxes are one-sided: kept only if the camera is on the outer side (d < 0)
+ * and, per triangle, if the snapped triangle is front-facing.  Roads are
+ * two-sided: a triangle is flipped to positive orientation; zero area drops. */
+static int raster_polygon(target_t *t, v3 *poly, int n, v3 nc, v3 p0,
+                          int one_sided, uint32_t cls, uint32_t prim)
+{
+    const view_t *vw = t->vw;
+    float d = fmaf(nc.x, p0.x, fmaf(nc.y, p0.y, nc.z * p0.z));
+    if (one_sided && !(d < 0.0f)) return 0;
+    n = clip_polygon(vw, poly, n);
+    if (n < 3) return 0;
+    /* depth plane: 1/z = A du + B dv + C at pixel offsets du, dv from the centre */
+    float fd = vw->f * d;
+    float A = nc.x / fd;
+    float B = -nc.y / fd;
+    float C = nc.z / d;
+    int32_t X[MAXV], Y[MAXV];
+    for (int k = 0; k < n; ++k) {
+        float u = poly[k].x / poly[k].z;
+        float w = -(poly[k].y / poly[k].z);
+        X[k] = (int32_t)rintf(fmaf(u, vw->F256, vw->CX256));
+        Y[k] = (int32_t)rintf(fmaf(w, vw->F256, vw->CY256));
+    }
+    int ntri = 0;
+    for (int k = 1; k + 1 < n; ++k) {
+        int32_t tx[3] = {X[0], X[k], X[k + 1]};
+        int32_t ty[3] = {Y[0], Y[k], Y[k + 1]};
+        int64_t area2 = ((int64_t)tx[1] - tx[0]) * ((int64_t)ty[2] - ty[0])
+                      - ((int64_t)tx[2] - tx[0]) * ((int64_t)ty[1] - ty[0]);
+        if (one_sided) {
+            if (area2 >= 0) continue;   /* front faces come out negative in y-down screen space */
+        } else if (area2 == 0) {
+            continue;
+        }
+        if (area2 < 0) {               /* store with positive orientation */
+            int32_t sx = tx[1], sy = ty[1];
+            tx[1] = tx[2]; ty[1] = ty[2];
+            tx[2] = sx; ty[2] = sy;
+        }
+        raster_tri(t, tx, ty, A, B, C, cls, prim);
+        ++ntri;
+    }
+    return ntri;
+}
+
+static void make_view(view_t *vw, const gpo_scene *sc, const gpo_camera *cam, int ego, float ck, float sk)
+{
+    const float *st = sc->agent_state + 4 * ego;
+    float se, ce;
+    gpo_sincos(st[2], &se, &ce);
+    vw->px = st[0];
+    vw->py = st[1];
+    vw->fx = fmaf(ce, ck, -(se * sk));
+    vw->fy = fmaf(se, ck, ce * sk);
+    vw->h = cam->cam_height;
+    vw->W = cam->width;
+    vw->H = cam->height;
+    vw->f = cam->focal_px;
+    vw->cx = 0.5f * (float)cam->width;
+    vw->cy = 0.5f * (float)cam->height;
+    vw->F256 = 256.0f * vw->f;
+    vw->CX256 = 256.0f * vw->cx;
+    vw->CY256 = 256.0f * vw->cy;
+    vw->G = 268435456.0f / vw->F256;    /* guard band: |x/z| <= 2^28 / F256 */
+    vw->z_near = cam->z_near;
+    vw->z_far = cam->z_far;
+}
+
+/* Render the view of agent `ego` through the camera whose yaw offset is
+ * (ck, sk) = (cos, sin).  Outputs (any may be NULL): rgb [H][W][3], depth
+ * [H][W] (1/invz, +inf for background), primid [H][W] (-1 for background).
+ * Primitive index: 6*agent + face for boxes, 6*n_agents + road for roads.
+ * Faces: 0 front, 1 left, 2 back, 3 right, 4 top, 5 bottom.
+ * `key_scratch` must hold H*W uint64.  Returns the number of rasterised
+ * triangles; *frags_out (optional) receives the fragment count. */
+long long gpo_render_view(const gpo_scene *sc, const gpo_camera *cam, int ego, float ck, float sk,
+                          uint64_t *key_scratch, uint8_t *rgb, float *depth, int32_t *primid,
+                          long long *frags_out)
+{
+    view_t vw;
+    make_view(&vw, sc, cam, ego, ck, sk);
+    const int W = vw.W, H = vw.H;
+    target_t t = { key_scratch, &vw, 0 };
+    for (int p = 0; p < W * H; ++p) key_scratch[p] = 0;
+    long long ntri = 0;
+    const uint32_t n_a = (uint32_t)sc->n_agents;
+
+    /* agent cuboids, the ego's own box excluded (one world per ego agent) */
+    for (int j = 0; j < sc->n_agents; ++j) {
+        if (j == ego) continue;
+        const float *st = sc->agent_state + 4 * j;
+        const float *dm = sc->agent_dims + 3 * j;
+        float sj, cj;
+        gpo_sincos(st[2], &sj, &cj);
+        float ox = st[0] - vw.px, oy = st[1] - vw.py;
+        float hl = 0.5f * dm[0], hw = 0.5f * dm[1], Hb = dm[2];
+        float ax = hl * cj, ay = hl * sj;        /* half length along the heading */
+        float bx = -(hw * sj), by = hw * cj;     /* half width to the left */
+        /* footprint, counter-clockwise seen from above:
+         * 0 front-right, 1 front-left, 2 back-left, 3 back-right */
+        float fxp[4] = { (ox + ax) - bx, (ox + ax) + bx, (ox - ax) + bx, (ox - ax) - bx };
+        float fyp[4] = { (oy + ay) - by, (oy + ay) + by, (oy - ay) + by, (oy - ay) - by };
+        v3 bot[4], top[4];
+        for (int k = 0; k < 4; ++k) {
+            bot[k] = to_cam(&vw, fxp[k], fyp[k], 0.0f);
+            top[k] = to_cam(&vw, fxp[k], fyp[k], Hb);
+        }
+        /* outward world normals per face */
+        float nwx[6] = { cj, -sj, -cj, sj, 0.0f, 0.0f };
+        float nwy[6] = { sj, cj, -sj, -cj, 0.0f, 0.0f };
+        float nwz[6] = { 0.0f, 0.0f, 0.0f, 0.0f, 1.0f, -1.0f };
+        for (int f = 0; f < 6; ++f) {
+            v3 poly[MAXV];
+            if (f < 4) {            /* side face over footprint edge f -> f+1 */
+                int a = f, b = (f + 1) & 3;
+                poly[0] = bot[a]; poly[1] = bot[b]; poly[2] = top[b]; poly[3] = top[a];
+            } else if (f == 4) {
+                poly[0] = top[0]; poly[1] = top[1]; poly[2] = top[2]; poly[3] = top[3];
+            } else {
+                poly[0] = bot[3]; poly[1] = bot[2]; poly[2] = bot[1]; poly[3] = bot[0];
+            }
+            v3 nc = dir_to_cam(&vw, nwx[f], nwy[f], nwz[f]);
+            v3 p0 = poly[0];
+            ntri += raster_polygon(&t, poly, 4, nc, p0, 1, 1u, (uint32_t)(6 * j + f));
+        }
+    }
+    /* road quads at z = 0, two-sided */
+    for (int r = 0; r < sc->n_roads; ++r) {
+        const float *q = sc->road_xy + 8 * r;
+        v3 poly[MAXV];
+        for (int k = 0; k < 4; ++k)
+            poly[k] = to_cam(&vw, q[2 * k] - vw.px, q[2 * k + 1] - vw.py, 0.0f);
+        v3 nc = dir_to_cam(&vw, 0.0f, 0.0f, 1.0f);
+        v3 p0 = poly[0];
+        ntri += raster_polygon(&t, poly, 4, nc, p0, 0, 0u, (uint32_t)(6 * n_a + r));
+    }
+
+    /* resolve */
+    for (int p = 0; p < W * H; ++p) {
+        uint64_t key = key_scratch[p];
+        int32_t prim = -1;
+        uint8_t color = 0;
+        float dep = INFINITY;
+        if (key != 0) {
+            uint32_t zb = (uint32_t)(key >> 32);
+            float invz;
+            memcpy(&invz, &zb, 4);
+            prim = (int32_t)(0x7FFFFFFFu - (uint32_t)(key & 0x7FFFFFFFu));
+            color = (prim < (int32_t)(6 * n_a)) ? sc->agent_color[prim / 6]
+                                                : sc->road_color[prim - 6 * (int32_t)n_a];
+            dep = 1.0f / invz;
+        }
+        if (rgb) {
+            rgb[3 * p + 0] = cam->palette[3 * color + 0];
+            rgb[3 * p + 1] = cam->palette[3 * color + 1];
+            rgb[3 * p + 2] = cam->palette[3 * color + 2];
+        }
+        if (depth) depth[p] = dep;
+        if (primid) primid[p] = prim;
+    }
+    if (frags_out) *frags_out = t.frags;
+    return ntri;
+}
