@@ -1,0 +1,155 @@
+/*
+ * gp.h -- C ABI of the Gigapixel hot path on MI355X (gfx950).
+ *
+ * The library advances a batch of driving scenes with a kinematic agent step
+ * and renders, for every agent, an ego-centric perspective view of a
+ * bounding-box world (agent cuboids plus flat road strips) into a uint8 RGB
+ * image that stays on the GPU.
+ *
+ * Paper passages (Gigapixel, "Scaling Self-Play for End-to-End Driving"):
+ *   - Sec. 3.1: the state S_t = (A_t, M, L_t) of agent boxes and map polylines;
+ *     O_pixel(S_t) renders S_t into an ego-centric perspective view on a
+ *     batched GPU renderer; agents are cuboids and lane polylines are thin
+ *     planar strips.
+ *   - App. A, "High-Throughput Batched Rendering": one world per ego agent,
+ *     all worlds rendered together in one batched launch; per-instance colour;
+ *     images exposed to the learner as a GPU tensor with no per-step CPU
+ *     transfer; image resolution and the camera set are configurable.
+ *   - App. A, "Action Space and Dynamics": kinematic bicycle with the
+ *     wheelbase at 60% of the vehicle length and clipped acceleration, speed
+ *     and steering; App. B (student hyper-parameters): dt = 0.1 s.
+ * The paper fixes no numeric conventions of the raster or the dynamics
+ * constants.  The conventions implemented (documented with each call below):
+ *   camera at the ego box centre, 1.6 m high, pitch 0; planar depth; pixel
+ *   samples at pixel centres, row 0 at the top; vertices snapped to 1/256
+ *   pixel (round half to even); top-left fill rule; box faces one-sided, road
+ *   strips two-sided; near/far clip at z_near/z_far; per-pixel winner = the
+ *   largest (1/z, agent-above-road, lower primitive index); the ego's own box
+ *   is not drawn; acceleration in [-6, 3] m/s^2, steering in [-0.5, 0.5] rad,
+ *   speed in [0, 30] m/s; project-owned sin/cos.
+ *
+ * Conventions of the ABI:
+ *   - Every device pointer argument is a plain device address (e.g. a torch
+ *     tensor's data_ptr()); every `stream` is a hipStream_t (NULL = default).
+ *   - Ownership: the caller owns all device memory, including the workspace
+ *     handed to gp_sim_create.  The library allocates no device memory; it
+ *     keeps only a small host-side handle.
+ *   - Calls are stream-ordered and return without synchronising the host.
+ *     The returned status reports argument and launch errors; a device fault
+ *     surfaces as GP_EDEVICE on a later call.
+ *   - No call aborts the process and no C++ exception crosses the ABI.
+ *   - One gp_sim is used by one host thread at a time.
+ */
+#ifndef GP_H
+#define GP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gp_sim gp_sim;
+
+typedef enum {
+    GP_OK = 0,
+    GP_EINVAL = -1,   /* bad argument; nothing was launched            */
+    GP_ENOMEM = -2,   /* workspace too small                          */
+    GP_EDEVICE = -3,  /* HIP runtime or launch error                  */
+    GP_ESTATE = -4    /* call not valid in the handle's current state */
+} gp_status;
+
+#define GP_MAX_CAMS 4
+
+/* Rendering and dynamics configuration, shared by every scene of a sim. */
+typedef struct {
+    int32_t width, height;            /* pixels, 1..1024 each                              */
+    int32_t n_cams;                   /* cameras per agent, 1..GP_MAX_CAMS                 */
+    float cam_dir[GP_MAX_CAMS][2];    /* (cos, sin) of each camera's yaw offset             */
+    float focal_px;                   /* focal length in pixels (width/2 for 90 deg HFOV)  */
+    float cam_height;                 /* camera height above the road plane, m (1.6)       */
+    float z_near, z_far;              /* clip distances along the view axis, m (0.5, 100)  */
+    float dt;                         /* step length, s (0.1)                              */
+    uint8_t palette[256][3];          /* RGB per colour index; entry 0 is the background   */
+} gp_config;
+
+/* One scene as host arrays (copied into the workspace by gp_sim_create). */
+typedef struct {
+    int32_t n_agents;                 /* >= 1 (the ego of each view is one of them)        */
+    int32_t n_roads;                  /* >= 0                                              */
+    const float *agent_state;         /* [n_agents][4] x, y (m), psi (rad), v (m/s)        */
+    const float *agent_dims;          /* [n_agents][3] length, width, height (m)           */
+    const uint8_t *agent_color;       /* [n_agents] palette index                          */
+    const float *road_xy;             /* [n_roads][4][2] corners (m) at z = 0, any winding */
+    const uint8_t *road_color;        /* [n_roads] palette index                           */
+} gp_scene_desc;
+
+/* Launch settings of the renderer.  Every setting gives bit-identical images;
+ * they only change speed (the autotuner picks among them). */
+typedef enum {
+    GP_SCHED_PLAIN = 0,       /* one launch per scene                                  */
+    GP_SCHED_PERSISTENT = 1   /* one launch; workgroups pull views from a work queue   */
+} gp_sched;
+
+typedef struct {
+    int32_t sched;            /* gp_sched                                             */
+    int32_t band_rows;        /* image rows per LDS depth-buffer band: 8, 16, 32 or 64 */
+    int32_t batch_tris;       /* triangles per LDS batch: 256, 512, 1024 or 2048       */
+    int32_t block_threads;    /* threads per workgroup: 256, 512 or 1024               */
+    int32_t blocks_per_cu;    /* persistent grid = blocks_per_cu * CUs (1..16)         */
+} gp_launch;
+
+/* Workspace bytes needed for these scenes (>= 0), or -1 on bad arguments. */
+int64_t gp_sim_required_bytes(const gp_config *cfg, const gp_scene_desc *scenes, int32_t n_scenes);
+
+/* Create a sim over n_scenes scenes.  Views are numbered scene-major, then
+ * agent, then camera: view = ((agent_base(s) + a) * n_cams + k).  Copies the
+ * scene arrays into d_workspace (stream-ordered on `stream`) and computes the
+ * initial heading cosines on the device.  The workspace must stay allocated
+ * until gp_sim_destroy. */
+gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32_t n_scenes,
+                        void *d_workspace, int64_t workspace_bytes, void *stream, gp_sim **out);
+
+gp_status gp_sim_set_launch(gp_sim *sim, const gp_launch *launch);
+gp_status gp_sim_get_launch(const gp_sim *sim, gp_launch *launch);
+
+/* One kinematic step of every agent (App. A dynamics).  d_actions: device
+ * float [total_agents][2] = (acceleration m/s^2, steering angle rad), in the
+ * agent order of the scenes.  Non-finite actions are clamped with fmin/fmax
+ * semantics (NaN becomes the lower bound). */
+gp_status gp_sim_step(gp_sim *sim, const float *d_actions, void *stream);
+
+/* Render every view of the current state.  d_rgb: device uint8
+ * [num_views][height][width][3] (required).  d_depth: optional device float
+ * [num_views][height][width], planar depth in m, +inf for background.
+ * d_primid: optional device int32 [num_views][height][width], -1 for
+ * background, else 6*agent + face (0 front, 1 left, 2 back, 3 right, 4 top,
+ * 5 bottom) for boxes and 6*n_agents + road for road strips, indices local
+ * to the scene. */
+gp_status gp_sim_render(gp_sim *sim, uint8_t *d_rgb, float *d_depth, int32_t *d_primid, void *stream);
+
+/* Step then render (rgb only) as one hipGraph replay.  The graph is captured
+ * on first use and re-captured when a pointer or the launch settings change.
+ * Uses the persistent schedule whatever the current launch setting. */
+gp_status gp_sim_step_render_graph(gp_sim *sim, const float *d_actions, uint8_t *d_rgb, void *stream);
+
+/* Copy the agent state [total_agents][4] out of / into the sim (device to
+ * device, stream-ordered).  set_state also refreshes the heading cosines. */
+gp_status gp_sim_get_state(gp_sim *sim, float *d_dst, void *stream);
+gp_status gp_sim_set_state(gp_sim *sim, const float *d_src, void *stream);
+
+int64_t gp_sim_num_views(const gp_sim *sim);
+int64_t gp_sim_num_agents(const gp_sim *sim);
+int32_t gp_sim_num_scenes(const gp_sim *sim);
+
+/* Free the host handle (and its graph).  Never frees the workspace. */
+void gp_sim_destroy(gp_sim *sim);
+
+/* Message for the last non-OK status returned on this thread. */
+const char *gp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GP_H */

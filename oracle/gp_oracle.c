@@ -210,6 +210,9 @@ static v3 crossing(int plane, const view_t *vw, v3 in, v3 out, float din, float 
     return r;
 }
 
+/* Returns the output count, or -1 if the output would exceed MAXV vertices
+ * (possible only for a self-intersecting input quad; such a polygon is
+ * dropped). */
 static int clip_plane(int plane, const view_t *vw, const v3 *in, int n, v3 *out)
 {
     int m = 0;
@@ -217,9 +220,14 @@ static int clip_plane(int plane, const view_t *vw, const v3 *in, int n, v3 *out)
         v3 a = in[i], b = in[(i + 1) % n];
         float da = plane_dist(plane, vw, a), db = plane_dist(plane, vw, b);
         int ia = da >= 0.0f, ib = db >= 0.0f;
-        if (ia) out[m++] = a;
-        if (ia && !ib) out[m++] = crossing(plane, vw, a, b, da, db);
-        if (!ia && ib) out[m++] = crossing(plane, vw, b, a, db, da);
+        if (ia) {
+            if (m == MAXV) return -1;
+            out[m++] = a;
+        }
+        if (ia != ib) {
+            if (m == MAXV) return -1;
+            out[m++] = ia ? crossing(plane, vw, a, b, da, db) : crossing(plane, vw, b, a, db, da);
+        }
     }
     return m;
 }
@@ -229,6 +237,7 @@ static int clip_polygon(const view_t *vw, v3 *poly, int n)
     v3 tmp[MAXV];
     for (int plane = 0; plane < 6 && n > 0; ++plane) {
         n = clip_plane(plane, vw, poly, n, tmp);
+        if (n < 0) return 0;
         memcpy(poly, tmp, sizeof(v3) * (size_t)n);
     }
     return n;

@@ -1,0 +1,460 @@
+// C ABI runtime of the Gigapixel hot path: argument checks, workspace
+// layout, scene upload, launch scheduling (per-scene, persistent work queue,
+// hipGraph replay) and error reporting.  The declarations and their contract
+// are in include/gp.h.
+#include "../../include/gp.h"
+#include "gp_device.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_last_error;
+
+gp_status fail(gp_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+gp_status fail(gp_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+gp_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(GP_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr int64_t kAlign = 256;
+int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    int64_t scenes, views, state, cs, dims, agent_color, roads, road_color, palette, queue, counter;
+    int64_t total;
+    int64_t n_agents, n_roads, n_views;
+};
+
+bool finite_cfg(const gp_config *c)
+{
+    return std::isfinite(c->focal_px) && std::isfinite(c->cam_height) && std::isfinite(c->z_near) &&
+           std::isfinite(c->z_far) && std::isfinite(c->dt);
+}
+
+gp_status check_inputs(const gp_config *cfg, const gp_scene_desc *sc, int32_t n)
+{
+    if (!cfg) return fail(GP_EINVAL, "cfg is NULL");
+    if (cfg->width < 1 || cfg->width > 1024 || cfg->height < 1 || cfg->height > 1024)
+        return fail(GP_EINVAL, "image size %dx%d outside 1..1024", cfg->width, cfg->height);
+    if (cfg->n_cams < 1 || cfg->n_cams > GP_MAX_CAMS)
+        return fail(GP_EINVAL, "n_cams %d outside 1..%d", cfg->n_cams, GP_MAX_CAMS);
+    if (!finite_cfg(cfg) || !(cfg->focal_px > 0.0f) || !(cfg->z_near > 0.0f) || !(cfg->z_far > cfg->z_near) ||
+        !(cfg->dt >= 0.0f))
+        return fail(GP_EINVAL, "camera/dynamics constants out of range");
+    if (256.0 * cfg->focal_px > 262144.0)
+        return fail(GP_EINVAL, "focal length above 1024 px");
+    for (int k = 0; k < cfg->n_cams; ++k)
+        if (!std::isfinite(cfg->cam_dir[k][0]) || !std::isfinite(cfg->cam_dir[k][1]))
+            return fail(GP_EINVAL, "camera direction %d not finite", k);
+    if (n < 1) return fail(GP_EINVAL, "n_scenes must be >= 1");
+    if (!sc) return fail(GP_EINVAL, "scenes is NULL");
+    int64_t na = 0, nr = 0;
+    for (int s = 0; s < n; ++s) {
+        const gp_scene_desc &d = sc[s];
+        if (d.n_agents < 1 || d.n_roads < 0)
+            return fail(GP_EINVAL, "scene %d: n_agents must be >= 1 and n_roads >= 0", s);
+        if (6LL * d.n_agents + d.n_roads >= (1LL << 31) - 1)
+            return fail(GP_EINVAL, "scene %d: too many primitives", s);
+        if (!d.agent_state || !d.agent_dims || !d.agent_color)
+            return fail(GP_EINVAL, "scene %d: agent arrays are NULL", s);
+        if (d.n_roads > 0 && (!d.road_xy || !d.road_color))
+            return fail(GP_EINVAL, "scene %d: road arrays are NULL", s);
+        na += d.n_agents;
+        nr += d.n_roads;
+    }
+    if (na * cfg->n_cams >= (1LL << 31)) return fail(GP_EINVAL, "too many views");
+    if (nr >= (1LL << 31)) return fail(GP_EINVAL, "too many roads");
+    return GP_OK;
+}
+
+Layout make_layout(const gp_config *cfg, const gp_scene_desc *sc, int32_t n)
+{
+    Layout L{};
+    for (int s = 0; s < n; ++s) {
+        L.n_agents += sc[s].n_agents;
+        L.n_roads += sc[s].n_roads;
+    }
+    L.n_views = L.n_agents * cfg->n_cams;
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) { int64_t at = o; o = align_up(o + std::max<int64_t>(bytes, 1)); return at; };
+    L.scenes = take(sizeof(gp::SceneRec) * (int64_t)n);
+    L.views = take(sizeof(gp::ViewRec) * L.n_views);
+    L.state = take(16 * L.n_agents);
+    L.cs = take(8 * L.n_agents);
+    L.dims = take(16 * L.n_agents);
+    L.agent_color = take(L.n_agents);
+    L.roads = take(32 * L.n_roads);
+    L.road_color = take(L.n_roads);
+    L.palette = take(768);
+    L.queue = take(4 * L.n_views);
+    L.counter = take(4);
+    L.total = o;
+    return L;
+}
+
+bool valid_launch(const gp_launch &l)
+{
+    const bool br = l.band_rows == 8 || l.band_rows == 16 || l.band_rows == 32 || l.band_rows == 64;
+    const bool bt = l.batch_tris == 256 || l.batch_tris == 512 || l.batch_tris == 1024 || l.batch_tris == 2048;
+    const bool th = l.block_threads == 256 || l.block_threads == 512 || l.block_threads == 1024;
+    const bool sc = l.sched == GP_SCHED_PLAIN || l.sched == GP_SCHED_PERSISTENT;
+    return br && bt && th && sc && l.blocks_per_cu >= 1 && l.blocks_per_cu <= 16;
+}
+
+}  // namespace
+
+struct gp_sim {
+    gp_config cfg;
+    int32_t n_scenes = 0;
+    Layout lay{};
+    std::vector<gp::SceneRec> scenes;
+    gp::DevSim dev{};
+    gp_launch launch{};
+    int device = 0;
+    int n_cu = 256;
+    size_t max_lds = 65536;
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    const float *g_act = nullptr;
+    uint8_t *g_rgb = nullptr;
+    gp_launch g_launch{};
+};
+
+namespace {
+
+gp::LaunchCfg launch_cfg(const gp_launch &l)
+{
+    gp::LaunchCfg c;
+    c.band_rows = l.band_rows;
+    c.batch_tris = l.batch_tris;
+    c.block_threads = l.block_threads;
+    return c;
+}
+
+gp_status check_lds(const gp_sim *sim, const gp_launch &l)
+{
+    const size_t need = gp::render_lds_bytes(sim->dev, launch_cfg(l));
+    if (need > sim->max_lds)
+        return fail(GP_EINVAL, "launch needs %zu B of LDS, the device allows %zu", need, sim->max_lds);
+    return GP_OK;
+}
+
+gp_status render_impl(gp_sim *sim, const gp::RenderOut &o, const gp_launch &l, hipStream_t st)
+{
+    const gp::LaunchCfg c = launch_cfg(l);
+    hipError_t e;
+    if (l.sched == GP_SCHED_PLAIN) {
+        for (int s = 0; s < sim->n_scenes; ++s) {
+            const gp::SceneRec &r = sim->scenes[s];
+            e = gp::launch_render(sim->dev, o, c, 0, r.view_base, r.n_agents * sim->cfg.n_cams, st);
+            if (e != hipSuccess) return hip_fail(e, "render launch");
+        }
+        return GP_OK;
+    }
+    e = gp::launch_reset_counter(sim->dev, st);
+    if (e != hipSuccess) return hip_fail(e, "queue reset");
+    const int64_t grid = std::min<int64_t>(sim->lay.n_views, (int64_t)l.blocks_per_cu * sim->n_cu);
+    e = gp::launch_render(sim->dev, o, c, 1, 0, (int)grid, st);
+    if (e != hipSuccess) return hip_fail(e, "render launch");
+    return GP_OK;
+}
+
+gp_status step_impl(gp_sim *sim, const float *act, const gp_launch &l, hipStream_t st)
+{
+    hipError_t e;
+    if (l.sched == GP_SCHED_PLAIN) {
+        for (int s = 0; s < sim->n_scenes; ++s) {
+            const gp::SceneRec &r = sim->scenes[s];
+            e = gp::launch_step(sim->dev, act, r.agent_base, r.n_agents, st);
+            if (e != hipSuccess) return hip_fail(e, "step launch");
+        }
+        return GP_OK;
+    }
+    e = gp::launch_step(sim->dev, act, 0, (int)sim->lay.n_agents, st);
+    if (e != hipSuccess) return hip_fail(e, "step launch");
+    return GP_OK;
+}
+
+void drop_graph(gp_sim *sim)
+{
+    if (sim->gexec) (void)hipGraphExecDestroy(sim->gexec);
+    if (sim->graph) (void)hipGraphDestroy(sim->graph);
+    sim->gexec = nullptr;
+    sim->graph = nullptr;
+}
+
+bool same_launch(const gp_launch &a, const gp_launch &b)
+{
+    return a.sched == b.sched && a.band_rows == b.band_rows && a.batch_tris == b.batch_tris &&
+           a.block_threads == b.block_threads && a.blocks_per_cu == b.blocks_per_cu;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gp_last_error(void) { return g_last_error.c_str(); }
+
+int64_t gp_sim_required_bytes(const gp_config *cfg, const gp_scene_desc *scenes, int32_t n_scenes)
+{
+    if (check_inputs(cfg, scenes, n_scenes) != GP_OK) return -1;
+    return make_layout(cfg, scenes, n_scenes).total;
+}
+
+gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32_t n_scenes,
+                        void *d_workspace, int64_t workspace_bytes, void *stream, gp_sim **out)
+{
+    if (!out) return fail(GP_EINVAL, "out is NULL");
+    *out = nullptr;
+    gp_status st = check_inputs(cfg, scenes, n_scenes);
+    if (st != GP_OK) return st;
+    const Layout L = make_layout(cfg, scenes, n_scenes);
+    if (!d_workspace) return fail(GP_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(d_workspace) % kAlign != 0)
+        return fail(GP_EINVAL, "workspace must be %lld-byte aligned", (long long)kAlign);
+    if (workspace_bytes < L.total)
+        return fail(GP_ENOMEM, "workspace has %lld bytes, %lld needed", (long long)workspace_bytes,
+                    (long long)L.total);
+
+    gp_sim *sim = new (std::nothrow) gp_sim();
+    if (!sim) return fail(GP_ENOMEM, "host allocation failed");
+    sim->cfg = *cfg;
+    sim->n_scenes = n_scenes;
+    sim->lay = L;
+    hipError_t e = hipGetDevice(&sim->device);
+    if (e != hipSuccess) { delete sim; return hip_fail(e, "hipGetDevice"); }
+    (void)hipDeviceGetAttribute(&sim->n_cu, hipDeviceAttributeMultiprocessorCount, sim->device);
+    int lds = 0;
+    (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, sim->device);
+    if (lds > 0) sim->max_lds = (size_t)lds;
+
+    // host image of the workspace
+    std::vector<unsigned char> host((size_t)L.total, 0);
+    auto at = [&](int64_t off) { return host.data() + off; };
+    sim->scenes.resize(n_scenes);
+    int32_t abase = 0, rbase = 0;
+    for (int s = 0; s < n_scenes; ++s) {
+        gp::SceneRec &r = sim->scenes[s];
+        r.agent_base = abase;
+        r.n_agents = scenes[s].n_agents;
+        r.road_base = rbase;
+        r.n_roads = scenes[s].n_roads;
+        r.view_base = abase * cfg->n_cams;
+        r.pad0 = r.pad1 = r.pad2 = 0;
+        abase += r.n_agents;
+        rbase += r.n_roads;
+    }
+    std::memcpy(at(L.scenes), sim->scenes.data(), sizeof(gp::SceneRec) * n_scenes);
+    auto *views = reinterpret_cast<gp::ViewRec *>(at(L.views));
+    auto *state = reinterpret_cast<float *>(at(L.state));
+    auto *dims = reinterpret_cast<float *>(at(L.dims));
+    auto *acol = at(L.agent_color);
+    auto *roads = reinterpret_cast<float *>(at(L.roads));
+    auto *rcol = at(L.road_color);
+    for (int s = 0; s < n_scenes; ++s) {
+        const gp_scene_desc &d = scenes[s];
+        const gp::SceneRec &r = sim->scenes[s];
+        for (int a = 0; a < d.n_agents; ++a) {
+            const int g = r.agent_base + a;
+            for (int k = 0; k < 4; ++k) state[4 * g + k] = d.agent_state[4 * a + k];
+            for (int k = 0; k < 3; ++k) dims[4 * g + k] = d.agent_dims[3 * a + k];
+            dims[4 * g + 3] = 0.0f;
+            acol[g] = d.agent_color[a];
+            for (int c = 0; c < cfg->n_cams; ++c) {
+                gp::ViewRec &v = views[(int64_t)g * cfg->n_cams + c];
+                v.scene = s;
+                v.ego_cam = a * 4 + c;
+            }
+        }
+        if (d.n_roads > 0) {
+            std::memcpy(roads + 8 * (int64_t)r.road_base, d.road_xy, sizeof(float) * 8 * (size_t)d.n_roads);
+            std::memcpy(rcol + r.road_base, d.road_color, (size_t)d.n_roads);
+        }
+    }
+    std::memcpy(at(L.palette), cfg->palette, 768);
+    // persistent queue: heavier scenes first, views of a scene adjacent so
+    // that they share the scene's geometry in L2
+    std::vector<int> order(n_scenes);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const int64_t ca = 6LL * scenes[a].n_agents + scenes[a].n_roads;
+        const int64_t cb = 6LL * scenes[b].n_agents + scenes[b].n_roads;
+        return ca > cb;
+    });
+    auto *queue = reinterpret_cast<int32_t *>(at(L.queue));
+    int64_t qi = 0;
+    for (int s : order) {
+        const gp::SceneRec &r = sim->scenes[s];
+        for (int v = 0; v < r.n_agents * cfg->n_cams; ++v) queue[qi++] = r.view_base + v;
+    }
+
+    unsigned char *base = static_cast<unsigned char *>(d_workspace);
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    e = hipMemcpyAsync(base, host.data(), (size_t)L.total, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    if (e != hipSuccess) { delete sim; return hip_fail(e, "workspace upload"); }
+
+    gp::DevSim &D = sim->dev;
+    D.scenes = reinterpret_cast<const gp::SceneRec *>(base + L.scenes);
+    D.views = reinterpret_cast<const gp::ViewRec *>(base + L.views);
+    D.state = reinterpret_cast<float4 *>(base + L.state);
+    D.cs = reinterpret_cast<float2 *>(base + L.cs);
+    D.dims = reinterpret_cast<const float4 *>(base + L.dims);
+    D.agent_color = base + L.agent_color;
+    D.roads = reinterpret_cast<const float4 *>(base + L.roads);
+    D.road_color = base + L.road_color;
+    D.palette = base + L.palette;
+    D.queue = reinterpret_cast<const int32_t *>(base + L.queue);
+    D.counter = reinterpret_cast<uint32_t *>(base + L.counter);
+    D.n_scenes = n_scenes;
+    D.n_agents = (int32_t)L.n_agents;
+    D.n_views = (int32_t)L.n_views;
+    D.width = cfg->width;
+    D.height = cfg->height;
+    D.n_cams = cfg->n_cams;
+    for (int k = 0; k < gp::kMaxCams; ++k) {
+        D.cam_dir[k][0] = cfg->cam_dir[k][0];
+        D.cam_dir[k][1] = cfg->cam_dir[k][1];
+    }
+    D.focal = cfg->focal_px;
+    D.cam_height = cfg->cam_height;
+    D.z_near = cfg->z_near;
+    D.z_far = cfg->z_far;
+    D.dt = cfg->dt;
+
+    e = gp::launch_cs(D, hs);
+    if (e != hipSuccess) { delete sim; return hip_fail(e, "heading cosines"); }
+
+    // default launch: persistent queue, a 32 KB band buffer
+    gp_launch l{};
+    l.sched = GP_SCHED_PERSISTENT;
+    l.band_rows = 64;
+    while (l.band_rows > 8 && 8LL * l.band_rows * cfg->width > 32768) l.band_rows /= 2;
+    l.batch_tris = 512;
+    l.block_threads = 256;
+    l.blocks_per_cu = 2;
+    sim->launch = l;
+    if (check_lds(sim, l) != GP_OK) { delete sim; return GP_EINVAL; }
+    e = hipStreamCreateWithFlags(&sim->capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) { delete sim; return hip_fail(e, "capture stream"); }
+    *out = sim;
+    return GP_OK;
+}
+
+gp_status gp_sim_set_launch(gp_sim *sim, const gp_launch *l)
+{
+    if (!sim || !l) return fail(GP_EINVAL, "NULL argument");
+    if (!valid_launch(*l)) return fail(GP_EINVAL, "launch settings out of range");
+    gp_status st = check_lds(sim, *l);
+    if (st != GP_OK) return st;
+    sim->launch = *l;
+    return GP_OK;
+}
+
+gp_status gp_sim_get_launch(const gp_sim *sim, gp_launch *l)
+{
+    if (!sim || !l) return fail(GP_EINVAL, "NULL argument");
+    *l = sim->launch;
+    return GP_OK;
+}
+
+gp_status gp_sim_step(gp_sim *sim, const float *d_actions, void *stream)
+{
+    if (!sim || !d_actions) return fail(GP_EINVAL, "NULL argument");
+    if (reinterpret_cast<uintptr_t>(d_actions) % 8 != 0) return fail(GP_EINVAL, "actions must be 8-byte aligned");
+    return step_impl(sim, d_actions, sim->launch, static_cast<hipStream_t>(stream));
+}
+
+gp_status gp_sim_render(gp_sim *sim, uint8_t *d_rgb, float *d_depth, int32_t *d_primid, void *stream)
+{
+    if (!sim || !d_rgb) return fail(GP_EINVAL, "NULL argument");
+    if (reinterpret_cast<uintptr_t>(d_rgb) % 4 != 0) return fail(GP_EINVAL, "rgb must be 4-byte aligned");
+    if ((d_depth && reinterpret_cast<uintptr_t>(d_depth) % 4) || (d_primid && reinterpret_cast<uintptr_t>(d_primid) % 4))
+        return fail(GP_EINVAL, "depth/primid must be 4-byte aligned");
+    gp::RenderOut o{d_rgb, d_depth, d_primid};
+    return render_impl(sim, o, sim->launch, static_cast<hipStream_t>(stream));
+}
+
+gp_status gp_sim_step_render_graph(gp_sim *sim, const float *d_actions, uint8_t *d_rgb, void *stream)
+{
+    if (!sim || !d_actions || !d_rgb) return fail(GP_EINVAL, "NULL argument");
+    if (reinterpret_cast<uintptr_t>(d_rgb) % 4 != 0 || reinterpret_cast<uintptr_t>(d_actions) % 8 != 0)
+        return fail(GP_EINVAL, "misaligned pointer");
+    gp_launch l = sim->launch;
+    l.sched = GP_SCHED_PERSISTENT;
+    if (!sim->gexec || sim->g_act != d_actions || sim->g_rgb != d_rgb || !same_launch(l, sim->g_launch)) {
+        drop_graph(sim);
+        hipError_t e = hipStreamBeginCapture(sim->capture_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "begin capture");
+        gp_status st = step_impl(sim, d_actions, l, sim->capture_stream);
+        gp::RenderOut o{d_rgb, nullptr, nullptr};
+        if (st == GP_OK) st = render_impl(sim, o, l, sim->capture_stream);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(sim->capture_stream, &g);
+        if (st != GP_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+        if (e != hipSuccess) return hip_fail(e, "end capture");
+        sim->graph = g;
+        e = hipGraphInstantiate(&sim->gexec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) { drop_graph(sim); return hip_fail(e, "graph instantiate"); }
+        sim->g_act = d_actions;
+        sim->g_rgb = d_rgb;
+        sim->g_launch = l;
+    }
+    hipError_t e = hipGraphLaunch(sim->gexec, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    return GP_OK;
+}
+
+gp_status gp_sim_get_state(gp_sim *sim, float *d_dst, void *stream)
+{
+    if (!sim || !d_dst) return fail(GP_EINVAL, "NULL argument");
+    hipError_t e = hipMemcpyAsync(d_dst, sim->dev.state, 16 * (size_t)sim->lay.n_agents,
+                                  hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? GP_OK : hip_fail(e, "get_state copy");
+}
+
+gp_status gp_sim_set_state(gp_sim *sim, const float *d_src, void *stream)
+{
+    if (!sim || !d_src) return fail(GP_EINVAL, "NULL argument");
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(sim->dev.state, d_src, 16 * (size_t)sim->lay.n_agents,
+                                  hipMemcpyDeviceToDevice, hs);
+    if (e != hipSuccess) return hip_fail(e, "set_state copy");
+    e = gp::launch_cs(sim->dev, hs);
+    return e == hipSuccess ? GP_OK : hip_fail(e, "heading cosines");
+}
+
+int64_t gp_sim_num_views(const gp_sim *sim) { return sim ? sim->lay.n_views : -1; }
+int64_t gp_sim_num_agents(const gp_sim *sim) { return sim ? sim->lay.n_agents : -1; }
+int32_t gp_sim_num_scenes(const gp_sim *sim) { return sim ? sim->n_scenes : -1; }
+
+void gp_sim_destroy(gp_sim *sim)
+{
+    if (!sim) return;
+    drop_graph(sim);
+    if (sim->capture_stream) (void)hipStreamDestroy(sim->capture_stream);
+    delete sim;
+}
+
+}  // extern "C"

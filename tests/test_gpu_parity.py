@@ -1,0 +1,312 @@
+"""HIP path vs the CPU oracle, through the C ABI, on the same seeded inputs.
+
+Bar: agent state bit-identical after every step; rgb and primitive ids
+bit-identical; depth within 1e-5 relative (bit-identical expected)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_19641_amd import scenegen as g
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2606_19641_amd import gp
+    gp.lib()
+
+
+def _sim(scenes, cam, pal, **launch):
+    from paper_2606_19641_amd import gp
+    s = gp.Sim(scenes, cam, pal)
+    if launch:
+        s.set_launch(**launch)
+    return s
+
+
+def _views_of(scenes, cam):
+    out = []
+    for si, s in enumerate(scenes):
+        for a in range(s.n_agents):
+            for k in range(len(cam.cam_dirs)):
+                out.append((si, a, k))
+    return out
+
+
+def _compare_views(scenes, cam, pal, rgb, depth, primid, picks, label=""):
+    """Compare GPU images of the picked (scene, agent, cam) views with the oracle."""
+    n_cams = len(cam.cam_dirs)
+    base = np.cumsum([0] + [s.n_agents for s in scenes])
+    for (si, a, k) in picks:
+        v = (base[si] + a) * n_cams + k
+        ref = oracle.render_scene_view(scenes[si], cam, pal, a, k)
+        got_rgb = rgb[v]
+        assert np.array_equal(got_rgb, ref.rgb), f"{label} rgb view {(si, a, k)}: " \
+            f"{int((got_rgb != ref.rgb).any(-1).sum())} px differ"
+        if primid is not None:
+            assert np.array_equal(primid[v], ref.primid), f"{label} primid view {(si, a, k)}"
+        if depth is not None:
+            d, r = depth[v], ref.depth
+            assert np.array_equal(np.isinf(d), np.isinf(r))
+            fin = np.isfinite(r)
+            rel = np.abs(d[fin].astype(np.float64) - r[fin]) / np.abs(r[fin])
+            assert rel.size == 0 or rel.max() <= 1e-5, f"{label} depth view {(si, a, k)} {rel.max()}"
+
+
+def _host_scene_state(scenes, state):
+    out, o = [], 0
+    for s in scenes:
+        out.append(g.Scene(agent_state=state[o:o + s.n_agents].copy(), agent_dims=s.agent_dims,
+                           agent_color=s.agent_color, road_xy=s.road_xy, road_color=s.road_color))
+        o += s.n_agents
+    return out
+
+
+# ------------------------------------------------------------------ step
+
+def test_step_bit_identical_each_step_small():
+    w = g.workload("small")
+    pal = g.default_palette()
+    sim = _sim(w.scenes, w.camera, pal)
+    st = np.concatenate([s.agent_state for s in w.scenes])
+    dims = np.concatenate([s.agent_dims for s in w.scenes])
+    for step in range(w.steps):
+        act = g.batch_actions(w.seed, step, w.scenes)
+        sim.step(torch.from_numpy(act).cuda())
+        got = sim.get_state().cpu().numpy()
+        ref, _ = oracle.step(st, dims, act, 0.1)
+        assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), f"step {step}"
+        st = got        # next step from the same pre-state on both sides
+
+
+def test_step_extreme_actions_bit_identical():
+    scenes = [g.crowded_scene(1)]
+    cam = g.camera_for(32)
+    sim = _sim(scenes, cam, g.default_palette())
+    n = scenes[0].n_agents
+    rng = np.random.default_rng(3)
+    act = (rng.standard_normal((n, 2)) * np.array([20.0, 2.0])).astype(np.float32)
+    act[0] = (np.nan, np.nan)
+    act[1] = (np.inf, -np.inf)
+    st = scenes[0].agent_state.copy()
+    for _ in range(5):
+        sim.step(torch.from_numpy(act).cuda())
+        got = sim.get_state().cpu().numpy()
+        st, _ = oracle.step(st, scenes[0].agent_dims, act, 0.1)
+        assert np.array_equal(got.view(np.uint32), st.view(np.uint32))
+
+
+# ------------------------------------------------------------------ render
+
+def test_small_workload_every_step_every_view():
+    """The small workload (1 scene, 8 agents, 200 quads, 64x64), 10 steps;
+    all views after every step, rgb + depth + primitive id."""
+    w = g.workload("small")
+    pal = g.default_palette()
+    sim = _sim(w.scenes, w.camera, pal)
+    st = np.concatenate([s.agent_state for s in w.scenes])
+    dims = np.concatenate([s.agent_dims for s in w.scenes])
+    for step in range(w.steps + 1):
+        rgb, depth, prim = sim.render(depth=True, primid=True)
+        torch.cuda.synchronize()
+        hs = _host_scene_state(w.scenes, st)
+        _compare_views(hs, w.camera, pal, rgb.cpu().numpy(), depth.cpu().numpy(), prim.cpu().numpy(),
+                       _views_of(hs, w.camera), f"step {step}")
+        if step < w.steps:
+            act = g.batch_actions(w.seed, step, w.scenes)
+            sim.step(torch.from_numpy(act).cuda())
+            st, _ = oracle.step(st, dims, act, 0.1)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_crowded_three_cameras(seed):
+    scenes = [g.crowded_scene(seed), g.crowded_scene(100 + seed, n_agents=9, n_roads=3)]
+    cam = g.camera_for(48, cams=g.FRONT_AND_SIDES)
+    pal = g.mixed_palette()
+    sim = _sim(scenes, cam, pal)
+    rgb, depth, prim = sim.render(depth=True, primid=True)
+    torch.cuda.synchronize()
+    _compare_views(scenes, cam, pal, rgb.cpu().numpy(), depth.cpu().numpy(), prim.cpu().numpy(),
+                   _views_of(scenes, cam))
+
+
+def test_nonsquare_and_ragged_width():
+    """Width not a multiple of 4 takes the byte-store path; 210x126 is the
+    paper's student resolution (App. B)."""
+    scenes = [g.crowded_scene(21)]
+    pal = g.mixed_palette()
+    for cam in (g.Camera(width=210, height=126, focal_px=105.0, cam_dirs=g.FRONT_AND_SIDES),
+                g.Camera(width=37, height=23, focal_px=18.5, cam_dirs=g.FRONT)):
+        sim = _sim(scenes, cam, pal)
+        rgb, depth, prim = sim.render(depth=True, primid=True)
+        torch.cuda.synchronize()
+        picks = [(0, a, k) for a in range(0, scenes[0].n_agents, 4) for k in range(len(cam.cam_dirs))]
+        _compare_views(scenes, cam, pal, rgb.cpu().numpy(), depth.cpu().numpy(), prim.cpu().numpy(),
+                       picks)
+
+
+def test_degenerate_scenes():
+    """A lone agent (empty view), no roads, a huge road quad (guard band),
+    zero-area and clockwise road strips, a flat box, boxes behind the camera."""
+    lone = g.Scene(agent_state=np.array([[0, 0, 0.3, 5]], np.float32),
+                   agent_dims=np.array([[4.5, 2, 1.5]], np.float32),
+                   agent_color=np.array([2], np.uint8), road_xy=np.zeros((0, 4, 2), np.float32),
+                   road_color=np.zeros(0, np.uint8))
+    roads = np.array([[[-1e5, -1e5], [1e5, -1e5], [1e5, 1e5], [-1e5, 1e5]],
+                      [[5, 1], [9, 1], [9, 1], [5, 1]],             # zero area
+                      [[4, -3], [4, 3], [30, 3], [30, -3]]], np.float32)   # clockwise
+    odd = g.Scene(agent_state=np.array([[0, 0, 0, 0], [8, 0, 0.2, 0], [-10, 0, 0, 0], [3, 0.5, 1.0, 0]], np.float32),
+                  agent_dims=np.array([[4, 2, 1.5], [8, 3, 0.0], [4, 2, 1.8], [4.5, 2, 1.4]], np.float32),
+                  agent_color=np.array([2, 3, 4, 5], np.uint8), road_xy=roads,
+                  road_color=np.array([1, 5, 1], np.uint8))
+    scenes = [lone, odd]
+    pal = g.mixed_palette()
+    for res in (32, 64):
+        cam = g.camera_for(res, cams=g.FRONT_AND_SIDES)
+        sim = _sim(scenes, cam, pal)
+        rgb, depth, prim = sim.render(depth=True, primid=True)
+        torch.cuda.synchronize()
+        _compare_views(scenes, cam, pal, rgb.cpu().numpy(), depth.cpu().numpy(), prim.cpu().numpy(),
+                       _views_of(scenes, cam))
+        assert np.all(prim.cpu().numpy()[:3] == -1)        # the lone agent sees nothing
+
+
+def test_overflow_fallback_path():
+    """A view with more triangles than one LDS batch holds goes band by band
+    with flushes; the image must not change."""
+    scene = g.make_scene(77, 0, 24, 8000)
+    cam = g.camera_for(128)
+    pal = g.default_palette()
+    sim = _sim([scene], cam, pal, batch_tris=256, band_rows=16)
+    rgb, depth, prim = sim.render(depth=True, primid=True)
+    torch.cuda.synchronize()
+    picks = [(0, a, 0) for a in range(0, 24, 3)]
+    _compare_views([scene], cam, pal, rgb.cpu().numpy(), depth.cpu().numpy(), prim.cpu().numpy(), picks)
+
+
+def _launch_variants():
+    out = []
+    for sched in (0, 1):
+        for band_rows in (8, 16, 32, 64):
+            for batch in (256, 512, 1024):
+                for threads in (256, 512):
+                    out.append(dict(sched=sched, band_rows=band_rows, batch_tris=batch,
+                                    block_threads=threads, blocks_per_cu=2))
+    return out
+
+
+def test_every_launch_variant_gives_identical_bits():
+    w = g.workload("uneven", n_scenes=6)
+    pal = g.default_palette()
+    sim = _sim(w.scenes, w.camera, pal)
+    ref = None
+    for lv in _launch_variants():
+        try:
+            sim.set_launch(**lv)
+        except Exception as e:      # a variant beyond the device's LDS limit is refused up front
+            assert "LDS" in str(e)
+            continue
+        rgb, depth, prim = sim.render(depth=True, primid=True)
+        torch.cuda.synchronize()
+        cur = (rgb.cpu().numpy(), depth.cpu().numpy(), prim.cpu().numpy())
+        if ref is None:
+            ref = cur
+            picks = [(s, a, k) for s in range(0, 6, 2) for a in (0, w.scenes[s].n_agents - 1) for k in range(3)]
+            _compare_views(w.scenes, w.camera, pal, *cur, picks)
+        else:
+            for a, b in zip(ref, cur):
+                assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), lv
+
+
+def test_uniform_full_size_bench_launch_sampled():
+    """64 scenes x 32 agents, 2,000 quads, 128x128, in the launch the bench
+    times (persistent, rgb only) for 3 steps; sampled views vs the oracle."""
+    w = g.workload("uniform")
+    pal = g.default_palette()
+    sim = _sim(w.scenes, w.camera, pal)
+    rgb = sim.new_rgb()
+    st = np.concatenate([s.agent_state for s in w.scenes])
+    dims = np.concatenate([s.agent_dims for s in w.scenes])
+    rng = np.random.default_rng(5)
+    for step in range(3):
+        act = g.batch_actions(w.seed, step, w.scenes)
+        sim.step(torch.from_numpy(act).cuda())
+        sim.render(rgb=rgb)
+        st, _ = oracle.step(st, dims, act, 0.1)
+    torch.cuda.synchronize()
+    assert np.array_equal(sim.get_state().cpu().numpy().view(np.uint32), st.view(np.uint32))
+    hs = _host_scene_state(w.scenes, st)
+    picks = [(int(rng.integers(64)), int(rng.integers(32)), 0) for _ in range(12)] + [(63, 31, 0), (0, 0, 0)]
+    _compare_views(hs, w.camera, pal, rgb.cpu().numpy(), None, None, picks)
+
+
+def test_uneven_full_size_graph_sampled():
+    """256 uneven scenes, 3 cameras, 128x128: step + render replayed as a
+    hipGraph (the bench's batched form); sampled views vs the oracle, and the
+    graph result equals the eager per-scene result."""
+    w = g.workload("uneven")
+    pal = g.default_palette()
+    sim = _sim(w.scenes, w.camera, pal)
+    sim2 = _sim(w.scenes, w.camera, pal, sched=0)
+    rgb = sim.new_rgb()
+    rgb2 = sim2.new_rgb()
+    act_d = torch.empty((sim.n_agents, 2), dtype=torch.float32, device="cuda")
+    st = np.concatenate([s.agent_state for s in w.scenes])
+    dims = np.concatenate([s.agent_dims for s in w.scenes])
+    for step in range(2):
+        act = g.batch_actions(w.seed, step, w.scenes)
+        act_d.copy_(torch.from_numpy(act))
+        sim.step_render_graph(act_d, rgb)
+        sim2.step(act_d)
+        sim2.render(rgb=rgb2)
+        torch.cuda.synchronize()
+        assert torch.equal(rgb, rgb2), f"graph vs plain at step {step}"
+        st, _ = oracle.step(st, dims, act, 0.1)
+    hs = _host_scene_state(w.scenes, st)
+    rng = np.random.default_rng(9)
+    picks = []
+    for _ in range(10):
+        si = int(rng.integers(256))
+        picks.append((si, int(rng.integers(w.scenes[si].n_agents)), int(rng.integers(3))))
+    _compare_views(hs, w.camera, pal, rgb.cpu().numpy(), None, None, picks)
+
+
+def test_state_save_restore_reproduces_images():
+    w = g.workload("uniform", n_scenes=3)
+    pal = g.default_palette()
+    a = _sim(w.scenes, w.camera, pal)
+    acts = [torch.from_numpy(g.batch_actions(w.seed, k, w.scenes)).cuda() for k in range(10)]
+    for k in range(5):
+        a.step(acts[k])
+    saved = a.get_state().clone()
+    for k in range(5, 10):
+        a.step(acts[k])
+    ra, _, _ = a.render()
+    b = _sim(w.scenes, w.camera, pal)
+    b.set_state(saved)
+    for k in range(5, 10):
+        b.step(acts[k])
+    rb, _, _ = b.render()
+    torch.cuda.synchronize()
+    assert torch.equal(ra, rb)
+    assert torch.equal(a.get_state(), b.get_state())
+
+
+def test_bad_arguments_rejected():
+    from paper_2606_19641_amd import gp
+    w = g.workload("small")
+    sim = _sim(w.scenes, w.camera, g.default_palette())
+    with pytest.raises(gp.GpError):
+        sim.set_launch(band_rows=12)
+    with pytest.raises(gp.GpError):
+        sim.set_launch(batch_tris=100)
+    with pytest.raises(ValueError):
+        sim.step(torch.zeros((3, 2), device="cuda"))
+    bad = g.Camera(width=0, height=64, focal_px=32.0)
+    with pytest.raises(gp.GpError):
+        gp.Sim(w.scenes, bad, g.default_palette())
