@@ -9,17 +9,29 @@
 namespace gp {
 
 constexpr int kMaxCams = 4;
+constexpr int kBinQuads = 64;            // road strips per culling bin
+constexpr int kMaxPrims = 1 << 23;       // primitives per scene (key packs 23 bits)
 
-// Per-scene record: first agent, agent count, first road, road count, first view.
+// Per-scene record.
 struct SceneRec {
-    int32_t agent_base, n_agents, road_base, n_roads;
-    int32_t view_base, pad0, pad1, pad2;
+    int32_t agent_base, n_agents;   // agents [agent_base, agent_base + n_agents)
+    int32_t road_base, n_roads;     // road slots [road_base, road_base + n_roads)
+    int32_t view_base;              // first view of the scene
+    int32_t bin_base, n_bins;       // culling bins [bin_base, bin_base + n_bins)
+    int32_t pad;
 };
 
 // One view: scene index and (ego agent local index, camera index).
 struct ViewRec {
     int32_t scene;
     int32_t ego_cam;   // ego * 4 + cam
+};
+
+// Road culling bin: bounding box of up to kBinQuads consecutive road slots.
+struct RoadBin {
+    float xmin, ymin, xmax, ymax;
+    int32_t start, count;           // slot range, relative to the scene's road_base
+    int32_t pad0, pad1;
 };
 
 // Everything a kernel needs, passed by value.
@@ -30,13 +42,18 @@ struct DevSim {
     float2 *cs;               // [A] cos psi, sin psi
     const float4 *dims;       // [A] L, W, H, 0
     const uint8_t *agent_color;
-    const float4 *roads;      // [R][2] corners (x0 y0 x1 y1) (x2 y2 x3 y3)
-    const uint8_t *road_color;
+    const float4 *roads;      // [R][2] corners of road slot r: (x0 y0 x1 y1) (x2 y2 x3 y3)
+    const int32_t *road_index;// [R] index of road slot r in its scene's input order
+    const uint8_t *road_color;// [R] colour of road slot r
+    const RoadBin *bins;
     const uint8_t *palette;   // [256*3]
     const int32_t *queue;     // [V] view order for the persistent schedule
-    uint32_t *counter;        // work-queue head
+    uint32_t *counter;        // [2] work-queue head, finished workgroups (zero between launches)
     int32_t n_scenes, n_agents, n_views;
     int32_t width, height, n_cams;
+    int32_t road_color_uniform;   // 1 if every road strip has the colour road_color0
+    int32_t road_color0;
+    float road_zmax;          // no pixel sample sees the road plane beyond this depth
     float cam_dir[kMaxCams][2];
     float focal, cam_height, z_near, z_far, dt;
 };
@@ -57,9 +74,9 @@ struct LaunchCfg {
 hipError_t launch_step(const DevSim &s, const float *actions, int agent_begin, int agent_count,
                        hipStream_t st);
 hipError_t launch_cs(const DevSim &s, hipStream_t st);
-hipError_t launch_reset_counter(const DevSim &s, hipStream_t st);
-hipError_t launch_render(const DevSim &s, const RenderOut &o, const LaunchCfg &c, int persistent,
-                         int view_begin, int grid, hipStream_t st);
-size_t render_lds_bytes(const DevSim &s, const LaunchCfg &c);
+// fast = 1: rgb-only kernel for a uniform road colour; fast = 0: general kernel
+hipError_t launch_render(const DevSim &s, const RenderOut &o, const LaunchCfg &c, int fast,
+                         int persistent, int view_begin, int grid, hipStream_t st);
+size_t render_lds_bytes(const DevSim &s, const LaunchCfg &c, int fast);
 
 }  // namespace gp

@@ -1,33 +1,40 @@
 // HIP kernels of the Gigapixel hot path for gfx950 (MI355X).
 //
-//   k_step    kinematic bicycle step, one thread per agent
-//             (App. A, "Action Space and Dynamics"; dt from App. B)
-//   k_cs      heading cosines of the current state (used after create/set_state)
-//   k_render  per-agent ego-centric raster of cuboids and road strips
-//             (Sec. 3.1 O_pixel; App. A "High-Throughput Batched Rendering")
+//   k_step         kinematic bicycle step, one thread per agent
+//                  (App. A, "Action Space and Dynamics"; dt from App. B)
+//   k_cs           heading cosines of the current state (after create / set_state)
+//   k_render<0>    general ego-centric raster: rgb + optional depth and
+//                  primitive id, any road colours
+//   k_render<1>    rgb-only raster for scenes whose road strips share one colour
+//                  (Sec. 3.1 O_pixel; App. A "High-Throughput Batched Rendering")
 //
-// Numerics: every float operation below is written out explicitly (fmaf for
-// fused operations) and the file is compiled with -ffp-contract=off,
-// correctly rounded division and IEEE denormals, so that each result is a
-// deterministic function of the inputs.  Coverage is exact integer work.
+// Numerics: every float operation is written out (fmaf for fused operations)
+// and the file is compiled with -ffp-contract=off, correctly rounded division
+// and IEEE denormals, so each result is a deterministic function of the
+// inputs.  Coverage is exact: edge functions are evaluated in fp64 where every
+// intermediate is an integer below 2^53, and in int64 otherwise.
 //
-// Render design (one workgroup per view):
-//   1. cull + setup: every box face and road strip of the scene is moved to
-//      camera space and tested against the view frustum; survivors that need
-//      no clipping are projected and snapped at once, the rest go to a small
-//      LDS queue that is clipped in a dense second pass.  Triangles whose
-//      bounding box holds at least one pixel sample are appended to an LDS
-//      triangle list with wave ballot + prefix-count compaction.
-//   2. raster: the image is walked in bands of rows; each band has a 64-bit
-//      depth/winner key per pixel in LDS.  Each wave takes triangles from
-//      the list and its lanes sweep the triangle's sample box, testing the
-//      three edge functions exactly and folding covered fragments into the
-//      key buffer with LDS atomic max.
-//   3. resolve: keys become palette colours (and optional depth / primitive
-//      id) and are stored with packed dword writes.
-//   If a view produces more triangles than the LDS list holds, the view is
-//   redone band by band, flushing the list into the band's key buffer
-//   whenever it fills (same result: the per-pixel key is a maximum).
+// Render design, one workgroup per view (persistent work queue or one launch
+// per scene):
+//   cull    boxes are tested against the view frustum by their bounding
+//           cylinder, road strips by the bounding box of their culling bin
+//           (<= 64 spatially sorted strips); survivors are compacted with
+//           wave ballots into LDS.
+//   setup   the faces / strips of the survivors go to camera space, are
+//           rejected against the frustum, and those that need no clipping are
+//           projected and snapped at once; the rest are clipped in a dense
+//           second pass.  Triangles whose bounding box holds a pixel sample
+//           are appended to LDS lists (ballot + popcount compaction).
+//   raster  per (triangle, pixel row) the exact span of covered samples is
+//           computed from the three edge functions.  Road spans of the rgb
+//           kernel are OR-ed into a per-row coverage bitmask: all strips lie in
+//           one plane, so their depth at a pixel does not depend on the strip,
+//           and with one road colour only coverage matters.  Box spans (and
+//           every span of the general kernel) give fragments whose 64-bit key
+//           (1/z, agent-above-road, lower primitive index, colour) is folded
+//           into a band of LDS with atomic max.
+//   resolve keys and road coverage become palette colours, stored with packed
+//           dword writes (optional depth / primitive id in the general kernel).
 
 #include "gp_device.h"
 
@@ -98,29 +105,20 @@ __global__ void k_cs(DevSim s)
     s.cs[i] = make_float2(cp, sp);
 }
 
-__global__ void k_reset_counter(uint32_t *c) { *c = 0u; }
-
-// ------------------------------------------------------------ render
+// ------------------------------------------------------------ geometry
 
 struct V3 { float x, y, z; };
+struct Plane { float A, B, C; };
 
 // per-view camera constants
 struct Cam {
     float px, py, fx, fy, h;
     float f, cx, cy, F256, CX256, CY256, G, zn, zf;
     float t_left, t_right, t_top, t_bottom;   // frustum slopes for culling
+    Plane road;                               // depth plane shared by every road strip
+    float road_zmax;                          // farthest road depth a sample row can see
     int W, H;
 };
-
-// triangle in the LDS list: vertices in 1/256 px with positive orientation,
-// depth plane, key low word, pixel-sample bounding box (inclusive)
-struct TriRec {
-    int32_t X0, Y0, X1, Y1, X2, Y2;
-    float A, B, C;
-    uint32_t keylo;
-    int16_t i0, i1, j0, j1;
-};
-static_assert(sizeof(TriRec) == 48, "TriRec layout");
 
 __device__ __forceinline__ V3 to_cam(const Cam &c, float dx, float dy, float Z)
 {
@@ -140,7 +138,60 @@ __device__ __forceinline__ V3 dir_to_cam(const Cam &c, float nx, float ny, float
     return n;
 }
 
-// A candidate polygon: 4 camera-space corners, the face normal and the key.
+__device__ __forceinline__ float plane_d(const V3 &n, const V3 &p0)
+{
+    return fmaf(n.x, p0.x, fmaf(n.y, p0.y, n.z * p0.z));
+}
+
+// 1/z = A du + B dv + C at pixel offsets du, dv from the principal point
+__device__ __forceinline__ Plane face_plane(const Cam &c, const V3 &n, float d)
+{
+    const float fd = c.f * d;
+    Plane pl;
+    pl.A = n.x / fd;
+    pl.B = -n.y / fd;
+    pl.C = n.z / d;
+    return pl;
+}
+
+__device__ __forceinline__ Cam make_cam(const DevSim &s, const SceneRec &sc, int ego, int k)
+{
+    Cam c;
+    const int ga = sc.agent_base + ego;
+    const float4 st = s.state[ga];
+    const float2 cs = s.cs[ga];
+    const float ce = cs.x, se = cs.y;
+    const float ck = s.cam_dir[k][0], sk = s.cam_dir[k][1];
+    c.px = st.x;
+    c.py = st.y;
+    c.fx = fmaf(ce, ck, -(se * sk));
+    c.fy = fmaf(se, ck, ce * sk);
+    c.h = s.cam_height;
+    c.W = s.width;
+    c.H = s.height;
+    c.f = s.focal;
+    c.cx = 0.5f * (float)s.width;
+    c.cy = 0.5f * (float)s.height;
+    c.F256 = 256.0f * c.f;
+    c.CX256 = 256.0f * c.cx;
+    c.CY256 = 256.0f * c.cy;
+    c.G = 268435456.0f / c.F256;
+    c.zn = s.z_near;
+    c.zf = s.z_far;
+    c.t_right = ((float)s.width - c.cx) / c.f;
+    c.t_left = c.cx / c.f;
+    c.t_top = c.cy / c.f;
+    c.t_bottom = ((float)s.height - c.cy) / c.f;
+    c.road_zmax = s.road_zmax;
+    // every road corner has camera y = -h, so d = n.p0 = -h for every strip
+    const V3 n = dir_to_cam(c, 0.0f, 0.0f, 1.0f);
+    V3 p0;
+    p0.x = 0.0f; p0.y = 0.0f - c.h; p0.z = 0.0f;
+    c.road = face_plane(c, n, plane_d(n, p0));
+    return c;
+}
+
+// A candidate polygon: 4 camera-space corners, its normal and its key word.
 struct Poly {
     V3 v[4];
     V3 n;
@@ -148,70 +199,77 @@ struct Poly {
     bool one_sided;
 };
 
-// Build candidate c of the scene: c < 6*n_a is face (c % 6) of agent c / 6,
-// otherwise road strip c - 6*n_a.  Returns false for the ego's own faces.
-__device__ __forceinline__ bool build_poly(const DevSim &s, const SceneRec &sc, const Cam &cam,
-                                           int ego, int c, Poly &P)
+// key low word: agent-above-road bit, inverted primitive index (23 bits), colour
+__device__ __forceinline__ uint32_t key_low(uint32_t cls, int prim, uint32_t color)
 {
-    const int nbox = 6 * sc.n_agents;
-    if (c < nbox) {
-        const int j = c / 6, f = c - 6 * j;
-        if (j == ego) return false;
-        const int ga = sc.agent_base + j;
-        const float4 st = s.state[ga];
-        const float2 csj = s.cs[ga];
-        const float4 dm = s.dims[ga];
-        const float cj = csj.x, sj = csj.y;
-        const float ox = st.x - cam.px, oy = st.y - cam.py;
-        const float hl = 0.5f * dm.x, hw = 0.5f * dm.y, Hb = dm.z;
-        const float ax = hl * cj, ay = hl * sj;
-        const float bx = -(hw * sj), by = hw * cj;
-        // footprint corners, counter-clockwise from above:
-        // 0 front-right, 1 front-left, 2 back-left, 3 back-right
-        float cx4[4], cy4[4];
-        cx4[0] = (ox + ax) - bx; cy4[0] = (oy + ay) - by;
-        cx4[1] = (ox + ax) + bx; cy4[1] = (oy + ay) + by;
-        cx4[2] = (ox - ax) + bx; cy4[2] = (oy - ay) + by;
-        cx4[3] = (ox - ax) - bx; cy4[3] = (oy - ay) - by;
-        float nx, ny, nz;
-        if (f < 4) {
-            const int a = f, b = (f + 1) & 3;
-            P.v[0] = to_cam(cam, cx4[a], cy4[a], 0.0f);
-            P.v[1] = to_cam(cam, cx4[b], cy4[b], 0.0f);
-            P.v[2] = to_cam(cam, cx4[b], cy4[b], Hb);
-            P.v[3] = to_cam(cam, cx4[a], cy4[a], Hb);
-            nx = (f == 0) ? cj : (f == 1) ? -sj : (f == 2) ? -cj : sj;
-            ny = (f == 0) ? sj : (f == 1) ? cj : (f == 2) ? -sj : -cj;
-            nz = 0.0f;
-        } else if (f == 4) {
-            for (int k = 0; k < 4; ++k) P.v[k] = to_cam(cam, cx4[k], cy4[k], Hb);
-            nx = 0.0f; ny = 0.0f; nz = 1.0f;
-        } else {
-            for (int k = 0; k < 4; ++k) P.v[k] = to_cam(cam, cx4[3 - k], cy4[3 - k], 0.0f);
-            nx = 0.0f; ny = 0.0f; nz = -1.0f;
-        }
-        P.n = dir_to_cam(cam, nx, ny, nz);
-        P.keylo = (1u << 31) | (0x7FFFFFFFu - (uint32_t)c);
-        P.one_sided = true;
-    } else {
-        const int r = c - nbox;
-        const float4 q0 = s.roads[2 * (sc.road_base + r)];
-        const float4 q1 = s.roads[2 * (sc.road_base + r) + 1];
-        P.v[0] = to_cam(cam, q0.x - cam.px, q0.y - cam.py, 0.0f);
-        P.v[1] = to_cam(cam, q0.z - cam.px, q0.w - cam.py, 0.0f);
-        P.v[2] = to_cam(cam, q1.x - cam.px, q1.y - cam.py, 0.0f);
-        P.v[3] = to_cam(cam, q1.z - cam.px, q1.w - cam.py, 0.0f);
-        P.n = dir_to_cam(cam, 0.0f, 0.0f, 1.0f);
-        P.keylo = 0x7FFFFFFFu - (uint32_t)c;
-        P.one_sided = false;
-    }
-    return true;
+    return (cls << 31) | ((uint32_t)(kMaxPrims - 1 - prim) << 8) | color;
 }
 
-// Conservative frustum rejection: true if the polygon certainly covers no
-// pixel sample.  Near and far use the clipper's own predicates; the four side
-// planes use the tile slopes with a relative margin, valid for every point of
-// the polygon's convex hull, so clipping cannot bring a vertex back inside.
+// face f (0 front, 1 left, 2 back, 3 right, 4 top, 5 bottom) of agent j
+__device__ __forceinline__ void build_face(const DevSim &s, const SceneRec &sc, const Cam &cam, int j,
+                                           int f, Poly &P)
+{
+    const int ga = sc.agent_base + j;
+    const float4 st = s.state[ga];
+    const float2 csj = s.cs[ga];
+    const float4 dm = s.dims[ga];
+    const float cj = csj.x, sj = csj.y;
+    const float ox = st.x - cam.px, oy = st.y - cam.py;
+    const float hl = 0.5f * dm.x, hw = 0.5f * dm.y, Hb = dm.z;
+    const float ax = hl * cj, ay = hl * sj;
+    const float bx = -(hw * sj), by = hw * cj;
+    // footprint corners, counter-clockwise from above:
+    // 0 front-right, 1 front-left, 2 back-left, 3 back-right
+    float cx4[4], cy4[4];
+    cx4[0] = (ox + ax) - bx; cy4[0] = (oy + ay) - by;
+    cx4[1] = (ox + ax) + bx; cy4[1] = (oy + ay) + by;
+    cx4[2] = (ox - ax) + bx; cy4[2] = (oy - ay) + by;
+    cx4[3] = (ox - ax) - bx; cy4[3] = (oy - ay) - by;
+    float nx, ny, nz;
+    if (f < 4) {
+        const int a = f, b = (f + 1) & 3;
+        P.v[0] = to_cam(cam, cx4[a], cy4[a], 0.0f);
+        P.v[1] = to_cam(cam, cx4[b], cy4[b], 0.0f);
+        P.v[2] = to_cam(cam, cx4[b], cy4[b], Hb);
+        P.v[3] = to_cam(cam, cx4[a], cy4[a], Hb);
+        nx = (f == 0) ? cj : (f == 1) ? -sj : (f == 2) ? -cj : sj;
+        ny = (f == 0) ? sj : (f == 1) ? cj : (f == 2) ? -sj : -cj;
+        nz = 0.0f;
+    } else if (f == 4) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) P.v[k] = to_cam(cam, cx4[k], cy4[k], Hb);
+        nx = 0.0f; ny = 0.0f; nz = 1.0f;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) P.v[k] = to_cam(cam, cx4[3 - k], cy4[3 - k], 0.0f);
+        nx = 0.0f; ny = 0.0f; nz = -1.0f;
+    }
+    P.n = dir_to_cam(cam, nx, ny, nz);
+    P.keylo = key_low(1u, 6 * j + f, s.agent_color[ga]);
+    P.one_sided = true;
+}
+
+// road slot `slot` (relative to the scene's road_base)
+__device__ __forceinline__ void build_road(const DevSim &s, const SceneRec &sc, const Cam &cam, int slot,
+                                           Poly &P)
+{
+    const int g = sc.road_base + slot;
+    const float4 q0 = s.roads[2 * g];
+    const float4 q1 = s.roads[2 * g + 1];
+    P.v[0] = to_cam(cam, q0.x - cam.px, q0.y - cam.py, 0.0f);
+    P.v[1] = to_cam(cam, q0.z - cam.px, q0.w - cam.py, 0.0f);
+    P.v[2] = to_cam(cam, q1.x - cam.px, q1.y - cam.py, 0.0f);
+    P.v[3] = to_cam(cam, q1.z - cam.px, q1.w - cam.py, 0.0f);
+    P.n = dir_to_cam(cam, 0.0f, 0.0f, 1.0f);
+    P.keylo = key_low(0u, 6 * sc.n_agents + s.road_index[g], s.road_color[g]);
+    P.one_sided = false;
+}
+
+// Conservative frustum rejection of a convex set given by 4 points: true if
+// it certainly covers no pixel sample.  Near and far use the clipper's own
+// predicates; the side planes use a relative margin that dominates rounding,
+// and hold for every point of the convex hull, so clipping cannot bring a
+// point back inside.
 __device__ __forceinline__ bool outside(const Cam &c, const V3 *v)
 {
     bool n = true, fa = true, l = true, r = true, t = true, b = true;
@@ -228,6 +286,48 @@ __device__ __forceinline__ bool outside(const Cam &c, const V3 *v)
         b = b && (fmaf(-c.t_bottom, v[k].z, -v[k].y) > my);
     }
     return n || fa || l || r || t || b;
+}
+
+// Whole-box rejection by the box's bounding cylinder (radius hl + hw >= half
+// diagonal, height H) with the same margins as outside().
+__device__ __forceinline__ bool box_outside(const DevSim &s, const SceneRec &sc, const Cam &c, int j)
+{
+    const int ga = sc.agent_base + j;
+    const float4 st = s.state[ga];
+    const float4 dm = s.dims[ga];
+    const float ox = st.x - c.px, oy = st.y - c.py;
+    const float r = 0.5f * (dm.x + dm.y);
+    const float z = fmaf(ox, c.fx, oy * c.fy);
+    const float x = fmaf(ox, c.fy, -(oy * c.fx));
+    const float m = 1e-3f * (fabsf(x) + fabsf(z) + r + dm.z + c.h) + 1e-4f;
+    const float zmax = z + r, zmin = z - r;
+    if (zmax < c.zn - m) return true;
+    if (zmin > c.zf + m) return true;
+    if (x - c.t_right * z - r * (1.0f + c.t_right) > m) return true;
+    if (-x - c.t_left * z - r * (1.0f + c.t_left) > m) return true;
+    if (-(dm.z - c.h) - c.t_bottom * zmax > m) return true;
+    if (-c.h - c.t_top * zmax > m) return true;
+    return false;
+}
+
+// Road geometry lies at camera height -h, so a road point at depth z projects
+// to image row v = cy + h f / z.  The host computes road_zmax, 2% beyond the
+// largest depth that a sample row at or before the far plane looks at; a set
+// whose points are all farther projects strictly between two sample rows (or
+// above the horizon) and covers no sample.
+__device__ __forceinline__ bool road_beyond(const Cam &c, const V3 *v)
+{
+    return v[0].z > c.road_zmax && v[1].z > c.road_zmax && v[2].z > c.road_zmax && v[3].z > c.road_zmax;
+}
+
+__device__ __forceinline__ bool bin_outside(const DevSim &s, const Cam &c, const RoadBin &b)
+{
+    V3 v[4];
+    v[0] = to_cam(c, b.xmin - c.px, b.ymin - c.py, 0.0f);
+    v[1] = to_cam(c, b.xmax - c.px, b.ymin - c.py, 0.0f);
+    v[2] = to_cam(c, b.xmax - c.px, b.ymax - c.py, 0.0f);
+    v[3] = to_cam(c, b.xmin - c.px, b.ymax - c.py, 0.0f);
+    return outside(c, v) || road_beyond(c, v);
 }
 
 // clip plane signed distance; >= 0 is inside
@@ -261,23 +361,31 @@ __device__ __forceinline__ void snap(const Cam &c, const V3 &p, int32_t &X, int3
     Y = (int32_t)rintf(fmaf(w, c.F256, c.CY256));
 }
 
-struct Plane { float A, B, C; };
+// ------------------------------------------------------------ triangle lists
 
-__device__ __forceinline__ Plane face_plane(const Cam &c, const V3 &n, float d)
-{
-    const float fd = c.f * d;
-    Plane pl;
-    pl.A = n.x / fd;
-    pl.B = -n.y / fd;
-    pl.C = n.z / d;
-    return pl;
-}
+// A snapped triangle with positive orientation, its sample rows [j0, j1] and
+// whether its coordinates need the int64 span path (|coord| >= 2^25).
+struct TriGeo {
+    int32_t X0, Y0, X1, Y1, X2, Y2;
+    int16_t j0, j1;
+    int16_t huge, pad;
+};
+static_assert(sizeof(TriGeo) == 32, "TriGeo layout");
+
+// A triangle with its depth plane and key word (boxes; every primitive in
+// the general kernel).
+struct TriRec {
+    TriGeo g;
+    float A, B, C;
+    uint32_t keylo;
+};
+static_assert(sizeof(TriRec) == 48, "TriRec layout");
 
 // Orient and bound one fan triangle.  Returns false if it is culled or its
 // bounding box holds no sample within rows [r0, r1).
 __device__ __forceinline__ bool make_tri(const Cam &c, bool one_sided, int32_t X0, int32_t Y0,
                                          int32_t X1, int32_t Y1, int32_t X2, int32_t Y2, int r0,
-                                         int r1, TriRec &t)
+                                         int r1, TriGeo &t)
 {
     const int64_t area2 = (int64_t)(X1 - X0) * (int64_t)(Y2 - Y0) - (int64_t)(X2 - X0) * (int64_t)(Y1 - Y0);
     if (one_sided) {
@@ -291,101 +399,306 @@ __device__ __forceinline__ bool make_tri(const Cam &c, bool one_sided, int32_t X
     }
     const int32_t xmin = min(X0, min(X1, X2)), xmax = max(X0, max(X1, X2));
     const int32_t ymin = min(Y0, min(Y1, Y2)), ymax = max(Y0, max(Y1, Y2));
-    int i0 = (xmin - 128 + 255) >> 8, i1 = (xmax - 128) >> 8;
-    int j0 = (ymin - 128 + 255) >> 8, j1 = (ymax - 128) >> 8;
-    i0 = max(i0, 0); i1 = min(i1, c.W - 1);
-    j0 = max(j0, r0); j1 = min(j1, r1 - 1);
+    const int i0 = max((xmin - 128 + 255) >> 8, 0), i1 = min((xmax - 128) >> 8, c.W - 1);
+    const int j0 = max((ymin - 128 + 255) >> 8, r0), j1 = min((ymax - 128) >> 8, r1 - 1);
     if (i0 > i1 || j0 > j1) return false;
     t.X0 = X0; t.Y0 = Y0; t.X1 = X1; t.Y1 = Y1; t.X2 = X2; t.Y2 = Y2;
-    t.i0 = (int16_t)i0; t.i1 = (int16_t)i1; t.j0 = (int16_t)j0; t.j1 = (int16_t)j1;
+    t.j0 = (int16_t)j0;
+    t.j1 = (int16_t)j1;
+    const int32_t lim = 1 << 25;
+    t.huge = (int16_t)(xmin <= -lim || xmax >= lim || ymin <= -lim || ymax >= lim);
+    t.pad = 0;
     return true;
 }
 
+// ------------------------------------------------------------ exact row spans
+
+__device__ __forceinline__ int64_t floor_div64(int64_t a, int64_t b)   // b > 0
+{
+    int64_t q = a / b;
+    if ((a % b != 0) && (a < 0)) --q;
+    return q;
+}
+
+// Samples i of row j covered by the triangle: [xl, xr] clipped to [0, W).
+// Edge k runs from vertex k to k+1; E_k(i) = P_k - 256 dY_k i with
+// P_k = dX_k (Sy - Y_k) + dY_k (X_k - 128); a sample is inside iff every
+// E_k >= t_k, t_k = 0 on top (dY == 0, dX > 0) and left (dY < 0) edges, else 1.
+__device__ bool row_span(const TriGeo &t, int j, int W, int &xl_out, int &xr_out)
+{
+    const int32_t X[3] = {t.X0, t.X1, t.X2}, Y[3] = {t.Y0, t.Y1, t.Y2};
+    int xl = 0, xr = W - 1;
+    if (!t.huge) {
+        // every term is an integer below 2^53: fp64 is exact here
+        const double Sy = 256.0 * (double)j + 128.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int k1 = (k == 2) ? 0 : k + 1;
+            const int32_t dX = X[k1] - X[k], dY = Y[k1] - Y[k];
+            const double tk = (dY < 0 || (dY == 0 && dX > 0)) ? 0.0 : 1.0;
+            const double P = fma((double)dX, Sy - (double)Y[k], (double)dY * ((double)X[k] - 128.0));
+            if (dY == 0) {
+                if (P < tk) return false;
+                continue;
+            }
+            const double D = 256.0 * (double)dY;
+            const double q = (P - tk) / D;
+            if (dY > 0) {            // E decreases with i: i <= q
+                double ic = fmin(fmax(floor(q), -1.0), (double)W);
+                if (P - D * ic < tk) ic -= 1.0;
+                else if (P - D * (ic + 1.0) >= tk) ic += 1.0;
+                xr = min(xr, (int)ic);
+            } else {                 // E increases with i: i >= q
+                double ic = fmin(fmax(ceil(q), -1.0), (double)W);
+                if (P - D * ic < tk) ic += 1.0;
+                else if (P - D * (ic - 1.0) >= tk) ic -= 1.0;
+                xl = max(xl, (int)ic);
+            }
+        }
+    } else {
+        const int64_t Sy = 256 * (int64_t)j + 128;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int k1 = (k == 2) ? 0 : k + 1;
+            const int64_t dX = (int64_t)X[k1] - X[k], dY = (int64_t)Y[k1] - Y[k];
+            const int64_t tk = (dY < 0 || (dY == 0 && dX > 0)) ? 0 : 1;
+            const int64_t P = dX * (Sy - Y[k]) + dY * ((int64_t)X[k] - 128);
+            if (dY == 0) {
+                if (P < tk) return false;
+                continue;
+            }
+            if (dY > 0) {
+                const int64_t ic = floor_div64(P - tk, 256 * dY);
+                xr = (int)min((int64_t)xr, max(ic, (int64_t)-1));
+            } else {
+                // i >= (tk - P) / (256 |dY|), rounded up: ceil(-x) = -floor(x)
+                const int64_t ic = -floor_div64(P - tk, 256 * (-dY));
+                xl = (int)max((int64_t)xl, min(ic, (int64_t)W));
+            }
+        }
+    }
+    xl_out = xl;
+    xr_out = xr;
+    return xl <= xr;
+}
+
+// ------------------------------------------------------------ LDS context
+
+// LDS counters: list lengths, overflow flag, clip-queue and survivor counts,
+// pending triangles of the current round (two parities, roads / others), and
+// the row range touched by box triangles (rgb kernel)
+enum { C_TRIS = 0, C_RTRIS, C_OVF, C_CLIPQ, C_SURV, C_PR0, C_PR1, C_PT0, C_PT1, C_BMIN, C_BMAX, C_NCNT = 16 };
+
 struct Lds {
-    TriRec *tris;
-    unsigned long long *zbuf;
-    uint8_t *palette;
-    int32_t *clipq;
-    int32_t *cnt;      // [0] list count, [1] overflow flag, [2] clip-queue count
+    TriRec *tris;            // boxes (rgb kernel) or everything (general kernel)
+    TriGeo *rtris;           // road strips (rgb kernel)
+    unsigned long long *zb;  // band of 64-bit keys
+    unsigned long long *road;// rgb kernel: per-row road coverage bits [H][nw]
+    int32_t *scan;           // [cap + 1] row-count prefix
+    int32_t *surv;           // [B] surviving boxes / bins
+    int32_t *clipq;          // [B] candidates that need clipping
+    int32_t *cnt;            // counters (C_*)
+    int32_t *wsum;           // [16] per-wave partial sums
+    uint32_t *pal;           // [256] RGB as u32
     int cap;
+    int nw;                  // 64-bit words per image row
 };
 
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
 
-// Append up to two triangles per lane with one LDS atomic per wave.
-__device__ __forceinline__ void append2(Lds &L, bool v0, const TriRec &t0, bool v1, const TriRec &t1)
+// Block-wide exclusive scan of L.scan[0..n) in place; L.scan[n] = total.
+// Every thread must call it.
+__device__ int block_scan(Lds &L, int n)
+{
+    const int B = blockDim.x, tid = threadIdx.x;
+    const int per = (n + B - 1) / B;
+    const int beg = min(n, tid * per), end = min(n, beg + per);
+    int local = 0;
+    for (int i = beg; i < end; ++i) local += L.scan[i];
+    // inclusive scan of `local` across the wave
+    int v = local;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(v, o);
+        if ((int)lane_id() >= o) v += u;
+    }
+    const int w = tid >> 6;
+    if ((int)lane_id() == 63) L.wsum[w] = v;
+    __syncthreads();
+    int wbase = 0;
+    for (int k = 0; k < w; ++k) wbase += L.wsum[k];
+    int run = wbase + v - local;
+    for (int i = beg; i < end; ++i) {
+        const int c = L.scan[i];
+        L.scan[i] = run;
+        run += c;
+    }
+    if (tid == B - 1) L.scan[n] = run;
+    __syncthreads();
+    return L.scan[n];
+}
+
+// index t with scan[t] <= g < scan[t+1]
+__device__ __forceinline__ int find_row_owner(const Lds &L, int n, int g)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (L.scan[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Road strips of the rgb kernel: OR every covered sample into the row bitmask.
+__device__ void raster_roads(const Cam &cam, Lds &L, int n)
+{
+    if (n <= 0) return;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) L.scan[t] = L.rtris[t].j1 - L.rtris[t].j0 + 1;
+    __syncthreads();
+    const int total = block_scan(L, n);
+    for (int gi = threadIdx.x; gi < total; gi += blockDim.x) {
+        const int t = find_row_owner(L, n, gi);
+        const TriGeo tg = L.rtris[t];
+        const int j = tg.j0 + (gi - L.scan[t]);
+        int xl, xr;
+        if (!row_span(tg, j, cam.W, xl, xr)) continue;
+        unsigned long long *row = L.road + (size_t)j * L.nw;
+        const int w0 = xl >> 6, w1 = xr >> 6;
+        for (int wd = w0; wd <= w1; ++wd) {
+            const int lo = (wd == w0) ? (xl & 63) : 0;
+            const int hi = (wd == w1) ? (xr & 63) : 63;
+            const unsigned long long m = (hi == 63 ? ~0ull : ((1ull << (hi + 1)) - 1ull)) & (~0ull << lo);
+            atomicOr(&row[wd], m);
+        }
+    }
+    __syncthreads();
+}
+
+// Fragments of listed triangles in rows [b0, b1) folded into the key band.
+__device__ void raster_tris(const Cam &cam, Lds &L, int n, int b0, int b1)
+{
+    if (n <= 0) return;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        const int j0 = max((int)L.tris[t].g.j0, b0), j1 = min((int)L.tris[t].g.j1, b1 - 1);
+        L.scan[t] = max(0, j1 - j0 + 1);
+    }
+    __syncthreads();
+    const int total = block_scan(L, n);
+    for (int gi = threadIdx.x; gi < total; gi += blockDim.x) {
+        const int t = find_row_owner(L, n, gi);
+        const TriRec tr = L.tris[t];
+        const int j = max((int)tr.g.j0, b0) + (gi - L.scan[t]);
+        int xl, xr;
+        if (!row_span(tr.g, j, cam.W, xl, xr)) continue;
+        const float dv = ((float)j + 0.5f) - cam.cy;
+        unsigned long long *row = L.zb + (size_t)(j - b0) * cam.W;
+        for (int i = xl; i <= xr; ++i) {
+            const float du = ((float)i + 0.5f) - cam.cx;
+            const float invz = fmaf(tr.A, du, fmaf(tr.B, dv, tr.C));
+            if (!(invz > 0.0f)) continue;
+            atomicMax(&row[i], ((unsigned long long)__float_as_uint(invz) << 32) | tr.keylo);
+        }
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------ setup
+
+// How triangles are consumed during a setup pass.
+struct Sink {
+    int fast;        // rgb kernel: road strips go to the road list
+    int flush_tris;  // L.tris may be flushed into the key band [r0, r1)
+    int r0, r1;      // rows kept; flushes of L.tris go to this band
+};
+
+__device__ __forceinline__ void flush_tris(const Cam &cam, Lds &L, const Sink &K)
+{
+    raster_tris(cam, L, min(L.cnt[C_TRIS], L.cap), K.r0, K.r1);
+    if (threadIdx.x == 0) L.cnt[C_TRIS] = 0;
+    __syncthreads();
+}
+
+__device__ __forceinline__ void flush_roads(const Cam &cam, Lds &L)
+{
+    raster_roads(cam, L, min(L.cnt[C_RTRIS], L.cap));
+    if (threadIdx.x == 0) L.cnt[C_RTRIS] = 0;
+    __syncthreads();
+}
+
+// Make room for `need` more triangles in every list that can be flushed.
+// Uniform: must be called by every thread after a barrier.
+__device__ __forceinline__ void make_room(const Cam &cam, Lds &L, const Sink &K, int need)
+{
+    if (K.fast && L.cnt[C_RTRIS] + need > L.cap) flush_roads(cam, L);
+    if (K.flush_tris && L.cnt[C_TRIS] + need > L.cap) flush_tris(cam, L, K);
+}
+
+// Append with one LDS atomic per wave; lanes whose triangle does not fit
+// raise the overflow flag (only possible for a list that cannot be flushed).
+__device__ __forceinline__ void append_wave(Lds &L, int which, bool v0, const TriRec &t0, bool v1,
+                                            const TriRec &t1)
 {
     const unsigned long long b0 = __ballot(v0), b1 = __ballot(v1);
     const int n0 = __popcll(b0), n = n0 + __popcll(b1);
     if (n == 0) return;
     const unsigned long long lt = (1ull << lane_id()) - 1ull;
-    int base = 0;
     const int leader = __ffsll((long long)(b0 | b1)) - 1;
-    if ((int)lane_id() == leader) base = atomicAdd(&L.cnt[0], n);
+    int base = 0;
+    if ((int)lane_id() == leader) {
+        base = atomicAdd(&L.cnt[which], n);
+        if (base + n > L.cap) L.cnt[C_OVF] = 1;
+    }
     base = __shfl(base, leader);
-    if (base + n > L.cap) {
-        if ((int)lane_id() == leader) L.cnt[1] = 1;
-    }
-    if (v0) {
-        const int pos = base + __popcll(b0 & lt);
-        if (pos < L.cap) L.tris[pos] = t0;
-    }
-    if (v1) {
-        const int pos = base + n0 + __popcll(b1 & lt);
-        if (pos < L.cap) L.tris[pos] = t1;
+    const int p0 = base + __popcll(b0 & lt), p1 = base + n0 + __popcll(b1 & lt);
+    if (which == C_RTRIS) {
+        if (v0 && p0 < L.cap) L.rtris[p0] = t0.g;
+        if (v1 && p1 < L.cap) L.rtris[p1] = t1.g;
+    } else {
+        if (v0 && p0 < L.cap) L.tris[p0] = t0;
+        if (v1 && p1 < L.cap) L.tris[p1] = t1;
     }
 }
 
-__device__ __forceinline__ void append1(Lds &L, const TriRec &t)
+__device__ __forceinline__ void append_one(Lds &L, int which, const TriRec &t)
 {
-    const int pos = atomicAdd(&L.cnt[0], 1);
-    if (pos < L.cap)
-        L.tris[pos] = t;
-    else
-        L.cnt[1] = 1;
+    const int pos = atomicAdd(&L.cnt[which], 1);
+    if (pos < L.cap) {
+        if (which == C_RTRIS) L.rtris[pos] = t.g;
+        else L.tris[pos] = t;
+    } else {
+        L.cnt[C_OVF] = 1;
+    }
 }
 
-// Fast path for one candidate: returns true if it must go through the clipper.
-__device__ __forceinline__ bool fast_candidate(const DevSim &s, const SceneRec &sc, const Cam &cam,
-                                               int ego, int c, bool active, int r0, int r1, Lds &L)
+// Fast path for one live candidate polygon: cull, project and orient its two
+// triangles unless it needs the clipper (then `clip` is set).
+__device__ __forceinline__ void fast_poly(const Cam &cam, const Poly &P, const Sink &K, TriRec &t0, bool &v0,
+                                          TriRec &t1, bool &v1, bool &clip)
 {
-    Poly P;
-    bool live = active && build_poly(s, sc, cam, ego, c, P);
-    bool clip = false;
-    TriRec t0, t1;
-    bool v0 = false, v1 = false;
-    if (live) {
-        live = !outside(cam, P.v);
-        if (live) {
-            const V3 &p0 = P.v[0];
-            const float d = fmaf(P.n.x, p0.x, fmaf(P.n.y, p0.y, P.n.z * p0.z));
-            if (P.one_sided && !(d < 0.0f)) live = false;
-            if (live) {
-                clip = needs_clip(cam, P.v);
-                if (!clip) {
-                    int32_t X[4], Y[4];
+    if (outside(cam, P.v)) return;
+    if (!P.one_sided && road_beyond(cam, P.v)) return;
+    const float d = plane_d(P.n, P.v[0]);
+    if (P.one_sided && !(d < 0.0f)) return;
+    clip = needs_clip(cam, P.v);
+    if (clip) return;
+    int32_t X[4], Y[4];
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) snap(cam, P.v[k], X[k], Y[k]);
-                    v0 = make_tri(cam, P.one_sided, X[0], Y[0], X[1], Y[1], X[2], Y[2], r0, r1, t0);
-                    v1 = make_tri(cam, P.one_sided, X[0], Y[0], X[2], Y[2], X[3], Y[3], r0, r1, t1);
-                    if (v0 || v1) {
-                        const Plane pl = face_plane(cam, P.n, d);
-                        t0.A = pl.A; t0.B = pl.B; t0.C = pl.C; t0.keylo = P.keylo;
-                        t1.A = pl.A; t1.B = pl.B; t1.C = pl.C; t1.keylo = P.keylo;
-                    }
-                }
-            }
-        }
+    for (int k = 0; k < 4; ++k) snap(cam, P.v[k], X[k], Y[k]);
+    v0 = make_tri(cam, P.one_sided, X[0], Y[0], X[1], Y[1], X[2], Y[2], K.r0, K.r1, t0.g);
+    v1 = make_tri(cam, P.one_sided, X[0], Y[0], X[2], Y[2], X[3], Y[3], K.r0, K.r1, t1.g);
+    if ((v0 || v1) && !(K.fast && !P.one_sided)) {
+        const Plane pl = face_plane(cam, P.n, d);
+        t0.A = pl.A; t0.B = pl.B; t0.C = pl.C; t0.keylo = P.keylo;
+        t1.A = pl.A; t1.B = pl.B; t1.C = pl.C; t1.keylo = P.keylo;
     }
-    append2(L, v0, t0, v1, t1);
-    return clip;
 }
 
 // Sutherland-Hodgman against one plane.  Walk the vertices; keep an inside
 // vertex; if the edge to the next vertex crosses the plane emit the crossing,
-// computed from the inside end towards the outside end.
-// Returns the output count, or -1 when more than kMaxVerts vertices would
-// result (only a self-intersecting input quad can do that; it is dropped).
+// computed from the inside end towards the outside end.  Returns the output
+// count, or -1 when more than kMaxVerts vertices would result (only a
+// self-intersecting input quad can do that; it is dropped).
 constexpr int kMaxVerts = 12;
 constexpr int kMaxTrisPerCand = kMaxVerts - 2;
 
@@ -419,13 +732,9 @@ __device__ int clip_one(int plane, const Cam &c, const V3 *in, int n, V3 *out)
 }
 
 // Slow path: clip, project and emit the fan of one candidate.
-__device__ __noinline__ void clip_candidate(const DevSim &s, const SceneRec &sc, const Cam &cam,
-                                            int ego, int c, int r0, int r1, Lds &L)
+__device__ __noinline__ void clip_poly(const Cam &cam, const Poly &P, const Sink &K, Lds &L)
 {
-    Poly P;
-    if (!build_poly(s, sc, cam, ego, c, P)) return;
-    const V3 p0 = P.v[0];
-    const float d = fmaf(P.n.x, p0.x, fmaf(P.n.y, p0.y, P.n.z * p0.z));
+    const float d = plane_d(P.n, P.v[0]);
     if (P.one_sided && !(d < 0.0f)) return;
     V3 a[kMaxVerts], b[kMaxVerts];
     int n = 4;
@@ -437,199 +746,232 @@ __device__ __noinline__ void clip_candidate(const DevSim &s, const SceneRec &sc,
     }
     if (n < 3) return;
     const Plane pln = face_plane(cam, P.n, d);
+    const bool road = K.fast && !P.one_sided;
     int32_t X[kMaxVerts], Y[kMaxVerts];
     for (int k = 0; k < n; ++k) snap(cam, a[k], X[k], Y[k]);
     for (int k = 1; k + 1 < n; ++k) {
         TriRec t;
-        if (make_tri(cam, P.one_sided, X[0], Y[0], X[k], Y[k], X[k + 1], Y[k + 1], r0, r1, t)) {
+        if (make_tri(cam, P.one_sided, X[0], Y[0], X[k], Y[k], X[k + 1], Y[k + 1], K.r0, K.r1, t.g)) {
             t.A = pln.A; t.B = pln.B; t.C = pln.C; t.keylo = P.keylo;
-            append1(L, t);
+            append_one(L, road ? C_RTRIS : C_TRIS, t);
+            if (K.fast && !road) {
+                atomicMin(&L.cnt[C_BMIN], (int)t.g.j0);
+                atomicMax(&L.cnt[C_BMAX], (int)t.g.j1);
+            }
         }
     }
 }
 
-__device__ __forceinline__ bool covers(const TriRec &t, int64_t Sx, int64_t Sy)
+// Candidate code for the clip queue: boxes j*8 + f, roads -(slot + 1).
+__device__ __forceinline__ void build_code(const DevSim &s, const SceneRec &sc, const Cam &cam, int code,
+                                           Poly &P)
 {
-    const int32_t X[3] = {t.X0, t.X1, t.X2}, Y[3] = {t.Y0, t.Y1, t.Y2};
-    bool in = true;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const int k1 = (k + 1) % 3;
-        const int64_t dX = (int64_t)X[k1] - X[k], dY = (int64_t)Y[k1] - Y[k];
-        const int64_t E = dX * (Sy - Y[k]) - dY * (Sx - X[k]);
-        const bool tl = (dY < 0) || (dY == 0 && dX > 0);
-        in = in && ((E > 0) || (E == 0 && tl));
-    }
-    return in;
+    if (code >= 0) build_face(s, sc, cam, code >> 3, code & 7, P);
+    else build_road(s, sc, cam, -code - 1, P);
 }
 
-// Fold list triangles into the key buffer of rows [b0, b1).
-__device__ void raster_list(const Cam &cam, Lds &L, int ntri, int b0, int b1)
+// One setup pass over boxes (kind 0) or road bins (kind 1).
+__device__ void setup_source(const DevSim &s, const SceneRec &sc, const Cam &cam, int ego, int kind,
+                             const Sink &K, Lds &L)
 {
-    const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int ti = w; ti < ntri; ti += nw) {
-        const TriRec t = L.tris[ti];
-        const int j0 = max((int)t.j0, b0), j1 = min((int)t.j1, b1 - 1);
-        if (j0 > j1) continue;
-        const int bw = t.i1 - t.i0 + 1;
-        const int n = bw * (j1 - j0 + 1);
-        const float inv_bw = 1.0f / (float)bw;
-        for (int sidx = lane; sidx < n; sidx += 64) {
-            const int dj = (int)(((float)sidx + 0.5f) * inv_bw);
-            const int di = sidx - dj * bw;
-            const int i = t.i0 + di, j = j0 + dj;
-            if (di < 0 || di >= bw || j > j1) continue;     // cannot happen for n < 2^20
-            if (!covers(t, 256 * (int64_t)i + 128, 256 * (int64_t)j + 128)) continue;
-            const float du = ((float)i + 0.5f) - cam.cx;
-            const float dv = ((float)j + 0.5f) - cam.cy;
-            const float invz = fmaf(t.A, du, fmaf(t.B, dv, t.C));
-            if (!(invz > 0.0f)) continue;
-            const unsigned long long key =
-                ((unsigned long long)__float_as_uint(invz) << 32) | (unsigned long long)t.keylo;
-            atomicMax(&L.zbuf[(j - b0) * cam.W + i], key);
+    const int B = blockDim.x, tid = threadIdx.x;
+    const int n_units = kind == 0 ? sc.n_agents : sc.n_bins;
+    const bool can_flush = (kind == 1 && K.fast) || K.flush_tris;
+    // with flushing, a round may add at most 2 triangles per lane; keep it below the capacity
+    const int per_round = can_flush ? min(B, max(64, (L.cap / 2) & ~63)) : B;
+    for (int u0 = 0; u0 < n_units; u0 += B) {
+        // ---- cull units, compact the survivors
+        const int u = u0 + tid;
+        bool keep = false;
+        if (u < n_units) {
+            if (kind == 0) keep = (u != ego) && !box_outside(s, sc, cam, u);
+            else keep = !bin_outside(s, cam, s.bins[sc.bin_base + u]);
+        }
+        if (tid == 0) {
+            L.cnt[C_SURV] = 0;
+            L.cnt[C_PR0] = L.cnt[C_PR1] = L.cnt[C_PT0] = L.cnt[C_PT1] = 0;
+        }
+        __syncthreads();
+        {
+            const unsigned long long bm = __ballot(keep);
+            const int nk = __popcll(bm);
+            int base = 0;
+            if (nk > 0) {
+                const int leader = __ffsll((long long)bm) - 1;
+                if ((int)lane_id() == leader) base = atomicAdd(&L.cnt[C_SURV], nk);
+                base = __shfl(base, leader);
+            }
+            if (keep) L.surv[base + __popcll(bm & ((1ull << lane_id()) - 1ull))] = u;
+        }
+        __syncthreads();
+        const int ns = L.cnt[C_SURV];
+        const int ncand = kind == 0 ? 6 * ns : kBinQuads * ns;
+        // ---- rounds over the candidates of the survivors
+        int par = 0;
+        for (int c0 = 0; c0 < ncand; c0 += per_round, par ^= 1) {
+            const int c = c0 + tid;
+            bool live = tid < per_round && c < ncand;
+            int code = 0;
+            Poly P;
+            if (live) {
+                if (kind == 0) {
+                    const int j = L.surv[c / 6], f = c - 6 * (c / 6);
+                    code = j * 8 + f;
+                    build_face(s, sc, cam, j, f, P);
+                } else {
+                    const RoadBin &bn = s.bins[sc.bin_base + L.surv[c / kBinQuads]];
+                    const int k = c % kBinQuads;
+                    live = k < bn.count;
+                    if (live) {
+                        code = -(bn.start + k + 1);
+                        build_road(s, sc, cam, bn.start + k, P);
+                    }
+                }
+            }
+            TriRec t0, t1;
+            bool v0 = false, v1 = false, clip = false;
+            if (live) fast_poly(cam, P, K, t0, v0, t1, v1, clip);
+            const bool road = K.fast && kind == 1;
+            if (clip) {
+                const int q = atomicAdd(&L.cnt[C_CLIPQ], 1);
+                L.clipq[q] = code;
+            }
+            if (can_flush) {
+                // count this round's triangles, flush first if they would not fit
+                const int nr = __popcll(__ballot(v0 && road)) + __popcll(__ballot(v1 && road));
+                const int nt = __popcll(__ballot(v0 && !road)) + __popcll(__ballot(v1 && !road));
+                if (lane_id() == 0 && (nr | nt)) {
+                    atomicAdd(&L.cnt[C_PR0 + par], nr);
+                    atomicAdd(&L.cnt[C_PT0 + par], nt);
+                }
+                __syncthreads();
+                if (K.fast && L.cnt[C_RTRIS] + L.cnt[C_PR0 + par] > L.cap) flush_roads(cam, L);
+                if (K.flush_tris && L.cnt[C_TRIS] + L.cnt[C_PT0 + par] > L.cap) flush_tris(cam, L, K);
+                if (tid == 0) { L.cnt[C_PR0 + (par ^ 1)] = 0; L.cnt[C_PT0 + (par ^ 1)] = 0; }
+            }
+            append_wave(L, C_RTRIS, v0 && road, t0, v1 && road, t1);
+            append_wave(L, C_TRIS, v0 && !road, t0, v1 && !road, t1);
+            if (K.fast && !road) {
+                if (v0) { atomicMin(&L.cnt[C_BMIN], (int)t0.g.j0); atomicMax(&L.cnt[C_BMAX], (int)t0.g.j1); }
+                if (v1) { atomicMin(&L.cnt[C_BMIN], (int)t1.g.j0); atomicMax(&L.cnt[C_BMAX], (int)t1.g.j1); }
+            }
+            __syncthreads();
+            const int nq = L.cnt[C_CLIPQ];
+            // the clipper may emit up to kMaxTrisPerCand triangles per candidate
+            const int chunk = can_flush ? max(1, L.cap / kMaxTrisPerCand) : B;
+            for (int q0 = 0; q0 < nq; q0 += chunk) {
+                const int qn = min(chunk, nq - q0);
+                if (can_flush) make_room(cam, L, K, qn * kMaxTrisPerCand);
+                for (int q = q0 + tid; q < q0 + qn; q += B) {
+                    Poly Q;
+                    build_code(s, sc, cam, L.clipq[q], Q);
+                    clip_poly(cam, Q, K, L);
+                }
+                __syncthreads();
+            }
+            if (tid == 0) L.cnt[C_CLIPQ] = 0;
+            __syncthreads();
         }
     }
 }
+
+// ------------------------------------------------------------ resolve
 
 __device__ __forceinline__ void clear_band(Lds &L, int npix)
 {
-    for (int p = threadIdx.x; p < npix; p += blockDim.x) L.zbuf[p] = 0ull;
+    for (int p = threadIdx.x; p < npix; p += blockDim.x) L.zb[p] = 0ull;
 }
 
-__device__ __forceinline__ uint8_t color_of(const DevSim &s, const SceneRec &sc, int32_t prim)
+// rgb kernel: rows [r0, r1) from the road coverage bits and, with keys, the
+// box key band whose first row is zb0.
+//
+// Every road strip shares the depth plane (A, B, C) with A = +-0, so the road
+// 1/z of pixel (i, j) is fma(A, du, y) = y for y = fma(B, dv, C) != 0: one
+// value per row, positive exactly below the horizon.  A box fragment beats
+// the road where its 1/z is not smaller (agents rank above roads on ties).
+template <bool KEYS>
+__device__ void resolve_fast(const DevSim &s, const Cam &cam, Lds &L, uint8_t *rgb, int64_t view, int r0,
+                             int r1, int zb0)
 {
-    const int nbox = 6 * sc.n_agents;
-    return prim < nbox ? s.agent_color[sc.agent_base + prim / 6]
-                       : s.road_color[sc.road_base + (prim - nbox)];
+    const int W = cam.W;
+    const int64_t img = view * (int64_t)W * cam.H;
+    const uint32_t road_rgb = L.pal[s.road_color0];
+    const uint32_t bg_rgb = L.pal[0];
+    auto color_of = [&](bool road, float rz, const unsigned long long *kp, int m) -> uint32_t {
+        if (KEYS) {
+            const unsigned long long kb = kp[m];
+            const bool box = kb != 0ull && (!road || (uint32_t)(kb >> 32) >= __float_as_uint(rz));
+            if (box) return L.pal[(uint32_t)kb & 0xFFu];
+        }
+        return road ? road_rgb : bg_rgb;
+    };
+    if ((W & 3) == 0) {
+        const int tpr = W >> 2;                       // threads per row, 4 pixels each
+        const int rpi = (int)blockDim.x / tpr;        // rows per pass (W <= 4 * blockDim)
+        const int rr = (int)threadIdx.x / tpr, qi = (int)threadIdx.x - rr * tpr;
+        if (rr >= rpi) return;
+        const int i = 4 * qi;
+        for (int j = r0 + rr; j < r1; j += rpi) {
+            const float dv = ((float)j + 0.5f) - cam.cy;
+            const float rz = fmaf(cam.road.B, dv, cam.road.C);
+            const bool rowok = rz > 0.0f;
+            const uint32_t bits = rowok ? (uint32_t)(L.road[(size_t)j * L.nw + (i >> 6)] >> (i & 63)) & 0xFu : 0u;
+            const unsigned long long *kp = KEYS ? L.zb + (size_t)(j - zb0) * W + i : nullptr;
+            const uint32_t c0 = color_of(bits & 1u, rz, kp, 0), c1 = color_of(bits & 2u, rz, kp, 1);
+            const uint32_t c2 = color_of(bits & 4u, rz, kp, 2), c3 = color_of(bits & 8u, rz, kp, 3);
+            uint32_t *out = reinterpret_cast<uint32_t *>(rgb + 3 * (img + (int64_t)j * W + i));
+            out[0] = (c0 & 0xFFFFFFu) | (c1 << 24);
+            out[1] = ((c1 >> 8) & 0xFFFFu) | (c2 << 16);
+            out[2] = ((c2 >> 16) & 0xFFu) | (c3 << 8);
+        }
+    } else {
+        const int npix = (r1 - r0) * W;
+        for (int p = threadIdx.x; p < npix; p += blockDim.x) {
+            const int j = r0 + p / W, i = p - (p / W) * W;
+            const float dv = ((float)j + 0.5f) - cam.cy;
+            const float rz = fmaf(cam.road.B, dv, cam.road.C);
+            const bool road = rz > 0.0f && ((L.road[(size_t)j * L.nw + (i >> 6)] >> (i & 63)) & 1ull);
+            const unsigned long long *kp = KEYS ? L.zb + (size_t)(j - zb0) * W + i : nullptr;
+            const uint32_t c = color_of(road, rz, kp, 0);
+            uint8_t *dst = rgb + 3 * (img + (int64_t)j * W + i);
+            dst[0] = (uint8_t)c;
+            dst[1] = (uint8_t)(c >> 8);
+            dst[2] = (uint8_t)(c >> 16);
+        }
+    }
 }
 
-__device__ void resolve_band(const DevSim &s, const SceneRec &sc, const Cam &cam, Lds &L,
-                             const RenderOut &o, int64_t view, int b0, int b1)
+// general kernel: key band -> colour, depth, primitive id.
+__device__ void resolve_general(const Cam &cam, Lds &L, const RenderOut &o, int64_t view, int b0, int b1)
 {
     const int W = cam.W;
     const int npix = (b1 - b0) * W;
-    const int64_t pix0 = view * (int64_t)cam.W * cam.H + (int64_t)b0 * W;
-    if ((W & 3) == 0) {
-        uint32_t *rgb32 = reinterpret_cast<uint32_t *>(o.rgb + 3 * pix0);
-        for (int q = threadIdx.x; q < (npix >> 2); q += blockDim.x) {
-            uint8_t c[12];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int p = 4 * q + k;
-                const unsigned long long key = L.zbuf[p];
-                int32_t prim = -1;
-                uint8_t ci = 0;
-                if (key != 0ull) {
-                    prim = (int32_t)(0x7FFFFFFFu - (uint32_t)(key & 0x7FFFFFFFull));
-                    ci = color_of(s, sc, prim);
-                }
-                c[3 * k + 0] = L.palette[3 * ci + 0];
-                c[3 * k + 1] = L.palette[3 * ci + 1];
-                c[3 * k + 2] = L.palette[3 * ci + 2];
-                if (o.depth) {
-                    const float invz = __uint_as_float((uint32_t)(key >> 32));
-                    o.depth[pix0 + p] = (key != 0ull) ? 1.0f / invz : __int_as_float(0x7F800000);
-                }
-                if (o.primid) o.primid[pix0 + p] = prim;
-            }
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const uint32_t w = (uint32_t)c[4 * k] | ((uint32_t)c[4 * k + 1] << 8) |
-                                   ((uint32_t)c[4 * k + 2] << 16) | ((uint32_t)c[4 * k + 3] << 24);
-                rgb32[3 * q + k] = w;
-            }
+    const int64_t pix0 = view * (int64_t)W * cam.H + (int64_t)b0 * W;
+    for (int p = threadIdx.x; p < npix; p += blockDim.x) {
+        const unsigned long long key = L.zb[p];
+        const uint32_t c = L.pal[key ? ((uint32_t)key & 0xFFu) : 0u];
+        uint8_t *dst = o.rgb + 3 * (pix0 + p);
+        dst[0] = (uint8_t)c;
+        dst[1] = (uint8_t)(c >> 8);
+        dst[2] = (uint8_t)(c >> 16);
+        if (o.depth) {
+            const float invz = __uint_as_float((uint32_t)(key >> 32));
+            o.depth[pix0 + p] = key ? 1.0f / invz : __int_as_float(0x7F800000);
         }
-    } else {
-        for (int p = threadIdx.x; p < npix; p += blockDim.x) {
-            const unsigned long long key = L.zbuf[p];
-            int32_t prim = -1;
-            uint8_t ci = 0;
-            if (key != 0ull) {
-                prim = (int32_t)(0x7FFFFFFFu - (uint32_t)(key & 0x7FFFFFFFull));
-                ci = color_of(s, sc, prim);
-            }
-            uint8_t *dst = o.rgb + 3 * (pix0 + p);
-            dst[0] = L.palette[3 * ci + 0];
-            dst[1] = L.palette[3 * ci + 1];
-            dst[2] = L.palette[3 * ci + 2];
-            if (o.depth) {
-                const float invz = __uint_as_float((uint32_t)(key >> 32));
-                o.depth[pix0 + p] = (key != 0ull) ? 1.0f / invz : __int_as_float(0x7F800000);
-            }
-            if (o.primid) o.primid[pix0 + p] = prim;
-        }
+        if (o.primid)
+            o.primid[pix0 + p] = key ? (int32_t)(kMaxPrims - 1) - (int32_t)(((uint32_t)key >> 8) & (kMaxPrims - 1)) : -1;
     }
 }
 
-__device__ __forceinline__ Cam make_cam(const DevSim &s, const SceneRec &sc, int ego, int k)
+// ------------------------------------------------------------ per view
+
+__device__ __forceinline__ void reset_counts(Lds &L)
 {
-    Cam c;
-    const int ga = sc.agent_base + ego;
-    const float4 st = s.state[ga];
-    const float2 cs = s.cs[ga];
-    const float ce = cs.x, se = cs.y;
-    const float ck = s.cam_dir[k][0], sk = s.cam_dir[k][1];
-    c.px = st.x;
-    c.py = st.y;
-    c.fx = fmaf(ce, ck, -(se * sk));
-    c.fy = fmaf(se, ck, ce * sk);
-    c.h = s.cam_height;
-    c.W = s.width;
-    c.H = s.height;
-    c.f = s.focal;
-    c.cx = 0.5f * (float)s.width;
-    c.cy = 0.5f * (float)s.height;
-    c.F256 = 256.0f * c.f;
-    c.CX256 = 256.0f * c.cx;
-    c.CY256 = 256.0f * c.cy;
-    c.G = 268435456.0f / c.F256;
-    c.zn = s.z_near;
-    c.zf = s.z_far;
-    c.t_right = ((float)s.width - c.cx) / c.f;
-    c.t_left = c.cx / c.f;
-    c.t_top = c.cy / c.f;
-    c.t_bottom = ((float)s.height - c.cy) / c.f;
-    return c;
+    const int t = threadIdx.x;
+    if (t < C_NCNT) L.cnt[t] = (t == C_BMIN) ? 0x7FFFFFFF : (t == C_BMAX ? -1 : 0);
 }
 
-// Run the cull/setup pass over every candidate, emitting triangles that touch
-// rows [r0, r1).  With flush = false an overflow only raises the flag; with
-// flush = true the list is rastered into the band buffer when it gets full.
-__device__ void setup_pass(const DevSim &s, const SceneRec &sc, const Cam &cam, int ego, int r0,
-                           int r1, Lds &L, bool flush)
-{
-    const int ncand = 6 * sc.n_agents + sc.n_roads;
-    const int B = blockDim.x;
-    // while flushing, limit each round so that a full round always fits
-    const int per_round = flush ? min(B, L.cap / kMaxTrisPerCand) : B;
-    for (int base = 0; base < ncand; base += per_round) {
-        if (flush) {
-            __syncthreads();
-            if (L.cnt[0] + per_round * kMaxTrisPerCand > L.cap) {
-                raster_list(cam, L, min(L.cnt[0], L.cap), r0, r1);
-                __syncthreads();
-                if (threadIdx.x == 0) L.cnt[0] = 0;
-                __syncthreads();
-            }
-        }
-        const int c = base + (int)threadIdx.x;
-        const bool active = (int)threadIdx.x < per_round && c < ncand;
-        const bool clip = fast_candidate(s, sc, cam, ego, c, active, r0, r1, L);
-        if (clip) {
-            const int q = atomicAdd(&L.cnt[2], 1);
-            L.clipq[q] = c;
-        }
-        __syncthreads();
-        const int nq = L.cnt[2];
-        for (int q = threadIdx.x; q < nq; q += B) clip_candidate(s, sc, cam, ego, L.clipq[q], r0, r1, L);
-        __syncthreads();
-        if (threadIdx.x == 0) L.cnt[2] = 0;
-        if (!flush && L.cnt[1]) break;      // uniform: read after the barrier above
-        __syncthreads();
-    }
-    __syncthreads();
-}
-
+template <int FAST>
 __device__ void render_view(const DevSim &s, const RenderOut &o, const LaunchCfg &lc, Lds &L, int view)
 {
     const ViewRec vr = s.views[view];
@@ -637,68 +979,127 @@ __device__ void render_view(const DevSim &s, const RenderOut &o, const LaunchCfg
     const int ego = vr.ego_cam >> 2, k = vr.ego_cam & 3;
     const Cam cam = make_cam(s, sc, ego, k);
     const int H = cam.H, W = cam.W, BR = lc.band_rows;
-    if (threadIdx.x == 0) { L.cnt[0] = 0; L.cnt[1] = 0; L.cnt[2] = 0; }
+    reset_counts(L);
+    if (FAST) {
+        for (int p = threadIdx.x; p < H * L.nw; p += blockDim.x) L.road[p] = 0ull;
+    }
     __syncthreads();
-    setup_pass(s, sc, cam, ego, 0, H, L, false);
-    const bool overflow = L.cnt[1] != 0;
-    const int ntri = min(L.cnt[0], L.cap);
+    Sink K;
+    K.fast = FAST;
+    K.flush_tris = 0;
+    K.r0 = 0;
+    K.r1 = H;
+    setup_source(s, sc, cam, ego, 0, K, L);           // boxes
+    setup_source(s, sc, cam, ego, 1, K, L);           // road strips
+    if (FAST) flush_roads(cam, L);
+    const bool overflow = L.cnt[C_OVF] != 0;
+    const int ntri = min(L.cnt[C_TRIS], L.cap);
+    // rows that need the key band: every row for the general kernel; for the
+    // rgb kernel the rows touched by box triangles (all rows after an overflow)
+    int kr0 = 0, kr1 = H;
+    if (FAST && !overflow) {
+        kr0 = min(L.cnt[C_BMIN], H);
+        kr1 = max(L.cnt[C_BMAX] + 1, kr0);
+    }
     __syncthreads();
-    for (int b0 = 0; b0 < H; b0 += BR) {
-        const int b1 = min(H, b0 + BR);
+    if (FAST) {
+        resolve_fast<false>(s, cam, L, o.rgb, view, 0, kr0, 0);
+        resolve_fast<false>(s, cam, L, o.rgb, view, kr1, H, 0);
+    }
+    for (int b0 = kr0; b0 < kr1; b0 += BR) {
+        const int b1 = min(kr1, b0 + BR);
         clear_band(L, (b1 - b0) * W);
         __syncthreads();
         if (!overflow) {
-            raster_list(cam, L, ntri, b0, b1);
+            raster_tris(cam, L, ntri, b0, b1);
         } else {
-            if (threadIdx.x == 0) { L.cnt[0] = 0; L.cnt[1] = 0; L.cnt[2] = 0; }
+            // the list did not hold every triangle: redo this band's setup
+            // with flushes into the band
+            reset_counts(L);
             __syncthreads();
-            setup_pass(s, sc, cam, ego, b0, b1, L, true);
-            raster_list(cam, L, min(L.cnt[0], L.cap), b0, b1);
+            Sink KB;
+            KB.fast = FAST;
+            KB.flush_tris = 1;
+            KB.r0 = b0;
+            KB.r1 = b1;
+            setup_source(s, sc, cam, ego, 0, KB, L);
+            if (!FAST) setup_source(s, sc, cam, ego, 1, KB, L);
+            flush_tris(cam, L, KB);
         }
-        __syncthreads();
-        resolve_band(s, sc, cam, L, o, view, b0, b1);
+        if (FAST) resolve_fast<true>(s, cam, L, o.rgb, view, b0, b1, b0);
+        else resolve_general(cam, L, o, view, b0, b1);
         __syncthreads();
     }
 }
 
+template <int FAST>
 __global__ void k_render(DevSim s, RenderOut o, LaunchCfg lc, int persistent, int view_begin)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     Lds L;
     L.cap = lc.batch_tris;
+    L.nw = (s.width + 63) >> 6;
     size_t off = 0;
     L.tris = reinterpret_cast<TriRec *>(smem + off);
-    off += sizeof(TriRec) * (size_t)lc.batch_tris;
-    L.zbuf = reinterpret_cast<unsigned long long *>(smem + off);
-    off += sizeof(unsigned long long) * (size_t)lc.band_rows * s.width;
+    off += sizeof(TriRec) * (size_t)L.cap;
+    L.rtris = reinterpret_cast<TriGeo *>(smem + off);
+    off += FAST ? sizeof(TriGeo) * (size_t)L.cap : 0;
+    L.zb = reinterpret_cast<unsigned long long *>(smem + off);
+    off += 8u * (size_t)lc.band_rows * s.width;
+    L.road = reinterpret_cast<unsigned long long *>(smem + off);
+    off += FAST ? 8u * (size_t)s.height * L.nw : 0;
+    L.scan = reinterpret_cast<int32_t *>(smem + off);
+    off += 4u * (size_t)(L.cap + 4);
+    L.surv = reinterpret_cast<int32_t *>(smem + off);
+    off += 4u * blockDim.x;
     L.clipq = reinterpret_cast<int32_t *>(smem + off);
-    off += sizeof(int32_t) * blockDim.x;
+    off += 4u * blockDim.x;
     L.cnt = reinterpret_cast<int32_t *>(smem + off);
-    off += 16;
-    L.palette = smem + off;
-    for (int p = threadIdx.x; p < 768; p += blockDim.x) L.palette[p] = s.palette[p];
+    off += 4u * 16;
+    L.wsum = reinterpret_cast<int32_t *>(smem + off);
+    off += 4u * 16;
+    L.pal = reinterpret_cast<uint32_t *>(smem + off);
+    for (int p = threadIdx.x; p < 256; p += blockDim.x)
+        L.pal[p] = (uint32_t)s.palette[3 * p] | ((uint32_t)s.palette[3 * p + 1] << 8) |
+                   ((uint32_t)s.palette[3 * p + 2] << 16);
     __shared__ int s_item;
     if (!persistent) {
         __syncthreads();
-        render_view(s, o, lc, L, view_begin + blockIdx.x);
+        render_view<FAST>(s, o, lc, L, view_begin + blockIdx.x);
         return;
     }
+    // counter[0]: queue head; counter[1]: workgroups that have left the loop.
+    // The last workgroup to leave zeroes both, so the next launch on the
+    // stream starts from an empty queue without a separate reset (and a
+    // captured graph holds no memset node).
     for (;;) {
         __syncthreads();
-        if (threadIdx.x == 0) s_item = (int)atomicAdd(s.counter, 1u);
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(&s.counter[0], 1u);
         __syncthreads();
         const int it = s_item;
         if (it >= s.n_views) break;
-        render_view(s, o, lc, L, s.queue[it]);
+        render_view<FAST>(s, o, lc, L, s.queue[it]);
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t done = atomicAdd(&s.counter[1], 1u);
+        if (done == gridDim.x - 1) {
+            atomicExch(&s.counter[0], 0u);
+            atomicExch(&s.counter[1], 0u);
+            __threadfence();
+        }
     }
 }
 
 // ------------------------------------------------------------ launchers
 
-size_t render_lds_bytes(const DevSim &s, const LaunchCfg &c)
+size_t render_lds_bytes(const DevSim &s, const LaunchCfg &c, int fast)
 {
-    return sizeof(TriRec) * (size_t)c.batch_tris + 8u * (size_t)c.band_rows * s.width +
-           4u * (size_t)c.block_threads + 16u + 768u;
+    const size_t nw = (size_t)(s.width + 63) / 64;
+    size_t b = sizeof(TriRec) * (size_t)c.batch_tris + 8u * (size_t)c.band_rows * s.width +
+               4u * (size_t)(c.batch_tris + 4) + 8u * (size_t)c.block_threads + 64u + 64u + 1024u;
+    if (fast) b += sizeof(TriGeo) * (size_t)c.batch_tris + 8u * (size_t)s.height * nw;
+    return b;
 }
 
 hipError_t launch_step(const DevSim &s, const float *actions, int agent_begin, int agent_count,
@@ -718,19 +1119,17 @@ hipError_t launch_cs(const DevSim &s, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_reset_counter(const DevSim &s, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, s.counter);
-    return hipGetLastError();
-}
-
-hipError_t launch_render(const DevSim &s, const RenderOut &o, const LaunchCfg &c, int persistent,
-                         int view_begin, int grid, hipStream_t st)
+hipError_t launch_render(const DevSim &s, const RenderOut &o, const LaunchCfg &c, int fast,
+                         int persistent, int view_begin, int grid, hipStream_t st)
 {
     if (grid <= 0) return hipSuccess;
-    const size_t lds = render_lds_bytes(s, c);
-    hipLaunchKernelGGL(k_render, dim3(grid), dim3(c.block_threads), lds, st, s, o, c, persistent,
-                       view_begin);
+    const size_t lds = render_lds_bytes(s, c, fast);
+    if (fast)
+        hipLaunchKernelGGL(k_render<1>, dim3(grid), dim3(c.block_threads), lds, st, s, o, c, persistent,
+                           view_begin);
+    else
+        hipLaunchKernelGGL(k_render<0>, dim3(grid), dim3(c.block_threads), lds, st, s, o, c, persistent,
+                           view_begin);
     return hipGetLastError();
 }
 

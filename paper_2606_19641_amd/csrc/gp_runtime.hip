@@ -1,7 +1,8 @@
 // C ABI runtime of the Gigapixel hot path: argument checks, workspace
-// layout, scene upload, launch scheduling (per-scene, persistent work queue,
-// hipGraph replay) and error reporting.  The declarations and their contract
-// are in include/gp.h.
+// layout, scene upload (with spatial sorting of road strips into culling
+// bins), launch scheduling (per-scene, persistent work queue, hipGraph
+// replay) and error reporting.  The declarations and their contract are in
+// include/gp.h.
 #include "../../include/gp.h"
 #include "gp_device.h"
 
@@ -39,10 +40,13 @@ gp_status hip_fail(hipError_t e, const char *what)
 constexpr int64_t kAlign = 256;
 int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+int64_t n_bins_of(int32_t n_roads) { return (n_roads + gp::kBinQuads - 1) / gp::kBinQuads; }
+
 struct Layout {
-    int64_t scenes, views, state, cs, dims, agent_color, roads, road_color, palette, queue, counter;
+    int64_t scenes, views, state, cs, dims, agent_color, roads, road_index, road_color, bins, palette,
+        queue, counter;
     int64_t total;
-    int64_t n_agents, n_roads, n_views;
+    int64_t n_agents, n_roads, n_views, n_bins;
 };
 
 bool finite_cfg(const gp_config *c)
@@ -59,10 +63,9 @@ gp_status check_inputs(const gp_config *cfg, const gp_scene_desc *sc, int32_t n)
     if (cfg->n_cams < 1 || cfg->n_cams > GP_MAX_CAMS)
         return fail(GP_EINVAL, "n_cams %d outside 1..%d", cfg->n_cams, GP_MAX_CAMS);
     if (!finite_cfg(cfg) || !(cfg->focal_px > 0.0f) || !(cfg->z_near > 0.0f) || !(cfg->z_far > cfg->z_near) ||
-        !(cfg->dt >= 0.0f))
+        !(cfg->dt >= 0.0f) || !(cfg->cam_height > 0.0f))
         return fail(GP_EINVAL, "camera/dynamics constants out of range");
-    if (256.0 * cfg->focal_px > 262144.0)
-        return fail(GP_EINVAL, "focal length above 1024 px");
+    if (cfg->focal_px > 1024.0f) return fail(GP_EINVAL, "focal length above 1024 px");
     for (int k = 0; k < cfg->n_cams; ++k)
         if (!std::isfinite(cfg->cam_dir[k][0]) || !std::isfinite(cfg->cam_dir[k][1]))
             return fail(GP_EINVAL, "camera direction %d not finite", k);
@@ -73,12 +76,14 @@ gp_status check_inputs(const gp_config *cfg, const gp_scene_desc *sc, int32_t n)
         const gp_scene_desc &d = sc[s];
         if (d.n_agents < 1 || d.n_roads < 0)
             return fail(GP_EINVAL, "scene %d: n_agents must be >= 1 and n_roads >= 0", s);
-        if (6LL * d.n_agents + d.n_roads >= (1LL << 31) - 1)
-            return fail(GP_EINVAL, "scene %d: too many primitives", s);
+        if (6LL * d.n_agents + d.n_roads >= gp::kMaxPrims)
+            return fail(GP_EINVAL, "scene %d: more than %d primitives", s, gp::kMaxPrims);
         if (!d.agent_state || !d.agent_dims || !d.agent_color)
             return fail(GP_EINVAL, "scene %d: agent arrays are NULL", s);
         if (d.n_roads > 0 && (!d.road_xy || !d.road_color))
             return fail(GP_EINVAL, "scene %d: road arrays are NULL", s);
+        for (int64_t i = 0; i < 8LL * d.n_roads; ++i)
+            if (!std::isfinite(d.road_xy[i])) return fail(GP_EINVAL, "scene %d: road corner not finite", s);
         na += d.n_agents;
         nr += d.n_roads;
     }
@@ -93,6 +98,7 @@ Layout make_layout(const gp_config *cfg, const gp_scene_desc *sc, int32_t n)
     for (int s = 0; s < n; ++s) {
         L.n_agents += sc[s].n_agents;
         L.n_roads += sc[s].n_roads;
+        L.n_bins += n_bins_of(sc[s].n_roads);
     }
     L.n_views = L.n_agents * cfg->n_cams;
     int64_t o = 0;
@@ -104,10 +110,12 @@ Layout make_layout(const gp_config *cfg, const gp_scene_desc *sc, int32_t n)
     L.dims = take(16 * L.n_agents);
     L.agent_color = take(L.n_agents);
     L.roads = take(32 * L.n_roads);
+    L.road_index = take(4 * L.n_roads);
     L.road_color = take(L.n_roads);
+    L.bins = take(sizeof(gp::RoadBin) * L.n_bins);
     L.palette = take(768);
     L.queue = take(4 * L.n_views);
-    L.counter = take(4);
+    L.counter = take(8);
     L.total = o;
     return L;
 }
@@ -119,6 +127,74 @@ bool valid_launch(const gp_launch &l)
     const bool th = l.block_threads == 256 || l.block_threads == 512 || l.block_threads == 1024;
     const bool sc = l.sched == GP_SCHED_PLAIN || l.sched == GP_SCHED_PERSISTENT;
     return br && bt && th && sc && l.blocks_per_cu >= 1 && l.blocks_per_cu <= 16;
+}
+
+// 2-D Morton code of 16-bit coordinates
+uint32_t morton16(uint32_t x, uint32_t y)
+{
+    auto spread = [](uint32_t v) {
+        v &= 0xFFFFu;
+        v = (v | (v << 8)) & 0x00FF00FFu;
+        v = (v | (v << 4)) & 0x0F0F0F0Fu;
+        v = (v | (v << 2)) & 0x33333333u;
+        v = (v | (v << 1)) & 0x55555555u;
+        return v;
+    };
+    return spread(x) | (spread(y) << 1);
+}
+
+// Order the road strips of one scene along a Morton curve of their centres
+// and cut the order into bins of kBinQuads; each bin keeps the exact float
+// bounding box of its strips' corners.  Returns the slot -> input index map.
+std::vector<int32_t> sort_roads(const gp_scene_desc &d, std::vector<gp::RoadBin> &bins)
+{
+    const int n = d.n_roads;
+    std::vector<int32_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    if (n == 0) return order;
+    double xmin = 1e300, ymin = 1e300, xmax = -1e300, ymax = -1e300;
+    std::vector<double> cx(n), cy(n);
+    for (int r = 0; r < n; ++r) {
+        double sx = 0, sy = 0;
+        for (int k = 0; k < 4; ++k) {
+            sx += d.road_xy[8 * r + 2 * k];
+            sy += d.road_xy[8 * r + 2 * k + 1];
+        }
+        cx[r] = sx / 4;
+        cy[r] = sy / 4;
+        xmin = std::min(xmin, cx[r]);
+        xmax = std::max(xmax, cx[r]);
+        ymin = std::min(ymin, cy[r]);
+        ymax = std::max(ymax, cy[r]);
+    }
+    const double sx = xmax > xmin ? 65535.0 / (xmax - xmin) : 0.0;
+    const double sy = ymax > ymin ? 65535.0 / (ymax - ymin) : 0.0;
+    std::vector<uint32_t> code(n);
+    for (int r = 0; r < n; ++r)
+        code[r] = morton16((uint32_t)((cx[r] - xmin) * sx), (uint32_t)((cy[r] - ymin) * sy));
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return code[a] < code[b]; });
+    for (int b0 = 0; b0 < n; b0 += gp::kBinQuads) {
+        gp::RoadBin bn{};
+        bn.start = b0;
+        bn.count = std::min(gp::kBinQuads, n - b0);
+        float x0 = INFINITY, y0 = INFINITY, x1 = -INFINITY, y1 = -INFINITY;
+        for (int k = 0; k < bn.count; ++k) {
+            const int r = order[b0 + k];
+            for (int c = 0; c < 4; ++c) {
+                const float x = d.road_xy[8 * r + 2 * c], y = d.road_xy[8 * r + 2 * c + 1];
+                x0 = std::min(x0, x);
+                x1 = std::max(x1, x);
+                y0 = std::min(y0, y);
+                y1 = std::max(y1, y);
+            }
+        }
+        bn.xmin = x0;
+        bn.ymin = y0;
+        bn.xmax = x1;
+        bn.ymax = y1;
+        bins.push_back(bn);
+    }
+    return order;
 }
 
 }  // namespace
@@ -154,7 +230,8 @@ gp::LaunchCfg launch_cfg(const gp_launch &l)
 
 gp_status check_lds(const gp_sim *sim, const gp_launch &l)
 {
-    const size_t need = gp::render_lds_bytes(sim->dev, launch_cfg(l));
+    const size_t need = std::max(gp::render_lds_bytes(sim->dev, launch_cfg(l), 0),
+                                 sim->dev.road_color_uniform ? gp::render_lds_bytes(sim->dev, launch_cfg(l), 1) : 0);
     if (need > sim->max_lds)
         return fail(GP_EINVAL, "launch needs %zu B of LDS, the device allows %zu", need, sim->max_lds);
     return GP_OK;
@@ -163,19 +240,20 @@ gp_status check_lds(const gp_sim *sim, const gp_launch &l)
 gp_status render_impl(gp_sim *sim, const gp::RenderOut &o, const gp_launch &l, hipStream_t st)
 {
     const gp::LaunchCfg c = launch_cfg(l);
+    // the rgb-only kernel serves renders without depth / primitive id when
+    // every road strip has the same colour; everything else takes the general one
+    const int fast = (!o.depth && !o.primid && sim->dev.road_color_uniform) ? 1 : 0;
     hipError_t e;
     if (l.sched == GP_SCHED_PLAIN) {
         for (int s = 0; s < sim->n_scenes; ++s) {
             const gp::SceneRec &r = sim->scenes[s];
-            e = gp::launch_render(sim->dev, o, c, 0, r.view_base, r.n_agents * sim->cfg.n_cams, st);
+            e = gp::launch_render(sim->dev, o, c, fast, 0, r.view_base, r.n_agents * sim->cfg.n_cams, st);
             if (e != hipSuccess) return hip_fail(e, "render launch");
         }
         return GP_OK;
     }
-    e = gp::launch_reset_counter(sim->dev, st);
-    if (e != hipSuccess) return hip_fail(e, "queue reset");
     const int64_t grid = std::min<int64_t>(sim->lay.n_views, (int64_t)l.blocks_per_cu * sim->n_cu);
-    e = gp::launch_render(sim->dev, o, c, 1, 0, (int)grid, st);
+    e = gp::launch_render(sim->dev, o, c, fast, 1, 0, (int)grid, st);
     if (e != hipSuccess) return hip_fail(e, "render launch");
     return GP_OK;
 }
@@ -253,28 +331,30 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
     std::vector<unsigned char> host((size_t)L.total, 0);
     auto at = [&](int64_t off) { return host.data() + off; };
     sim->scenes.resize(n_scenes);
-    int32_t abase = 0, rbase = 0;
-    for (int s = 0; s < n_scenes; ++s) {
-        gp::SceneRec &r = sim->scenes[s];
-        r.agent_base = abase;
-        r.n_agents = scenes[s].n_agents;
-        r.road_base = rbase;
-        r.n_roads = scenes[s].n_roads;
-        r.view_base = abase * cfg->n_cams;
-        r.pad0 = r.pad1 = r.pad2 = 0;
-        abase += r.n_agents;
-        rbase += r.n_roads;
-    }
-    std::memcpy(at(L.scenes), sim->scenes.data(), sizeof(gp::SceneRec) * n_scenes);
     auto *views = reinterpret_cast<gp::ViewRec *>(at(L.views));
     auto *state = reinterpret_cast<float *>(at(L.state));
     auto *dims = reinterpret_cast<float *>(at(L.dims));
     auto *acol = at(L.agent_color);
     auto *roads = reinterpret_cast<float *>(at(L.roads));
+    auto *ridx = reinterpret_cast<int32_t *>(at(L.road_index));
     auto *rcol = at(L.road_color);
+    auto *bins = reinterpret_cast<gp::RoadBin *>(at(L.bins));
+    int32_t abase = 0, rbase = 0, bbase = 0;
+    bool uniform = true;
+    int color0 = -1;
     for (int s = 0; s < n_scenes; ++s) {
         const gp_scene_desc &d = scenes[s];
-        const gp::SceneRec &r = sim->scenes[s];
+        gp::SceneRec &r = sim->scenes[s];
+        std::vector<gp::RoadBin> sb;
+        const std::vector<int32_t> order = sort_roads(d, sb);
+        r.agent_base = abase;
+        r.n_agents = d.n_agents;
+        r.road_base = rbase;
+        r.n_roads = d.n_roads;
+        r.view_base = abase * cfg->n_cams;
+        r.bin_base = bbase;
+        r.n_bins = (int32_t)sb.size();
+        r.pad = 0;
         for (int a = 0; a < d.n_agents; ++a) {
             const int g = r.agent_base + a;
             for (int k = 0; k < 4; ++k) state[4 * g + k] = d.agent_state[4 * a + k];
@@ -287,11 +367,20 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
                 v.ego_cam = a * 4 + c;
             }
         }
-        if (d.n_roads > 0) {
-            std::memcpy(roads + 8 * (int64_t)r.road_base, d.road_xy, sizeof(float) * 8 * (size_t)d.n_roads);
-            std::memcpy(rcol + r.road_base, d.road_color, (size_t)d.n_roads);
+        for (int k = 0; k < d.n_roads; ++k) {
+            const int src = order[k];
+            std::memcpy(roads + 8 * (int64_t)(rbase + k), d.road_xy + 8 * (int64_t)src, 32);
+            ridx[rbase + k] = src;
+            rcol[rbase + k] = d.road_color[src];
+            if (color0 < 0) color0 = d.road_color[src];
+            uniform = uniform && d.road_color[src] == color0;
         }
+        if (!sb.empty()) std::memcpy(bins + bbase, sb.data(), sizeof(gp::RoadBin) * sb.size());
+        abase += d.n_agents;
+        rbase += d.n_roads;
+        bbase += (int32_t)sb.size();
     }
+    std::memcpy(at(L.scenes), sim->scenes.data(), sizeof(gp::SceneRec) * n_scenes);
     std::memcpy(at(L.palette), cfg->palette, 768);
     // persistent queue: heavier scenes first, views of a scene adjacent so
     // that they share the scene's geometry in L2
@@ -323,7 +412,9 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
     D.dims = reinterpret_cast<const float4 *>(base + L.dims);
     D.agent_color = base + L.agent_color;
     D.roads = reinterpret_cast<const float4 *>(base + L.roads);
+    D.road_index = reinterpret_cast<const int32_t *>(base + L.road_index);
     D.road_color = base + L.road_color;
+    D.bins = reinterpret_cast<const gp::RoadBin *>(base + L.bins);
     D.palette = base + L.palette;
     D.queue = reinterpret_cast<const int32_t *>(base + L.queue);
     D.counter = reinterpret_cast<uint32_t *>(base + L.counter);
@@ -333,6 +424,8 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
     D.width = cfg->width;
     D.height = cfg->height;
     D.n_cams = cfg->n_cams;
+    D.road_color_uniform = uniform ? 1 : 0;
+    D.road_color0 = color0 < 0 ? 0 : color0;
     for (int k = 0; k < gp::kMaxCams; ++k) {
         D.cam_dir[k][0] = cfg->cam_dir[k][0];
         D.cam_dir[k][1] = cfg->cam_dir[k][1];
@@ -342,15 +435,30 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
     D.z_near = cfg->z_near;
     D.z_far = cfg->z_far;
     D.dt = cfg->dt;
+    // Road points project to row v = cy + h f / z.  Rows whose sample is below
+    // the horizon and not more than 4 subpixels above the far line can show
+    // road; the farthest depth they look at, plus 2% (>= 2.5 subpixels of
+    // clearance at the nearest-to-horizon row), bounds every visible road point.
+    {
+        const double hf = (double)cfg->cam_height * (double)cfg->focal_px;
+        const double v_far = hf / (double)cfg->z_far;
+        const double cy = 0.5 * cfg->height;
+        double zmax = 0.0;
+        for (int j = 0; j < cfg->height; ++j) {
+            const double dv = j + 0.5 - cy;
+            if (dv > 0.0 && dv >= v_far - 4.0 / 256.0) zmax = std::max(zmax, hf / dv);
+        }
+        D.road_zmax = (float)(zmax * 1.02);
+    }
 
     e = gp::launch_cs(D, hs);
     if (e != hipSuccess) { delete sim; return hip_fail(e, "heading cosines"); }
 
-    // default launch: persistent queue, a 32 KB band buffer
+    // default launch: persistent queue, a 16 KB band buffer
     gp_launch l{};
     l.sched = GP_SCHED_PERSISTENT;
     l.band_rows = 64;
-    while (l.band_rows > 8 && 8LL * l.band_rows * cfg->width > 32768) l.band_rows /= 2;
+    while (l.band_rows > 8 && 8LL * l.band_rows * cfg->width > 16384) l.band_rows /= 2;
     l.batch_tris = 512;
     l.block_threads = 256;
     l.blocks_per_cu = 2;

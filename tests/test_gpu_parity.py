@@ -135,17 +135,64 @@ def test_crowded_three_cameras(seed):
                    _views_of(scenes, cam))
 
 
+@pytest.mark.parametrize("seed", range(4))
+def test_rgb_kernel_matches_oracle_and_general_kernel(seed):
+    """rgb-only renders of uniform-road-colour scenes take the rgb kernel
+    (road coverage bitmask); it must equal the oracle and the general kernel."""
+    scenes = [g.crowded_scene(200 + seed), g.crowded_scene(300 + seed, n_agents=40, n_roads=120)]
+    for s in scenes:
+        s.road_color[:] = 1
+    cam = g.camera_for(64, cams=g.FRONT_AND_SIDES)
+    pal = g.mixed_palette()
+    sim = _sim(scenes, cam, pal)
+    fast, _, _ = sim.render()
+    gen, _, _ = sim.render(depth=True)
+    torch.cuda.synchronize()
+    assert torch.equal(fast, gen)
+    _compare_views(scenes, cam, pal, fast.cpu().numpy(), None, None, _views_of(scenes, cam))
+
+
+def test_mixed_road_colours_rgb_only_takes_general_kernel():
+    scenes = [g.crowded_scene(7)]
+    cam = g.camera_for(48, cams=g.FRONT_AND_SIDES)
+    pal = g.mixed_palette()
+    sim = _sim(scenes, cam, pal)
+    rgb, _, _ = sim.render()
+    torch.cuda.synchronize()
+    _compare_views(scenes, cam, pal, rgb.cpu().numpy(), None, None, _views_of(scenes, cam))
+
+
+def test_rgb_kernel_box_list_overflow():
+    """128 boxes crowded around the camera overflow a 256-entry LDS list; the
+    rgb kernel then redoes the boxes band by band."""
+    s = g.crowded_scene(41, n_agents=128, n_roads=60, radius=18.0)
+    s.road_color[:] = 1
+    cam = g.camera_for(128)
+    pal = g.mixed_palette()
+    for lv in (dict(batch_tris=256, band_rows=16), dict(batch_tris=512, band_rows=8)):
+        sim = _sim([s], cam, pal, **lv)
+        rgb, _, _ = sim.render()
+        torch.cuda.synchronize()
+        _compare_views([s], cam, pal, rgb.cpu().numpy(), None, None, [(0, a, 0) for a in range(0, 128, 9)])
+
+
 def test_nonsquare_and_ragged_width():
     """Width not a multiple of 4 takes the byte-store path; 210x126 is the
     paper's student resolution (App. B)."""
-    scenes = [g.crowded_scene(21)]
+    scenes = [g.crowded_scene(21), g.workload("small").scenes[0]]
     pal = g.mixed_palette()
     for cam in (g.Camera(width=210, height=126, focal_px=105.0, cam_dirs=g.FRONT_AND_SIDES),
-                g.Camera(width=37, height=23, focal_px=18.5, cam_dirs=g.FRONT)):
+                g.Camera(width=37, height=23, focal_px=18.5, cam_dirs=g.FRONT),
+                g.Camera(width=12, height=9, focal_px=2.5, cam_dirs=g.FRONT),       # far line near a sample row
+                g.Camera(width=16, height=16, focal_px=8.0, z_far=30.0, cam_dirs=g.FRONT_AND_SIDES)):
         sim = _sim(scenes, cam, pal)
         rgb, depth, prim = sim.render(depth=True, primid=True)
         torch.cuda.synchronize()
         picks = [(0, a, k) for a in range(0, scenes[0].n_agents, 4) for k in range(len(cam.cam_dirs))]
+        picks += [(1, a, k) for a in range(scenes[1].n_agents) for k in range(len(cam.cam_dirs))]
+        fast, _, _ = sim.render()
+        torch.cuda.synchronize()
+        assert torch.equal(fast, rgb)
         _compare_views(scenes, cam, pal, rgb.cpu().numpy(), depth.cpu().numpy(), prim.cpu().numpy(),
                        picks)
 
@@ -159,21 +206,27 @@ def test_degenerate_scenes():
                    road_color=np.zeros(0, np.uint8))
     roads = np.array([[[-1e5, -1e5], [1e5, -1e5], [1e5, 1e5], [-1e5, 1e5]],
                       [[5, 1], [9, 1], [9, 1], [5, 1]],             # zero area
-                      [[4, -3], [4, 3], [30, 3], [30, -3]]], np.float32)   # clockwise
+                      [[4, -3], [4, 3], [30, 3], [30, -3]],         # clockwise
+                      [[6, -5], [14, 5], [14, -5], [6, 5]],         # self-intersecting (bow tie)
+                      [[0.2, -40], [0.3, -40], [0.3, 40], [0.2, 40]]], np.float32)   # crosses the near plane
     odd = g.Scene(agent_state=np.array([[0, 0, 0, 0], [8, 0, 0.2, 0], [-10, 0, 0, 0], [3, 0.5, 1.0, 0]], np.float32),
                   agent_dims=np.array([[4, 2, 1.5], [8, 3, 0.0], [4, 2, 1.8], [4.5, 2, 1.4]], np.float32),
                   agent_color=np.array([2, 3, 4, 5], np.uint8), road_xy=roads,
-                  road_color=np.array([1, 5, 1], np.uint8))
-    scenes = [lone, odd]
+                  road_color=np.array([1, 5, 1, 1, 1], np.uint8))
+    uniform = g.Scene(agent_state=odd.agent_state, agent_dims=odd.agent_dims, agent_color=odd.agent_color,
+                      road_xy=roads, road_color=np.ones(len(roads), np.uint8))
     pal = g.mixed_palette()
-    for res in (32, 64):
-        cam = g.camera_for(res, cams=g.FRONT_AND_SIDES)
-        sim = _sim(scenes, cam, pal)
-        rgb, depth, prim = sim.render(depth=True, primid=True)
-        torch.cuda.synchronize()
-        _compare_views(scenes, cam, pal, rgb.cpu().numpy(), depth.cpu().numpy(), prim.cpu().numpy(),
-                       _views_of(scenes, cam))
-        assert np.all(prim.cpu().numpy()[:3] == -1)        # the lone agent sees nothing
+    for scenes in ([lone, odd], [lone, uniform]):
+        for res in (32, 64):
+            cam = g.camera_for(res, cams=g.FRONT_AND_SIDES)
+            sim = _sim(scenes, cam, pal)
+            rgb, depth, prim = sim.render(depth=True, primid=True)
+            fast, _, _ = sim.render()
+            torch.cuda.synchronize()
+            _compare_views(scenes, cam, pal, rgb.cpu().numpy(), depth.cpu().numpy(), prim.cpu().numpy(),
+                           _views_of(scenes, cam))
+            assert torch.equal(fast, rgb)
+            assert np.all(prim.cpu().numpy()[:3] == -1)        # the lone agent sees nothing
 
 
 def test_overflow_fallback_path():
@@ -212,12 +265,14 @@ def test_every_launch_variant_gives_identical_bits():
             assert "LDS" in str(e)
             continue
         rgb, depth, prim = sim.render(depth=True, primid=True)
+        fast, _, _ = sim.render()
         torch.cuda.synchronize()
-        cur = (rgb.cpu().numpy(), depth.cpu().numpy(), prim.cpu().numpy())
+        cur = (rgb.cpu().numpy(), depth.cpu().numpy(), prim.cpu().numpy(), fast.cpu().numpy())
         if ref is None:
             ref = cur
             picks = [(s, a, k) for s in range(0, 6, 2) for a in (0, w.scenes[s].n_agents - 1) for k in range(3)]
-            _compare_views(w.scenes, w.camera, pal, *cur, picks)
+            _compare_views(w.scenes, w.camera, pal, *cur[:3], picks)
+            assert np.array_equal(cur[0], cur[3])
         else:
             for a, b in zip(ref, cur):
                 assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), lv
