@@ -626,12 +626,17 @@ __device__ __forceinline__ void flush_roads(const Cam &cam, Lds &L)
     __syncthreads();
 }
 
-// Make room for `need` more triangles in every list that can be flushed.
-// Uniform: must be called by every thread after a barrier.
-__device__ __forceinline__ void make_room(const Cam &cam, Lds &L, const Sink &K, int need)
+// Flush the lists that cannot take `need_r` road / `need_t` other triangles.
+// Called by every thread after a barrier.  The decision is read by every
+// thread before the second barrier and acted on only after it, so a wave that
+// appends right after this call cannot change another wave's decision.
+__device__ __forceinline__ void make_room(const Cam &cam, Lds &L, const Sink &K, int need_r, int need_t)
 {
-    if (K.fast && L.cnt[C_RTRIS] + need > L.cap) flush_roads(cam, L);
-    if (K.flush_tris && L.cnt[C_TRIS] + need > L.cap) flush_tris(cam, L, K);
+    const bool fr = K.fast && L.cnt[C_RTRIS] + need_r > L.cap;
+    const bool ft = K.flush_tris && L.cnt[C_TRIS] + need_t > L.cap;
+    __syncthreads();
+    if (fr) flush_roads(cam, L);
+    if (ft) flush_tris(cam, L, K);
 }
 
 // Append with one LDS atomic per wave; lanes whose triangle does not fit
@@ -845,8 +850,7 @@ __device__ void setup_source(const DevSim &s, const SceneRec &sc, const Cam &cam
                     atomicAdd(&L.cnt[C_PT0 + par], nt);
                 }
                 __syncthreads();
-                if (K.fast && L.cnt[C_RTRIS] + L.cnt[C_PR0 + par] > L.cap) flush_roads(cam, L);
-                if (K.flush_tris && L.cnt[C_TRIS] + L.cnt[C_PT0 + par] > L.cap) flush_tris(cam, L, K);
+                make_room(cam, L, K, L.cnt[C_PR0 + par], L.cnt[C_PT0 + par]);
                 if (tid == 0) { L.cnt[C_PR0 + (par ^ 1)] = 0; L.cnt[C_PT0 + (par ^ 1)] = 0; }
             }
             append_wave(L, C_RTRIS, v0 && road, t0, v1 && road, t1);
@@ -861,7 +865,7 @@ __device__ void setup_source(const DevSim &s, const SceneRec &sc, const Cam &cam
             const int chunk = can_flush ? max(1, L.cap / kMaxTrisPerCand) : B;
             for (int q0 = 0; q0 < nq; q0 += chunk) {
                 const int qn = min(chunk, nq - q0);
-                if (can_flush) make_room(cam, L, K, qn * kMaxTrisPerCand);
+                if (can_flush) make_room(cam, L, K, qn * kMaxTrisPerCand, qn * kMaxTrisPerCand);
                 for (int q = q0 + tid; q < q0 + qn; q += B) {
                     Poly Q;
                     build_code(s, sc, cam, L.clipq[q], Q);
