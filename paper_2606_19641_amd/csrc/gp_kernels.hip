@@ -489,20 +489,86 @@ __device__ bool row_span(const TriGeo &t, int j, int W, int &xl_out, int &xr_out
 // the row range touched by box triangles (rgb kernel)
 enum { C_TRIS = 0, C_RTRIS, C_OVF, C_CLIPQ, C_SURV, C_PR0, C_PR1, C_PT0, C_PT1, C_BMIN, C_BMAX, C_NCNT = 16 };
 
+// List capacities: the general kernel keeps every triangle in one list of
+// batch_tris entries; the rgb kernel keeps road triangles in a list of
+// batch_tris entries and box triangles (far fewer) in one of batch_tris / 2.
+__host__ __device__ inline void list_caps(int fast, int batch_tris, int &tcap, int &rcap)
+{
+    tcap = fast ? max(128, batch_tris / 2) : batch_tris;
+    rcap = fast ? batch_tris : 0;
+}
+
+// Pointers into LDS keep their address space in the type, so every access
+// through them is a ds_* instruction (a generic pointer would make the
+// compiler issue flat instructions, which go through the vector-memory path).
+#define GP_LDS __attribute__((address_space(3)))
+template <class T> using lptr = GP_LDS T *;
+
 struct Lds {
-    TriRec *tris;            // boxes (rgb kernel) or everything (general kernel)
-    TriGeo *rtris;           // road strips (rgb kernel)
-    unsigned long long *zb;  // band of 64-bit keys
-    unsigned long long *road;// rgb kernel: per-row road coverage bits [H][nw]
-    int32_t *scan;           // [cap + 1] row-count prefix
-    int32_t *surv;           // [B] surviving boxes / bins
-    int32_t *clipq;          // [B] candidates that need clipping
-    int32_t *cnt;            // counters (C_*)
-    int32_t *wsum;           // [16] per-wave partial sums
-    uint32_t *pal;           // [256] RGB as u32
-    int cap;
-    int nw;                  // 64-bit words per image row
+    lptr<TriRec> tris;              // boxes (rgb kernel) or everything (general kernel)
+    lptr<TriGeo> rtris;             // road strips (rgb kernel)
+    lptr<unsigned long long> zb;    // band of 64-bit keys
+    lptr<unsigned long long> road;  // rgb kernel: per-row road coverage bits [H][nw]
+    lptr<int32_t> scan;             // [cap + 4] row-count prefix
+    lptr<int32_t> surv;             // [B] surviving boxes / bins
+    lptr<int32_t> clipq;            // [B] candidates that need clipping
+    lptr<int32_t> cnt;              // counters (C_*)
+    lptr<int32_t> wsum;             // [16] per-wave partial sums
+    lptr<uint32_t> pal;             // [256] RGB as u32
+    int tcap;                       // capacity of tris
+    int rcap;                       // capacity of rtris (rgb kernel)
+    int nw;                         // 64-bit words per image row
+    __device__ int cap_of(int which) const { return which == C_RTRIS ? rcap : tcap; }
 };
+
+// Whole-record LDS copies as 16-byte vectors (the records' implicit copy
+// operators only bind to generic addresses).
+typedef int gp_v4i __attribute__((ext_vector_type(4)));
+
+template <class T>
+__device__ __forceinline__ T lds_load(lptr<T> p)
+{
+    constexpr int N = sizeof(T) / 16;
+    static_assert(sizeof(T) == 16 * N, "record size");
+    union { T t; gp_v4i v[N]; } u;
+    lptr<gp_v4i> q = (lptr<gp_v4i>)p;
+#pragma unroll
+    for (int k = 0; k < N; ++k) u.v[k] = q[k];
+    return u.t;
+}
+
+template <class T>
+__device__ __forceinline__ void lds_store(lptr<T> p, const T &t)
+{
+    constexpr int N = sizeof(T) / 16;
+    union { T t; gp_v4i v[N]; } u;
+    u.t = t;
+    lptr<gp_v4i> q = (lptr<gp_v4i>)p;
+#pragma unroll
+    for (int k = 0; k < N; ++k) q[k] = u.v[k];
+}
+
+// LDS atomics (relaxed; the barriers order them)
+__device__ __forceinline__ int lds_add(lptr<int32_t> p, int v)
+{
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_min(lptr<int32_t> p, int v)
+{
+    __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_max(lptr<int32_t> p, int v)
+{
+    __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_max64(lptr<unsigned long long> p, unsigned long long v)
+{
+    __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_or64(lptr<unsigned long long> p, unsigned long long v)
+{
+    __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
 
@@ -559,17 +625,17 @@ __device__ void raster_roads(const Cam &cam, Lds &L, int n)
     const int total = block_scan(L, n);
     for (int gi = threadIdx.x; gi < total; gi += blockDim.x) {
         const int t = find_row_owner(L, n, gi);
-        const TriGeo tg = L.rtris[t];
+        const TriGeo tg = lds_load(L.rtris + t);
         const int j = tg.j0 + (gi - L.scan[t]);
         int xl, xr;
         if (!row_span(tg, j, cam.W, xl, xr)) continue;
-        unsigned long long *row = L.road + (size_t)j * L.nw;
+        lptr<unsigned long long> row = L.road + (size_t)j * L.nw;
         const int w0 = xl >> 6, w1 = xr >> 6;
         for (int wd = w0; wd <= w1; ++wd) {
             const int lo = (wd == w0) ? (xl & 63) : 0;
             const int hi = (wd == w1) ? (xr & 63) : 63;
             const unsigned long long m = (hi == 63 ? ~0ull : ((1ull << (hi + 1)) - 1ull)) & (~0ull << lo);
-            atomicOr(&row[wd], m);
+            lds_or64(row + wd, m);
         }
     }
     __syncthreads();
@@ -587,17 +653,17 @@ __device__ void raster_tris(const Cam &cam, Lds &L, int n, int b0, int b1)
     const int total = block_scan(L, n);
     for (int gi = threadIdx.x; gi < total; gi += blockDim.x) {
         const int t = find_row_owner(L, n, gi);
-        const TriRec tr = L.tris[t];
+        const TriRec tr = lds_load(L.tris + t);
         const int j = max((int)tr.g.j0, b0) + (gi - L.scan[t]);
         int xl, xr;
         if (!row_span(tr.g, j, cam.W, xl, xr)) continue;
         const float dv = ((float)j + 0.5f) - cam.cy;
-        unsigned long long *row = L.zb + (size_t)(j - b0) * cam.W;
+        lptr<unsigned long long> row = L.zb + (size_t)(j - b0) * cam.W;
         for (int i = xl; i <= xr; ++i) {
             const float du = ((float)i + 0.5f) - cam.cx;
             const float invz = fmaf(tr.A, du, fmaf(tr.B, dv, tr.C));
             if (!(invz > 0.0f)) continue;
-            atomicMax(&row[i], ((unsigned long long)__float_as_uint(invz) << 32) | tr.keylo);
+            lds_max64(row + i, ((unsigned long long)__float_as_uint(invz) << 32) | tr.keylo);
         }
     }
     __syncthreads();
@@ -614,14 +680,14 @@ struct Sink {
 
 __device__ __forceinline__ void flush_tris(const Cam &cam, Lds &L, const Sink &K)
 {
-    raster_tris(cam, L, min(L.cnt[C_TRIS], L.cap), K.r0, K.r1);
+    raster_tris(cam, L, min(L.cnt[C_TRIS], L.tcap), K.r0, K.r1);
     if (threadIdx.x == 0) L.cnt[C_TRIS] = 0;
     __syncthreads();
 }
 
 __device__ __forceinline__ void flush_roads(const Cam &cam, Lds &L)
 {
-    raster_roads(cam, L, min(L.cnt[C_RTRIS], L.cap));
+    raster_roads(cam, L, min(L.cnt[C_RTRIS], L.rcap));
     if (threadIdx.x == 0) L.cnt[C_RTRIS] = 0;
     __syncthreads();
 }
@@ -632,8 +698,8 @@ __device__ __forceinline__ void flush_roads(const Cam &cam, Lds &L)
 // appends right after this call cannot change another wave's decision.
 __device__ __forceinline__ void make_room(const Cam &cam, Lds &L, const Sink &K, int need_r, int need_t)
 {
-    const bool fr = K.fast && L.cnt[C_RTRIS] + need_r > L.cap;
-    const bool ft = K.flush_tris && L.cnt[C_TRIS] + need_t > L.cap;
+    const bool fr = K.fast && L.cnt[C_RTRIS] + need_r > L.rcap;
+    const bool ft = K.flush_tris && L.cnt[C_TRIS] + need_t > L.tcap;
     __syncthreads();
     if (fr) flush_roads(cam, L);
     if (ft) flush_tris(cam, L, K);
@@ -651,33 +717,35 @@ __device__ __forceinline__ void append_wave(Lds &L, int which, bool v0, const Tr
     const int leader = __ffsll((long long)(b0 | b1)) - 1;
     int base = 0;
     if ((int)lane_id() == leader) {
-        base = atomicAdd(&L.cnt[which], n);
-        if (base + n > L.cap) L.cnt[C_OVF] = 1;
+        base = lds_add(L.cnt + which, n);
+        if (base + n > L.cap_of(which)) L.cnt[C_OVF] = 1;
     }
     base = __shfl(base, leader);
     const int p0 = base + __popcll(b0 & lt), p1 = base + n0 + __popcll(b1 & lt);
     if (which == C_RTRIS) {
-        if (v0 && p0 < L.cap) L.rtris[p0] = t0.g;
-        if (v1 && p1 < L.cap) L.rtris[p1] = t1.g;
+        if (v0 && p0 < L.rcap) lds_store(L.rtris + p0, t0.g);
+        if (v1 && p1 < L.rcap) lds_store(L.rtris + p1, t1.g);
     } else {
-        if (v0 && p0 < L.cap) L.tris[p0] = t0;
-        if (v1 && p1 < L.cap) L.tris[p1] = t1;
+        if (v0 && p0 < L.tcap) lds_store(L.tris + p0, t0);
+        if (v1 && p1 < L.tcap) lds_store(L.tris + p1, t1);
     }
 }
 
 __device__ __forceinline__ void append_one(Lds &L, int which, const TriRec &t)
 {
-    const int pos = atomicAdd(&L.cnt[which], 1);
-    if (pos < L.cap) {
-        if (which == C_RTRIS) L.rtris[pos] = t.g;
-        else L.tris[pos] = t;
+    const int pos = lds_add(L.cnt + which, 1);
+    if (pos < L.cap_of(which)) {
+        if (which == C_RTRIS) lds_store(L.rtris + pos, t.g);
+        else lds_store(L.tris + pos, t);
     } else {
         L.cnt[C_OVF] = 1;
     }
 }
 
 // Fast path for one live candidate polygon: cull, project and orient its two
-// triangles unless it needs the clipper (then `clip` is set).
+// triangles unless it needs the clipper (then `clip` is set).  PLANE: the
+// triangles need their depth plane and key (not for the rgb kernel's roads).
+template <bool PLANE>
 __device__ __forceinline__ void fast_poly(const Cam &cam, const Poly &P, const Sink &K, TriRec &t0, bool &v0,
                                           TriRec &t1, bool &v1, bool &clip)
 {
@@ -692,7 +760,7 @@ __device__ __forceinline__ void fast_poly(const Cam &cam, const Poly &P, const S
     for (int k = 0; k < 4; ++k) snap(cam, P.v[k], X[k], Y[k]);
     v0 = make_tri(cam, P.one_sided, X[0], Y[0], X[1], Y[1], X[2], Y[2], K.r0, K.r1, t0.g);
     v1 = make_tri(cam, P.one_sided, X[0], Y[0], X[2], Y[2], X[3], Y[3], K.r0, K.r1, t1.g);
-    if ((v0 || v1) && !(K.fast && !P.one_sided)) {
+    if (PLANE && (v0 || v1)) {
         const Plane pl = face_plane(cam, P.n, d);
         t0.A = pl.A; t0.B = pl.B; t0.C = pl.C; t0.keylo = P.keylo;
         t1.A = pl.A; t1.B = pl.B; t1.C = pl.C; t1.keylo = P.keylo;
@@ -760,8 +828,8 @@ __device__ __noinline__ void clip_poly(const Cam &cam, const Poly &P, const Sink
             t.A = pln.A; t.B = pln.B; t.C = pln.C; t.keylo = P.keylo;
             append_one(L, road ? C_RTRIS : C_TRIS, t);
             if (K.fast && !road) {
-                atomicMin(&L.cnt[C_BMIN], (int)t.g.j0);
-                atomicMax(&L.cnt[C_BMAX], (int)t.g.j1);
+                lds_min(L.cnt + C_BMIN, (int)t.g.j0);
+                lds_max(L.cnt + C_BMAX, (int)t.g.j1);
             }
         }
     }
@@ -775,15 +843,22 @@ __device__ __forceinline__ void build_code(const DevSim &s, const SceneRec &sc, 
     else build_road(s, sc, cam, -code - 1, P);
 }
 
-// One setup pass over boxes (kind 0) or road bins (kind 1).
-__device__ void setup_source(const DevSim &s, const SceneRec &sc, const Cam &cam, int ego, int kind,
-                             const Sink &K, Lds &L)
+// One setup pass over boxes (KIND 0) or road bins (KIND 1); FAST selects the
+// rgb kernel, where road triangles go to the road list.  Both are template
+// parameters so that each pass carries only the records it can emit.
+template <int KIND, int FAST>
+__device__ void setup_source(const DevSim &s, const SceneRec &sc, const Cam &cam, int ego, const Sink &K,
+                             Lds &L)
 {
+    constexpr int kind = KIND;
+    constexpr bool road = FAST && KIND == 1;     // triangles of this pass go to the road list
     const int B = blockDim.x, tid = threadIdx.x;
     const int n_units = kind == 0 ? sc.n_agents : sc.n_bins;
-    const bool can_flush = (kind == 1 && K.fast) || K.flush_tris;
-    // with flushing, a round may add at most 2 triangles per lane; keep it below the capacity
-    const int per_round = can_flush ? min(B, max(64, (L.cap / 2) & ~63)) : B;
+    const bool can_flush = road || K.flush_tris;
+    // the list that may be flushed during this pass, and its capacity; with
+    // flushing a round adds at most 2 triangles per lane, so keep it below half
+    const int fcap = road ? L.rcap : L.tcap;
+    const int per_round = can_flush ? max(1, min(B, fcap / 2)) : B;
     for (int u0 = 0; u0 < n_units; u0 += B) {
         // ---- cull units, compact the survivors
         const int u = u0 + tid;
@@ -803,7 +878,7 @@ __device__ void setup_source(const DevSim &s, const SceneRec &sc, const Cam &cam
             int base = 0;
             if (nk > 0) {
                 const int leader = __ffsll((long long)bm) - 1;
-                if ((int)lane_id() == leader) base = atomicAdd(&L.cnt[C_SURV], nk);
+                if ((int)lane_id() == leader) base = lds_add(L.cnt + C_SURV, nk);
                 base = __shfl(base, leader);
             }
             if (keep) L.surv[base + __popcll(bm & ((1ull << lane_id()) - 1ull))] = u;
@@ -835,10 +910,9 @@ __device__ void setup_source(const DevSim &s, const SceneRec &sc, const Cam &cam
             }
             TriRec t0, t1;
             bool v0 = false, v1 = false, clip = false;
-            if (live) fast_poly(cam, P, K, t0, v0, t1, v1, clip);
-            const bool road = K.fast && kind == 1;
+            if (live) fast_poly<!road>(cam, P, K, t0, v0, t1, v1, clip);
             if (clip) {
-                const int q = atomicAdd(&L.cnt[C_CLIPQ], 1);
+                const int q = lds_add(L.cnt + C_CLIPQ, 1);
                 L.clipq[q] = code;
             }
             if (can_flush) {
@@ -846,23 +920,23 @@ __device__ void setup_source(const DevSim &s, const SceneRec &sc, const Cam &cam
                 const int nr = __popcll(__ballot(v0 && road)) + __popcll(__ballot(v1 && road));
                 const int nt = __popcll(__ballot(v0 && !road)) + __popcll(__ballot(v1 && !road));
                 if (lane_id() == 0 && (nr | nt)) {
-                    atomicAdd(&L.cnt[C_PR0 + par], nr);
-                    atomicAdd(&L.cnt[C_PT0 + par], nt);
+                    lds_add(L.cnt + C_PR0 + par, nr);
+                    lds_add(L.cnt + C_PT0 + par, nt);
                 }
                 __syncthreads();
                 make_room(cam, L, K, L.cnt[C_PR0 + par], L.cnt[C_PT0 + par]);
                 if (tid == 0) { L.cnt[C_PR0 + (par ^ 1)] = 0; L.cnt[C_PT0 + (par ^ 1)] = 0; }
             }
-            append_wave(L, C_RTRIS, v0 && road, t0, v1 && road, t1);
-            append_wave(L, C_TRIS, v0 && !road, t0, v1 && !road, t1);
-            if (K.fast && !road) {
-                if (v0) { atomicMin(&L.cnt[C_BMIN], (int)t0.g.j0); atomicMax(&L.cnt[C_BMAX], (int)t0.g.j1); }
-                if (v1) { atomicMin(&L.cnt[C_BMIN], (int)t1.g.j0); atomicMax(&L.cnt[C_BMAX], (int)t1.g.j1); }
+            if (road) append_wave(L, C_RTRIS, v0, t0, v1, t1);
+            else append_wave(L, C_TRIS, v0, t0, v1, t1);
+            if (FAST && !road) {
+                if (v0) { lds_min(L.cnt + C_BMIN, (int)t0.g.j0); lds_max(L.cnt + C_BMAX, (int)t0.g.j1); }
+                if (v1) { lds_min(L.cnt + C_BMIN, (int)t1.g.j0); lds_max(L.cnt + C_BMAX, (int)t1.g.j1); }
             }
             __syncthreads();
             const int nq = L.cnt[C_CLIPQ];
             // the clipper may emit up to kMaxTrisPerCand triangles per candidate
-            const int chunk = can_flush ? max(1, L.cap / kMaxTrisPerCand) : B;
+            const int chunk = can_flush ? max(1, fcap / kMaxTrisPerCand) : B;
             for (int q0 = 0; q0 < nq; q0 += chunk) {
                 const int qn = min(chunk, nq - q0);
                 if (can_flush) make_room(cam, L, K, qn * kMaxTrisPerCand, qn * kMaxTrisPerCand);
@@ -901,7 +975,7 @@ __device__ void resolve_fast(const DevSim &s, const Cam &cam, Lds &L, uint8_t *r
     const int64_t img = view * (int64_t)W * cam.H;
     const uint32_t road_rgb = L.pal[s.road_color0];
     const uint32_t bg_rgb = L.pal[0];
-    auto color_of = [&](bool road, float rz, const unsigned long long *kp, int m) -> uint32_t {
+    auto color_of = [&](bool road, float rz, lptr<unsigned long long> kp, int m) -> uint32_t {
         if (KEYS) {
             const unsigned long long kb = kp[m];
             const bool box = kb != 0ull && (!road || (uint32_t)(kb >> 32) >= __float_as_uint(rz));
@@ -920,7 +994,7 @@ __device__ void resolve_fast(const DevSim &s, const Cam &cam, Lds &L, uint8_t *r
             const float rz = fmaf(cam.road.B, dv, cam.road.C);
             const bool rowok = rz > 0.0f;
             const uint32_t bits = rowok ? (uint32_t)(L.road[(size_t)j * L.nw + (i >> 6)] >> (i & 63)) & 0xFu : 0u;
-            const unsigned long long *kp = KEYS ? L.zb + (size_t)(j - zb0) * W + i : nullptr;
+            lptr<unsigned long long> kp = L.zb + (KEYS ? (size_t)(j - zb0) * W + i : 0);
             const uint32_t c0 = color_of(bits & 1u, rz, kp, 0), c1 = color_of(bits & 2u, rz, kp, 1);
             const uint32_t c2 = color_of(bits & 4u, rz, kp, 2), c3 = color_of(bits & 8u, rz, kp, 3);
             uint32_t *out = reinterpret_cast<uint32_t *>(rgb + 3 * (img + (int64_t)j * W + i));
@@ -935,7 +1009,7 @@ __device__ void resolve_fast(const DevSim &s, const Cam &cam, Lds &L, uint8_t *r
             const float dv = ((float)j + 0.5f) - cam.cy;
             const float rz = fmaf(cam.road.B, dv, cam.road.C);
             const bool road = rz > 0.0f && ((L.road[(size_t)j * L.nw + (i >> 6)] >> (i & 63)) & 1ull);
-            const unsigned long long *kp = KEYS ? L.zb + (size_t)(j - zb0) * W + i : nullptr;
+            lptr<unsigned long long> kp = L.zb + (KEYS ? (size_t)(j - zb0) * W + i : 0);
             const uint32_t c = color_of(road, rz, kp, 0);
             uint8_t *dst = rgb + 3 * (img + (int64_t)j * W + i);
             dst[0] = (uint8_t)c;
@@ -993,11 +1067,11 @@ __device__ void render_view(const DevSim &s, const RenderOut &o, const LaunchCfg
     K.flush_tris = 0;
     K.r0 = 0;
     K.r1 = H;
-    setup_source(s, sc, cam, ego, 0, K, L);           // boxes
-    setup_source(s, sc, cam, ego, 1, K, L);           // road strips
+    setup_source<0, FAST>(s, sc, cam, ego, K, L);           // boxes
+    setup_source<1, FAST>(s, sc, cam, ego, K, L);           // road strips
     if (FAST) flush_roads(cam, L);
     const bool overflow = L.cnt[C_OVF] != 0;
-    const int ntri = min(L.cnt[C_TRIS], L.cap);
+    const int ntri = min(L.cnt[C_TRIS], L.tcap);
     // rows that need the key band: every row for the general kernel; for the
     // rgb kernel the rows touched by box triangles (all rows after an overflow)
     int kr0 = 0, kr1 = H;
@@ -1026,8 +1100,8 @@ __device__ void render_view(const DevSim &s, const RenderOut &o, const LaunchCfg
             KB.flush_tris = 1;
             KB.r0 = b0;
             KB.r1 = b1;
-            setup_source(s, sc, cam, ego, 0, KB, L);
-            if (!FAST) setup_source(s, sc, cam, ego, 1, KB, L);
+            setup_source<0, FAST>(s, sc, cam, ego, KB, L);
+            if (!FAST) setup_source<1, FAST>(s, sc, cam, ego, KB, L);
             flush_tris(cam, L, KB);
         }
         if (FAST) resolve_fast<true>(s, cam, L, o.rgb, view, b0, b1, b0);
@@ -1036,33 +1110,36 @@ __device__ void render_view(const DevSim &s, const RenderOut &o, const LaunchCfg
     }
 }
 
-template <int FAST>
-__global__ void k_render(DevSim s, RenderOut o, LaunchCfg lc, int persistent, int view_begin)
+// BLOCK is the launch's block size: the bound lets the register allocator
+// use what a BLOCK-thread workgroup can have instead of assuming 1024 threads.
+template <int FAST, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_render(DevSim s, RenderOut o, LaunchCfg lc, int persistent,
+                                                  int view_begin)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     Lds L;
-    L.cap = lc.batch_tris;
+    list_caps(FAST, lc.batch_tris, L.tcap, L.rcap);
     L.nw = (s.width + 63) >> 6;
     size_t off = 0;
-    L.tris = reinterpret_cast<TriRec *>(smem + off);
-    off += sizeof(TriRec) * (size_t)L.cap;
-    L.rtris = reinterpret_cast<TriGeo *>(smem + off);
-    off += FAST ? sizeof(TriGeo) * (size_t)L.cap : 0;
-    L.zb = reinterpret_cast<unsigned long long *>(smem + off);
+    L.tris = (lptr<TriRec>)(smem + off);
+    off += sizeof(TriRec) * (size_t)L.tcap;
+    L.rtris = (lptr<TriGeo>)(smem + off);
+    off += sizeof(TriGeo) * (size_t)L.rcap;
+    L.zb = (lptr<unsigned long long>)(smem + off);
     off += 8u * (size_t)lc.band_rows * s.width;
-    L.road = reinterpret_cast<unsigned long long *>(smem + off);
+    L.road = (lptr<unsigned long long>)(smem + off);
     off += FAST ? 8u * (size_t)s.height * L.nw : 0;
-    L.scan = reinterpret_cast<int32_t *>(smem + off);
-    off += 4u * (size_t)(L.cap + 4);
-    L.surv = reinterpret_cast<int32_t *>(smem + off);
+    L.scan = (lptr<int32_t>)(smem + off);
+    off += 4u * (size_t)(max(L.tcap, L.rcap) + 4);
+    L.surv = (lptr<int32_t>)(smem + off);
     off += 4u * blockDim.x;
-    L.clipq = reinterpret_cast<int32_t *>(smem + off);
+    L.clipq = (lptr<int32_t>)(smem + off);
     off += 4u * blockDim.x;
-    L.cnt = reinterpret_cast<int32_t *>(smem + off);
+    L.cnt = (lptr<int32_t>)(smem + off);
     off += 4u * 16;
-    L.wsum = reinterpret_cast<int32_t *>(smem + off);
+    L.wsum = (lptr<int32_t>)(smem + off);
     off += 4u * 16;
-    L.pal = reinterpret_cast<uint32_t *>(smem + off);
+    L.pal = (lptr<uint32_t>)(smem + off);
     for (int p = threadIdx.x; p < 256; p += blockDim.x)
         L.pal[p] = (uint32_t)s.palette[3 * p] | ((uint32_t)s.palette[3 * p + 1] << 8) |
                    ((uint32_t)s.palette[3 * p + 2] << 16);
@@ -1099,10 +1176,13 @@ __global__ void k_render(DevSim s, RenderOut o, LaunchCfg lc, int persistent, in
 
 size_t render_lds_bytes(const DevSim &s, const LaunchCfg &c, int fast)
 {
+    int tcap, rcap;
+    list_caps(fast, c.batch_tris, tcap, rcap);
     const size_t nw = (size_t)(s.width + 63) / 64;
-    size_t b = sizeof(TriRec) * (size_t)c.batch_tris + 8u * (size_t)c.band_rows * s.width +
-               4u * (size_t)(c.batch_tris + 4) + 8u * (size_t)c.block_threads + 64u + 64u + 1024u;
-    if (fast) b += sizeof(TriGeo) * (size_t)c.batch_tris + 8u * (size_t)s.height * nw;
+    size_t b = sizeof(TriRec) * (size_t)tcap + sizeof(TriGeo) * (size_t)rcap +
+               8u * (size_t)c.band_rows * s.width + 4u * (size_t)(max(tcap, rcap) + 4) +
+               8u * (size_t)c.block_threads + 64u + 64u + 1024u;
+    if (fast) b += 8u * (size_t)s.height * nw;
     return b;
 }
 
@@ -1128,12 +1208,22 @@ hipError_t launch_render(const DevSim &s, const RenderOut &o, const LaunchCfg &c
 {
     if (grid <= 0) return hipSuccess;
     const size_t lds = render_lds_bytes(s, c, fast);
-    if (fast)
-        hipLaunchKernelGGL(k_render<1>, dim3(grid), dim3(c.block_threads), lds, st, s, o, c, persistent,
-                           view_begin);
-    else
-        hipLaunchKernelGGL(k_render<0>, dim3(grid), dim3(c.block_threads), lds, st, s, o, c, persistent,
-                           view_begin);
+#define GP_LAUNCH(F, B)                                                                                 \
+    hipLaunchKernelGGL((k_render<F, B>), dim3(grid), dim3(B), lds, st, s, o, c, persistent, view_begin)
+    switch (c.block_threads) {
+    case 256:
+        if (fast) GP_LAUNCH(1, 256); else GP_LAUNCH(0, 256);
+        break;
+    case 512:
+        if (fast) GP_LAUNCH(1, 512); else GP_LAUNCH(0, 512);
+        break;
+    case 1024:
+        if (fast) GP_LAUNCH(1, 1024); else GP_LAUNCH(0, 1024);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef GP_LAUNCH
     return hipGetLastError();
 }
 
