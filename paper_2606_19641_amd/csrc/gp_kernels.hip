@@ -424,7 +424,37 @@ __device__ __forceinline__ int64_t floor_div64(int64_t a, int64_t b)   // b > 0
 // Edge k runs from vertex k to k+1; E_k(i) = P_k - 256 dY_k i with
 // P_k = dX_k (Sy - Y_k) + dY_k (X_k - 128); a sample is inside iff every
 // E_k >= t_k, t_k = 0 on top (dY == 0, dX > 0) and left (dY < 0) edges, else 1.
-__device__ bool row_span(const TriGeo &t, int j, int W, int &xl_out, int &xr_out)
+// The same span in exact int64 arithmetic, for triangles with a coordinate
+// of 2^25 subpixels or more (guard-band geometry).
+__device__ __forceinline__ bool row_span_int64(const TriGeo &t, int j, int W, int &xl_out, int &xr_out)
+{
+    const int32_t X[3] = {t.X0, t.X1, t.X2}, Y[3] = {t.Y0, t.Y1, t.Y2};
+    int xl = 0, xr = W - 1;
+    const int64_t Sy = 256 * (int64_t)j + 128;
+    for (int k = 0; k < 3; ++k) {
+        const int k1 = (k == 2) ? 0 : k + 1;
+        const int64_t dX = (int64_t)X[k1] - X[k], dY = (int64_t)Y[k1] - Y[k];
+        const int64_t tk = (dY < 0 || (dY == 0 && dX > 0)) ? 0 : 1;
+        const int64_t P = dX * (Sy - Y[k]) + dY * ((int64_t)X[k] - 128);
+        if (dY == 0) {
+            if (P < tk) return false;
+            continue;
+        }
+        if (dY > 0) {
+            const int64_t ic = floor_div64(P - tk, 256 * dY);
+            xr = (int)min((int64_t)xr, max(ic, (int64_t)-1));
+        } else {
+            // i >= (tk - P) / (256 |dY|), rounded up: ceil(-x) = -floor(x)
+            const int64_t ic = -floor_div64(P - tk, 256 * (-dY));
+            xl = (int)max((int64_t)xl, min(ic, (int64_t)W));
+        }
+    }
+    xl_out = xl;
+    xr_out = xr;
+    return xl <= xr;
+}
+
+__device__ __forceinline__ bool row_span(const TriGeo &t, int j, int W, int &xl_out, int &xr_out)
 {
     const int32_t X[3] = {t.X0, t.X1, t.X2}, Y[3] = {t.Y0, t.Y1, t.Y2};
     int xl = 0, xr = W - 1;
@@ -456,26 +486,7 @@ __device__ bool row_span(const TriGeo &t, int j, int W, int &xl_out, int &xr_out
             }
         }
     } else {
-        const int64_t Sy = 256 * (int64_t)j + 128;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const int k1 = (k == 2) ? 0 : k + 1;
-            const int64_t dX = (int64_t)X[k1] - X[k], dY = (int64_t)Y[k1] - Y[k];
-            const int64_t tk = (dY < 0 || (dY == 0 && dX > 0)) ? 0 : 1;
-            const int64_t P = dX * (Sy - Y[k]) + dY * ((int64_t)X[k] - 128);
-            if (dY == 0) {
-                if (P < tk) return false;
-                continue;
-            }
-            if (dY > 0) {
-                const int64_t ic = floor_div64(P - tk, 256 * dY);
-                xr = (int)min((int64_t)xr, max(ic, (int64_t)-1));
-            } else {
-                // i >= (tk - P) / (256 |dY|), rounded up: ceil(-x) = -floor(x)
-                const int64_t ic = -floor_div64(P - tk, 256 * (-dY));
-                xl = (int)max((int64_t)xl, min(ic, (int64_t)W));
-            }
-        }
+        return row_span_int64(t, j, W, xl_out, xr_out);
     }
     xl_out = xl;
     xr_out = xr;
@@ -617,7 +628,7 @@ __device__ __forceinline__ int find_row_owner(const Lds &L, int n, int g)
 }
 
 // Road strips of the rgb kernel: OR every covered sample into the row bitmask.
-__device__ void raster_roads(const Cam &cam, Lds &L, int n)
+__device__ __noinline__ void raster_roads(Lds L, int W, int n)
 {
     if (n <= 0) return;
     for (int t = threadIdx.x; t < n; t += blockDim.x) L.scan[t] = L.rtris[t].j1 - L.rtris[t].j0 + 1;
@@ -628,7 +639,7 @@ __device__ void raster_roads(const Cam &cam, Lds &L, int n)
         const TriGeo tg = lds_load(L.rtris + t);
         const int j = tg.j0 + (gi - L.scan[t]);
         int xl, xr;
-        if (!row_span(tg, j, cam.W, xl, xr)) continue;
+        if (!row_span(tg, j, W, xl, xr)) continue;
         lptr<unsigned long long> row = L.road + (size_t)j * L.nw;
         const int w0 = xl >> 6, w1 = xr >> 6;
         for (int wd = w0; wd <= w1; ++wd) {
@@ -642,7 +653,7 @@ __device__ void raster_roads(const Cam &cam, Lds &L, int n)
 }
 
 // Fragments of listed triangles in rows [b0, b1) folded into the key band.
-__device__ void raster_tris(const Cam &cam, Lds &L, int n, int b0, int b1)
+__device__ __noinline__ void raster_tris(Lds L, int W, float cx, float cy, int n, int b0, int b1)
 {
     if (n <= 0) return;
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
@@ -656,11 +667,11 @@ __device__ void raster_tris(const Cam &cam, Lds &L, int n, int b0, int b1)
         const TriRec tr = lds_load(L.tris + t);
         const int j = max((int)tr.g.j0, b0) + (gi - L.scan[t]);
         int xl, xr;
-        if (!row_span(tr.g, j, cam.W, xl, xr)) continue;
-        const float dv = ((float)j + 0.5f) - cam.cy;
-        lptr<unsigned long long> row = L.zb + (size_t)(j - b0) * cam.W;
+        if (!row_span(tr.g, j, W, xl, xr)) continue;
+        const float dv = ((float)j + 0.5f) - cy;
+        lptr<unsigned long long> row = L.zb + (size_t)(j - b0) * W;
         for (int i = xl; i <= xr; ++i) {
-            const float du = ((float)i + 0.5f) - cam.cx;
+            const float du = ((float)i + 0.5f) - cx;
             const float invz = fmaf(tr.A, du, fmaf(tr.B, dv, tr.C));
             if (!(invz > 0.0f)) continue;
             lds_max64(row + i, ((unsigned long long)__float_as_uint(invz) << 32) | tr.keylo);
@@ -680,14 +691,14 @@ struct Sink {
 
 __device__ __forceinline__ void flush_tris(const Cam &cam, Lds &L, const Sink &K)
 {
-    raster_tris(cam, L, min(L.cnt[C_TRIS], L.tcap), K.r0, K.r1);
+    raster_tris(L, cam.W, cam.cx, cam.cy, min(L.cnt[C_TRIS], L.tcap), K.r0, K.r1);
     if (threadIdx.x == 0) L.cnt[C_TRIS] = 0;
     __syncthreads();
 }
 
 __device__ __forceinline__ void flush_roads(const Cam &cam, Lds &L)
 {
-    raster_roads(cam, L, min(L.cnt[C_RTRIS], L.rcap));
+    raster_roads(L, cam.W, min(L.cnt[C_RTRIS], L.rcap));
     if (threadIdx.x == 0) L.cnt[C_RTRIS] = 0;
     __syncthreads();
 }
@@ -1089,7 +1100,7 @@ __device__ void render_view(const DevSim &s, const RenderOut &o, const LaunchCfg
         clear_band(L, (b1 - b0) * W);
         __syncthreads();
         if (!overflow) {
-            raster_tris(cam, L, ntri, b0, b1);
+            raster_tris(L, cam.W, cam.cx, cam.cy, ntri, b0, b1);
         } else {
             // the list did not hold every triangle: redo this band's setup
             // with flushes into the band

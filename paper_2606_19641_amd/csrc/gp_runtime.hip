@@ -454,11 +454,11 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
     e = gp::launch_cs(D, hs);
     if (e != hipSuccess) { delete sim; return hip_fail(e, "heading cosines"); }
 
-    // default launch: persistent queue, a 16 KB band buffer
+    // default launch: persistent queue, a band buffer of at most 32 KB
     gp_launch l{};
     l.sched = GP_SCHED_PERSISTENT;
     l.band_rows = 64;
-    while (l.band_rows > 8 && 8LL * l.band_rows * cfg->width > 16384) l.band_rows /= 2;
+    while (l.band_rows > 8 && 8LL * l.band_rows * cfg->width > 32768) l.band_rows /= 2;
     l.batch_tris = 512;
     l.block_threads = 256;
     l.blocks_per_cu = 2;
