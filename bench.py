@@ -26,6 +26,39 @@ if ROOT not in sys.path:
 
 METRIC = "agent-views/sec at 128×128 RGB (batched vs plain, same GPU); p99 step latency"
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 256 << 20
+COUNTERS = os.path.join(ROOT, "profiles", "k_render_rgb_uniform128_counters.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2606_19641_amd", "csrc", "gp_kernels.hip")
+
+
+def kernel_source_sha() -> str:
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_counters(workload_name: str, launch: dict):
+    """HBM traffic and VALU busy of the render kernel from the committed rocprofv3
+    counter summary, or None when that summary was taken on another kernel source,
+    workload or launch setting."""
+    if not os.path.exists(COUNTERS):
+        return None
+    kv = {}
+    with open(COUNTERS) as f:
+        for line in f:
+            if ":" in line and not line.startswith((" ", "#", "\t")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    try:
+        same = (kv["kernel_source_sha256"] == kernel_source_sha() and kv["workload"] == workload_name
+                and json.loads(kv["launch"]) == launch)
+        if not same:
+            return None
+        return {"traffic": float(kv["traffic_bytes_per_launch"]),
+                "valu_busy_pct": float(kv["valu_busy_pct"]),
+                "lds_bank_conflict_pct": float(kv["lds_bank_conflict_pct"])}
+    except (KeyError, ValueError):
+        return None
 
 
 def _workload(args):
@@ -63,26 +96,20 @@ def step_bytes(w) -> int:
     return 64 * w.n_agents
 
 
-def cpu_baseline(w, budget_s: float):
-    """The oracle on the host cores: step + render of a bounded sample of views."""
+def _oracle_rate(w, budget_s: float, threads: int):
+    """Views/s of the oracle over whole steps of the workload (step, then every
+    view), stopped when the budget is spent (a step may be cut short)."""
     import oracle
     from paper_2606_19641_amd import scenegen as g
-    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
-    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
-        threads = min(threads, int(os.environ["OMP_NUM_THREADS"]))
-    threads = max(1, threads)
     cams = len(w.camera.cam_dirs)
     pal = g.default_palette()
     st = np.concatenate([s.agent_state for s in w.scenes])
-    dm = np.concatenate([s.agent_dims for s in w.scenes])
-    nviews = w.n_views
     chunk = max(threads * 4, 16)
     done, steps = 0, 0
     t0 = time.perf_counter()
-    # whole steps of the workload (step, then every view) until the budget is spent;
-    # a step is cut short when the budget runs out mid-way
     while time.perf_counter() - t0 < budget_s:
-        st, _ = oracle.step(st, dm, g.batch_actions(w.seed, steps, w.scenes), 0.1)
+        st, _ = oracle.step(st, np.concatenate([s.agent_dims for s in w.scenes]),
+                            g.batch_actions(w.seed, steps, w.scenes), 0.1)
         scenes, o = [], 0
         for s in w.scenes:
             scenes.append(g.Scene(agent_state=st[o:o + s.n_agents], agent_dims=s.agent_dims,
@@ -95,10 +122,22 @@ def cpu_baseline(w, budget_s: float):
             if time.perf_counter() - t0 >= budget_s:
                 break
         steps += 1
-    dt = time.perf_counter() - t0
+    return done, steps, time.perf_counter() - t0
+
+
+def cpu_baseline(w, budget_s: float):
+    """The oracle on the host cores (all of them, then one) on a bounded sample."""
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+        threads = min(threads, int(os.environ["OMP_NUM_THREADS"]))
+    threads = max(1, threads)
+    done, steps, dt = _oracle_rate(w, budget_s, threads)
+    d1, _, t1 = _oracle_rate(w, max(1.0, budget_s / 4), 1)
     return {"value": done / dt, "unit": "agent-views/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} views over {steps} step(s) of the same workload ({nviews} views per "
-                      f"step; agent step + every view; {threads} threads, {dt:.1f} s)"}
+            "single_thread_value": d1 / t1,
+            "sample": f"{done} views over {steps} step(s) of the same workload ({w.n_views} views per "
+                      f"step; agent step + every view; {threads} threads, {dt:.1f} s); single thread: "
+                      f"{d1} views in {t1:.1f} s"}
 
 
 def main():
@@ -187,15 +226,17 @@ def main():
         sim.set_launch(sched=gp.SCHED_PERSISTENT)
 
     if args.copy_calibration:
-        src = torch.empty(256 << 20, dtype=torch.uint8, device=dev).fill_(1)
+        # a plain streaming kernel of known size: 256 MiB read, 256 MiB written
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
 
     rb = render_bytes(w)
     achieved = rb / (render_ms * 1e-3) / 1e9
+    meas = measured_counters(args.workload if args.workload != "sweep" else f"sweep{args.res}", launch)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, args.cpu_seconds)
@@ -222,8 +263,10 @@ def main():
         "p99_step_ms": float(np.percentile(lat_ms, 99)),
         "render_kernel_ms": render_ms,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_render", "bytes_per_launch": rb},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": meas["traffic"] if meas else None,
+                     "kernel": "k_render", "bytes_per_launch": rb,
+                     "valu_busy_pct": meas["valu_busy_pct"] if meas else None,
+                     "lds_bank_conflict_pct": meas["lds_bank_conflict_pct"] if meas else None},
         "cpu_baseline": cpu,
         "paper_context": "~50k agent steps/s from pixels on 1 NVIDIA A100L (workload not stated)",
     }

@@ -778,71 +778,109 @@ __device__ __forceinline__ void fast_poly(const Cam &cam, const Poly &P, const S
     }
 }
 
-// Sutherland-Hodgman against one plane.  Walk the vertices; keep an inside
-// vertex; if the edge to the next vertex crosses the plane emit the crossing,
-// computed from the inside end towards the outside end.  Returns the output
-// count, or -1 when more than kMaxVerts vertices would result (only a
-// self-intersecting input quad can do that; it is dropped).
+// Sutherland-Hodgman clipping of one candidate by a whole wave, in registers.
+// Lane k holds vertex k of the current polygon.  Against each plane, in the
+// order near, far, guard band left / right / top / bottom, the edge from
+// vertex k to vertex k+1 (cyclically) contributes vertex k when it is inside
+// and then the crossing point when the edge crosses the plane; the crossing
+// is computed from the inside end towards the outside end.  The outputs are
+// ordered by k, vertex before crossing, exactly as a sequential walk emits
+// them; output p is fetched by lane p from the lane that produced it.  A
+// polygon that would need more than kMaxVerts vertices (only a
+// self-intersecting input quad can) is dropped.
 constexpr int kMaxVerts = 12;
 constexpr int kMaxTrisPerCand = kMaxVerts - 2;
 
-__device__ int clip_one(int plane, const Cam &c, const V3 *in, int n, V3 *out)
+// the low 16 bits of x moved to the even bit positions
+__device__ __forceinline__ uint32_t spread_bits(uint32_t x)
 {
-    int m = 0;
-    for (int i = 0; i < n; ++i) {
-        const V3 a = in[i];
-        const V3 b = in[(i + 1 == n) ? 0 : i + 1];
-        const float da = plane_dist(plane, c, a), db = plane_dist(plane, c, b);
-        const bool ia = da >= 0.0f, ib = db >= 0.0f;
-        if (ia) {
-            if (m == kMaxVerts) return -1;
-            out[m++] = a;
-        }
-        if (ia != ib) {
-            if (m == kMaxVerts) return -1;
-            const V3 pin = ia ? a : b, pout = ia ? b : a;
-            const float din = ia ? da : db, dout = ia ? db : da;
-            const float t = din / (din - dout);
-            V3 r;
-            r.x = fmaf(t, pout.x - pin.x, pin.x);
-            r.y = fmaf(t, pout.y - pin.y, pin.y);
-            r.z = fmaf(t, pout.z - pin.z, pin.z);
-            if (plane == 0) r.z = c.zn;
-            if (plane == 1) r.z = c.zf;
-            out[m++] = r;
-        }
-    }
-    return m;
+    x &= 0xFFFFu;
+    x = (x | (x << 8)) & 0x00FF00FFu;
+    x = (x | (x << 4)) & 0x0F0F0F0Fu;
+    x = (x | (x << 2)) & 0x33333333u;
+    x = (x | (x << 1)) & 0x55555555u;
+    return x;
 }
 
-// Slow path: clip, project and emit the fan of one candidate.
-__device__ __noinline__ void clip_poly(const Cam &cam, const Poly &P, const Sink &K, Lds &L)
+// Component-wise choice; a conditional expression on whole records would go
+// through memory.
+__device__ __forceinline__ V3 sel_v3(bool c, const V3 &a, const V3 &b)
+{
+    V3 r;
+    r.x = c ? a.x : b.x;
+    r.y = c ? a.y : b.y;
+    r.z = c ? a.z : b.z;
+    return r;
+}
+
+__device__ __forceinline__ V3 shfl_v3(const V3 &v, int src)
+{
+    V3 r;
+    r.x = __shfl(v.x, src);
+    r.y = __shfl(v.y, src);
+    r.z = __shfl(v.z, src);
+    return r;
+}
+
+// Every lane of the wave calls this with the same candidate.
+__device__ __forceinline__ void clip_wave(const Cam &cam, const Poly &P, const Sink &K, Lds &L)
 {
     const float d = plane_d(P.n, P.v[0]);
     if (P.one_sided && !(d < 0.0f)) return;
-    V3 a[kMaxVerts], b[kMaxVerts];
+    const int lane = (int)lane_id();
+    const int l4 = lane & 3;
+    V3 v = sel_v3(l4 == 0, P.v[0], sel_v3(l4 == 1, P.v[1], sel_v3(l4 == 2, P.v[2], P.v[3])));
     int n = 4;
-    for (int k = 0; k < 4; ++k) a[k] = P.v[k];
-    for (int pl = 0; pl < 6 && n > 0; ++pl) {
-        n = clip_one(pl, cam, a, n, b);
-        if (n < 0) return;
-        for (int k = 0; k < n; ++k) a[k] = b[k];
+    for (int pl = 0; pl < 6; ++pl) {
+        const V3 b = shfl_v3(v, lane + 1 >= n ? 0 : lane + 1);
+        const float da = plane_dist(pl, cam, v), db = plane_dist(pl, cam, b);
+        const bool act = lane < n;
+        const bool ia = da >= 0.0f, ib = db >= 0.0f;
+        const bool e0 = act && ia, e1 = act && (ia != ib);
+        V3 r = v;
+        if (e1) {
+            const V3 pin = sel_v3(ia, v, b), pout = sel_v3(ia, b, v);
+            const float din = ia ? da : db, dout = ia ? db : da;
+            const float t = din / (din - dout);
+            r.x = fmaf(t, pout.x - pin.x, pin.x);
+            r.y = fmaf(t, pout.y - pin.y, pin.y);
+            r.z = fmaf(t, pout.z - pin.z, pin.z);
+            if (pl == 0) r.z = cam.zn;
+            if (pl == 1) r.z = cam.zf;
+        }
+        const uint32_t m0 = (uint32_t)__ballot(e0), m1 = (uint32_t)__ballot(e1);   // lanes < n <= 12
+        const int total = __popc(m0) + __popc(m1);
+        if (total == 0 || total > kMaxVerts) return;
+        // bit 2k: vertex of lane k, bit 2k+1: crossing of lane k; output p is the
+        // (p+1)-th set bit
+        uint32_t M = spread_bits(m0) | (spread_bits(m1) << 1);
+        const int drop = min(lane, total - 1);
+        for (int k = 0; k < drop; ++k) M &= M - 1u;
+        const int bit = __ffs(M) - 1;
+        const int src = bit >> 1;
+        const V3 fv = shfl_v3(v, src), fr = shfl_v3(r, src);
+        v = sel_v3(bit & 1, fr, fv);
+        n = total;
     }
     if (n < 3) return;
     const Plane pln = face_plane(cam, P.n, d);
     const bool road = K.fast && !P.one_sided;
-    int32_t X[kMaxVerts], Y[kMaxVerts];
-    for (int k = 0; k < n; ++k) snap(cam, a[k], X[k], Y[k]);
-    for (int k = 1; k + 1 < n; ++k) {
-        TriRec t;
-        if (make_tri(cam, P.one_sided, X[0], Y[0], X[k], Y[k], X[k + 1], Y[k + 1], K.r0, K.r1, t.g)) {
-            t.A = pln.A; t.B = pln.B; t.C = pln.C; t.keylo = P.keylo;
-            append_one(L, road ? C_RTRIS : C_TRIS, t);
-            if (K.fast && !road) {
-                lds_min(L.cnt + C_BMIN, (int)t.g.j0);
-                lds_max(L.cnt + C_BMAX, (int)t.g.j1);
-            }
-        }
+    int32_t X, Y;
+    snap(cam, v, X, Y);
+    const int32_t X0 = __shfl(X, 0), Y0 = __shfl(Y, 0);
+    const int nx = lane + 1 < n ? lane + 1 : 0;
+    const int32_t X2 = __shfl(X, nx), Y2 = __shfl(Y, nx);
+    // fan triangle (0, k, k+1) on lane k
+    TriRec t;
+    bool ok = false;
+    if (lane >= 1 && lane + 1 < n) {
+        ok = make_tri(cam, P.one_sided, X0, Y0, X, Y, X2, Y2, K.r0, K.r1, t.g);
+        t.A = pln.A; t.B = pln.B; t.C = pln.C; t.keylo = P.keylo;
+    }
+    append_wave(L, road ? C_RTRIS : C_TRIS, ok, t, false, t);
+    if (K.fast && !road && ok) {
+        lds_min(L.cnt + C_BMIN, (int)t.g.j0);
+        lds_max(L.cnt + C_BMAX, (int)t.g.j1);
     }
 }
 
@@ -948,13 +986,14 @@ __device__ void setup_source(const DevSim &s, const SceneRec &sc, const Cam &cam
             const int nq = L.cnt[C_CLIPQ];
             // the clipper may emit up to kMaxTrisPerCand triangles per candidate
             const int chunk = can_flush ? max(1, fcap / kMaxTrisPerCand) : B;
+            // one wave per queued candidate
             for (int q0 = 0; q0 < nq; q0 += chunk) {
                 const int qn = min(chunk, nq - q0);
                 if (can_flush) make_room(cam, L, K, qn * kMaxTrisPerCand, qn * kMaxTrisPerCand);
-                for (int q = q0 + tid; q < q0 + qn; q += B) {
+                for (int q = q0 + (tid >> 6); q < q0 + qn; q += B >> 6) {
                     Poly Q;
                     build_code(s, sc, cam, L.clipq[q], Q);
-                    clip_poly(cam, Q, K, L);
+                    clip_wave(cam, Q, K, L);
                 }
                 __syncthreads();
             }
