@@ -11,6 +11,7 @@ namespace gp {
 constexpr int kMaxCams = 4;
 constexpr int kBinQuads = 64;            // road strips per culling bin
 constexpr int kMaxPrims = 1 << 23;       // primitives per scene (key packs 23 bits)
+constexpr int kQueues = 8;               // work-queue segments, one per XCD of the MI355X
 
 // Per-scene record.
 struct SceneRec {
@@ -47,8 +48,10 @@ struct DevSim {
     const uint8_t *road_color;// [R] colour of road slot r
     const RoadBin *bins;
     const uint8_t *palette;   // [256*3]
-    const int32_t *queue;     // [V] view order for the persistent schedule
-    uint32_t *counter;        // [2] work-queue head, finished workgroups (zero between launches)
+    const int32_t *queue;     // [V] view order for the persistent schedule, kQueues segments
+    uint32_t *counter;        // [kQueues + 2] segment heads, finished workgroups, exhausted
+                              // segment mask (all zero between launches)
+    int32_t qseg[kQueues + 1];// segment q of the queue is [qseg[q], qseg[q + 1])
     int32_t n_scenes, n_agents, n_views;
     int32_t width, height, n_cams;
     int32_t road_color_uniform;   // 1 if every road strip has the colour road_color0

@@ -110,7 +110,12 @@ __global__ void k_cs(DevSim s)
 struct V3 { float x, y, z; };
 struct Plane { float A, B, C; };
 
-// per-view camera constants
+__device__ __forceinline__ float uniform_f(float x)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+
+// per-view camera constants (kCamFloats floats, then the image size)
 struct Cam {
     float px, py, fx, fy, h;
     float f, cx, cy, F256, CX256, CY256, G, zn, zf;
@@ -119,6 +124,8 @@ struct Cam {
     float road_zmax;                          // farthest road depth a sample row can see
     int W, H;
 };
+constexpr int kCamFloats = 22;
+static_assert(offsetof(Cam, W) == 4 * kCamFloats && sizeof(Cam) == 4 * (kCamFloats + 2), "Cam layout");
 
 __device__ __forceinline__ V3 to_cam(const Cam &c, float dx, float dy, float Z)
 {
@@ -188,6 +195,13 @@ __device__ __forceinline__ Cam make_cam(const DevSim &s, const SceneRec &sc, int
     V3 p0;
     p0.x = 0.0f; p0.y = 0.0f - c.h; p0.z = 0.0f;
     c.road = face_plane(c, n, plane_d(n, p0));
+    // one view per workgroup: every field is wave-uniform; keep them in
+    // scalar registers
+    float *f = &c.px;
+#pragma unroll
+    for (int q = 0; q < kCamFloats; ++q) f[q] = uniform_f(f[q]);
+    c.W = __builtin_amdgcn_readfirstlane(c.W);
+    c.H = __builtin_amdgcn_readfirstlane(c.H);
     return c;
 }
 
@@ -249,13 +263,11 @@ __device__ __forceinline__ void build_face(const DevSim &s, const SceneRec &sc, 
     P.one_sided = true;
 }
 
-// road slot `slot` (relative to the scene's road_base)
+// road slot `slot` (relative to the scene's road_base) with corners q0, q1
 __device__ __forceinline__ void build_road(const DevSim &s, const SceneRec &sc, const Cam &cam, int slot,
-                                           Poly &P)
+                                           const float4 &q0, const float4 &q1, Poly &P)
 {
     const int g = sc.road_base + slot;
-    const float4 q0 = s.roads[2 * g];
-    const float4 q1 = s.roads[2 * g + 1];
     P.v[0] = to_cam(cam, q0.x - cam.px, q0.y - cam.py, 0.0f);
     P.v[1] = to_cam(cam, q0.z - cam.px, q0.w - cam.py, 0.0f);
     P.v[2] = to_cam(cam, q1.x - cam.px, q1.y - cam.py, 0.0f);
@@ -526,6 +538,8 @@ struct Lds {
     lptr<int32_t> cnt;              // counters (C_*)
     lptr<int32_t> wsum;             // [16] per-wave partial sums
     lptr<uint32_t> pal;             // [256] RGB as u32
+    lptr<uint32_t> lut;             // rgb kernel: [16][4] the 16 four-pixel road/background
+                                    // patterns as 3 packed RGB dwords (+1 pad), 16-byte aligned
     int tcap;                       // capacity of tris
     int rcap;                       // capacity of rtris (rgb kernel)
     int nw;                         // 64-bit words per image row
@@ -788,6 +802,7 @@ __device__ __forceinline__ void fast_poly(const Cam &cam, const Poly &P, const S
 // them; output p is fetched by lane p from the lane that produced it.  A
 // polygon that would need more than kMaxVerts vertices (only a
 // self-intersecting input quad can) is dropped.
+static_assert(kBinQuads < 128, "bin count packs into 7 bits");
 constexpr int kMaxVerts = 12;
 constexpr int kMaxTrisPerCand = kMaxVerts - 2;
 
@@ -888,8 +903,12 @@ __device__ __forceinline__ void clip_wave(const Cam &cam, const Poly &P, const S
 __device__ __forceinline__ void build_code(const DevSim &s, const SceneRec &sc, const Cam &cam, int code,
                                            Poly &P)
 {
-    if (code >= 0) build_face(s, sc, cam, code >> 3, code & 7, P);
-    else build_road(s, sc, cam, -code - 1, P);
+    if (code >= 0) {
+        build_face(s, sc, cam, code >> 3, code & 7, P);
+    } else {
+        const int slot = -code - 1, g = sc.road_base + slot;
+        build_road(s, sc, cam, slot, s.roads[2 * g], s.roads[2 * g + 1], P);
+    }
 }
 
 // One setup pass over boxes (KIND 0) or road bins (KIND 1); FAST selects the
@@ -910,11 +929,19 @@ __device__ void setup_source(const DevSim &s, const SceneRec &sc, const Cam &cam
     const int per_round = can_flush ? max(1, min(B, fcap / 2)) : B;
     for (int u0 = 0; u0 < n_units; u0 += B) {
         // ---- cull units, compact the survivors
+        // survivors are recorded as the agent index (boxes) or as the bin's
+        // slot range start * 128 + count (roads)
         const int u = u0 + tid;
         bool keep = false;
+        int rec = u;
         if (u < n_units) {
-            if (kind == 0) keep = (u != ego) && !box_outside(s, sc, cam, u);
-            else keep = !bin_outside(s, cam, s.bins[sc.bin_base + u]);
+            if (kind == 0) {
+                keep = (u != ego) && !box_outside(s, sc, cam, u);
+            } else {
+                const RoadBin bn = s.bins[sc.bin_base + u];
+                keep = !bin_outside(s, cam, bn);
+                rec = bn.start * 128 + bn.count;
+            }
         }
         if (tid == 0) {
             L.cnt[C_SURV] = 0;
@@ -930,15 +957,30 @@ __device__ void setup_source(const DevSim &s, const SceneRec &sc, const Cam &cam
                 if ((int)lane_id() == leader) base = lds_add(L.cnt + C_SURV, nk);
                 base = __shfl(base, leader);
             }
-            if (keep) L.surv[base + __popcll(bm & ((1ull << lane_id()) - 1ull))] = u;
+            if (keep) L.surv[base + __popcll(bm & ((1ull << lane_id()) - 1ull))] = rec;
         }
         __syncthreads();
         const int ns = L.cnt[C_SURV];
         const int ncand = kind == 0 ? 6 * ns : kBinQuads * ns;
-        // ---- rounds over the candidates of the survivors
+        // ---- rounds over the candidates of the survivors; the road strips of
+        // the next round are fetched while this round is processed
+        float4 nq0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), nq1 = nq0;
+        auto fetch = [&](int cn) {
+            if (kind == 1 && tid < per_round && cn < ncand) {
+                const int pk = L.surv[cn / kBinQuads], k = cn % kBinQuads;
+                if (k < (pk & 127)) {
+                    const int g = sc.road_base + (pk >> 7) + k;
+                    nq0 = s.roads[2 * g];
+                    nq1 = s.roads[2 * g + 1];
+                }
+            }
+        };
+        fetch(tid);
         int par = 0;
         for (int c0 = 0; c0 < ncand; c0 += per_round, par ^= 1) {
             const int c = c0 + tid;
+            const float4 q0 = nq0, q1 = nq1;
+            if (c0 + per_round < ncand) fetch(c + per_round);
             bool live = tid < per_round && c < ncand;
             int code = 0;
             Poly P;
@@ -948,12 +990,12 @@ __device__ void setup_source(const DevSim &s, const SceneRec &sc, const Cam &cam
                     code = j * 8 + f;
                     build_face(s, sc, cam, j, f, P);
                 } else {
-                    const RoadBin &bn = s.bins[sc.bin_base + L.surv[c / kBinQuads]];
-                    const int k = c % kBinQuads;
-                    live = k < bn.count;
+                    const int pk = L.surv[c / kBinQuads], k = c % kBinQuads;
+                    live = k < (pk & 127);
                     if (live) {
-                        code = -(bn.start + k + 1);
-                        build_road(s, sc, cam, bn.start + k, P);
+                        const int slot = (pk >> 7) + k;
+                        code = -(slot + 1);
+                        build_road(s, sc, cam, slot, q0, q1, P);
                     }
                 }
             }
@@ -1069,6 +1111,34 @@ __device__ void resolve_fast(const DevSim &s, const Cam &cam, Lds &L, uint8_t *r
     }
 }
 
+// rgb kernel, rows [r0, r1) that no box fragment touches: the colour of a
+// pixel is road or background by its coverage bit alone (the road depth of a
+// row is positive exactly below the horizon).  A lane writes 16 pixels, 48
+// bytes, as three 16-byte stores assembled from the pattern table.  Needs
+// W % 16 == 0, W / 16 <= blockDim.x and a 16-byte aligned image.
+__device__ void resolve_rows_lut(const Cam &cam, Lds &L, uint8_t *rgb, int64_t view, int r0, int r1)
+{
+    const int W = cam.W;
+    const int tpr = W >> 4;                       // lanes per row
+    const int rpi = (int)blockDim.x / tpr;        // rows per pass
+    const int rr = (int)threadIdx.x / tpr, ci = (int)threadIdx.x - rr * tpr;
+    if (rr >= rpi) return;
+    const int i = ci << 4;
+    uint8_t *img = rgb + 3 * (view * (int64_t)W * cam.H);
+    typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+    const lptr<u4> lut = (lptr<u4>)L.lut;
+    for (int j = r0 + rr; j < r1; j += rpi) {
+        const float dv = ((float)j + 0.5f) - cam.cy;
+        const float rz = fmaf(cam.road.B, dv, cam.road.C);
+        const uint32_t bits = rz > 0.0f ? (uint32_t)(L.road[(size_t)j * L.nw + (i >> 6)] >> (i & 63)) & 0xFFFFu : 0u;
+        const u4 a = lut[bits & 15u], b = lut[(bits >> 4) & 15u], c = lut[(bits >> 8) & 15u], d = lut[bits >> 12];
+        u4 *out = reinterpret_cast<u4 *>(img + 3 * ((int64_t)j * W + i));
+        out[0] = u4{a.x, a.y, a.z, b.x};
+        out[1] = u4{b.y, b.z, c.x, c.y};
+        out[2] = u4{c.z, d.x, d.y, d.z};
+    }
+}
+
 // general kernel: key band -> colour, depth, primitive id.
 __device__ void resolve_general(const Cam &cam, Lds &L, const RenderOut &o, int64_t view, int b0, int b1)
 {
@@ -1131,8 +1201,13 @@ __device__ void render_view(const DevSim &s, const RenderOut &o, const LaunchCfg
     }
     __syncthreads();
     if (FAST) {
-        resolve_fast<false>(s, cam, L, o.rgb, view, 0, kr0, 0);
-        resolve_fast<false>(s, cam, L, o.rgb, view, kr1, H, 0);
+        if ((W & 15) == 0 && (W >> 4) <= (int)blockDim.x && ((uintptr_t)o.rgb & 15) == 0) {
+            resolve_rows_lut(cam, L, o.rgb, view, 0, kr0);
+            resolve_rows_lut(cam, L, o.rgb, view, kr1, H);
+        } else {
+            resolve_fast<false>(s, cam, L, o.rgb, view, 0, kr0, 0);
+            resolve_fast<false>(s, cam, L, o.rgb, view, kr1, H, 0);
+        }
     }
     for (int b0 = kr0; b0 < kr1; b0 += BR) {
         const int b1 = min(kr1, b0 + BR);
@@ -1190,33 +1265,67 @@ __global__ __launch_bounds__(BLOCK) void k_render(DevSim s, RenderOut o, LaunchC
     L.wsum = (lptr<int32_t>)(smem + off);
     off += 4u * 16;
     L.pal = (lptr<uint32_t>)(smem + off);
+    off += 4u * 256;
+    off = (off + 15) & ~(size_t)15;
+    L.lut = (lptr<uint32_t>)(smem + off);
     for (int p = threadIdx.x; p < 256; p += blockDim.x)
         L.pal[p] = (uint32_t)s.palette[3 * p] | ((uint32_t)s.palette[3 * p + 1] << 8) |
                    ((uint32_t)s.palette[3 * p + 2] << 16);
+    if (FAST && threadIdx.x < 16) {
+        // pattern b: pixel k is road where bit k of b is set, background elsewhere
+        auto rgb_of = [&](int idx) -> uint32_t {
+            return (uint32_t)s.palette[3 * idx] | ((uint32_t)s.palette[3 * idx + 1] << 8) |
+                   ((uint32_t)s.palette[3 * idx + 2] << 16);
+        };
+        const uint32_t road = rgb_of(s.road_color0), bg = rgb_of(0);
+        const int b = threadIdx.x;
+        const uint32_t c0 = (b & 1) ? road : bg, c1 = (b & 2) ? road : bg;
+        const uint32_t c2 = (b & 4) ? road : bg, c3 = (b & 8) ? road : bg;
+        L.lut[4 * b + 0] = c0 | (c1 << 24);
+        L.lut[4 * b + 1] = (c1 >> 8) | (c2 << 16);
+        L.lut[4 * b + 2] = (c2 >> 16) | (c3 << 8);
+        L.lut[4 * b + 3] = 0u;
+    }
     __shared__ int s_item;
     if (!persistent) {
         __syncthreads();
         render_view<FAST>(s, o, lc, L, view_begin + blockIdx.x);
         return;
     }
-    // counter[0]: queue head; counter[1]: workgroups that have left the loop.
-    // The last workgroup to leave zeroes both, so the next launch on the
-    // stream starts from an empty queue without a separate reset (and a
-    // captured graph holds no memset node).
+    // Work queue: kQueues segments of the view order, one per XCD; a segment
+    // holds whole scenes, so a scene's geometry is read through one XCD's L2.
+    // Workgroups are dispatched to the XCDs in turn, so workgroup b starts on
+    // segment b mod kQueues; when its segment is exhausted it marks it in the
+    // shared exhausted mask, which the same atomic returns, and moves on to
+    // the next segment not yet marked.  counter[q] is the head of segment q,
+    // counter[kQueues] counts the workgroups that have left the loop and
+    // counter[kQueues + 1] is the exhausted mask.  The last workgroup to leave
+    // zeroes them all, so the next launch on the stream starts from full
+    // queues without a separate reset (and a captured graph holds no memset
+    // node).
+    int cur = (int)(blockIdx.x % kQueues);       // thread 0's current segment
+    auto take = [&]() -> int {
+        for (;;) {
+            const int pos = (int)atomicAdd(&s.counter[cur], 1u);
+            if (pos < s.qseg[cur + 1] - s.qseg[cur]) return s.qseg[cur] + pos;
+            const uint32_t mask = atomicOr(&s.counter[kQueues + 1], 1u << cur) | (1u << cur);
+            if (mask == (1u << kQueues) - 1u) return s.n_views;
+            do cur = (cur + 1) % kQueues; while ((mask >> cur) & 1u);
+        }
+    };
     for (;;) {
         __syncthreads();
-        if (threadIdx.x == 0) s_item = (int)atomicAdd(&s.counter[0], 1u);
+        if (threadIdx.x == 0) s_item = take();
         __syncthreads();
-        const int it = s_item;
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
         if (it >= s.n_views) break;
         render_view<FAST>(s, o, lc, L, s.queue[it]);
     }
     if (threadIdx.x == 0) {
         __threadfence();
-        const uint32_t done = atomicAdd(&s.counter[1], 1u);
+        const uint32_t done = atomicAdd(&s.counter[kQueues], 1u);
         if (done == gridDim.x - 1) {
-            atomicExch(&s.counter[0], 0u);
-            atomicExch(&s.counter[1], 0u);
+            for (int q = 0; q < kQueues + 2; ++q) atomicExch(&s.counter[q], 0u);
             __threadfence();
         }
     }
@@ -1231,7 +1340,7 @@ size_t render_lds_bytes(const DevSim &s, const LaunchCfg &c, int fast)
     const size_t nw = (size_t)(s.width + 63) / 64;
     size_t b = sizeof(TriRec) * (size_t)tcap + sizeof(TriGeo) * (size_t)rcap +
                8u * (size_t)c.band_rows * s.width + 4u * (size_t)(max(tcap, rcap) + 4) +
-               8u * (size_t)c.block_threads + 64u + 64u + 1024u;
+               8u * (size_t)c.block_threads + 64u + 64u + 1024u + 16u + 256u;
     if (fast) b += 8u * (size_t)s.height * nw;
     return b;
 }

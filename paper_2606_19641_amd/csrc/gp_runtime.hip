@@ -115,7 +115,7 @@ Layout make_layout(const gp_config *cfg, const gp_scene_desc *sc, int32_t n)
     L.bins = take(sizeof(gp::RoadBin) * L.n_bins);
     L.palette = take(768);
     L.queue = take(4 * L.n_views);
-    L.counter = take(8);
+    L.counter = take(4 * (gp::kQueues + 2));
     L.total = o;
     return L;
 }
@@ -382,21 +382,34 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
     }
     std::memcpy(at(L.scenes), sim->scenes.data(), sizeof(gp::SceneRec) * n_scenes);
     std::memcpy(at(L.palette), cfg->palette, 768);
-    // persistent queue: heavier scenes first, views of a scene adjacent so
-    // that they share the scene's geometry in L2
+    // persistent queue: kQueues segments, one per XCD, each holding whole
+    // scenes so that a scene's geometry is read through one L2.  Scenes go to
+    // the segment with the least work so far, heaviest first (work of a view
+    // ~ its candidate primitives); inside a segment heavier scenes come first
+    // and the views of a scene are adjacent.
     std::vector<int> order(n_scenes);
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        const int64_t ca = 6LL * scenes[a].n_agents + scenes[a].n_roads;
-        const int64_t cb = 6LL * scenes[b].n_agents + scenes[b].n_roads;
-        return ca > cb;
-    });
+    auto view_work = [&](int s) { return 6LL * scenes[s].n_agents + scenes[s].n_roads + 64; };
+    auto scene_work = [&](int s) { return view_work(s) * (int64_t)scenes[s].n_agents * cfg->n_cams; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return scene_work(a) > scene_work(b); });
+    std::vector<std::vector<int>> seg(gp::kQueues);
+    std::vector<int64_t> load(gp::kQueues, 0);
+    for (int s : order) {
+        const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        seg[q].push_back(s);
+        load[q] += scene_work(s);
+    }
     auto *queue = reinterpret_cast<int32_t *>(at(L.queue));
     int64_t qi = 0;
-    for (int s : order) {
-        const gp::SceneRec &r = sim->scenes[s];
-        for (int v = 0; v < r.n_agents * cfg->n_cams; ++v) queue[qi++] = r.view_base + v;
+    for (int q = 0; q < gp::kQueues; ++q) {
+        std::stable_sort(seg[q].begin(), seg[q].end(), [&](int a, int b) { return view_work(a) > view_work(b); });
+        sim->dev.qseg[q] = (int32_t)qi;
+        for (int s : seg[q]) {
+            const gp::SceneRec &r = sim->scenes[s];
+            for (int v = 0; v < r.n_agents * cfg->n_cams; ++v) queue[qi++] = r.view_base + v;
+        }
     }
+    sim->dev.qseg[gp::kQueues] = (int32_t)qi;
 
     unsigned char *base = static_cast<unsigned char *>(d_workspace);
     hipStream_t hs = static_cast<hipStream_t>(stream);

@@ -197,6 +197,35 @@ def test_nonsquare_and_ragged_width():
                        picks)
 
 
+def test_image_pointer_alignment_and_pattern_widths():
+    """Key-free rows of the rgb kernel are written 16 pixels at a time with
+    16-byte stores when the width allows it and the image is 16-byte aligned;
+    a 4-byte aligned image address takes the dword path.  Both give the same
+    bits."""
+    scenes = [g.crowded_scene(33), g.crowded_scene(34, n_agents=6, n_roads=80)]
+    for s in scenes:
+        s.road_color[:] = 1
+    pal = g.mixed_palette()
+    for cam in (g.camera_for(48, cams=g.FRONT_AND_SIDES),
+                g.Camera(width=80, height=20, focal_px=40.0, cam_dirs=g.FRONT),
+                g.Camera(width=16, height=40, focal_px=8.0, cam_dirs=g.FRONT)):
+        sim = _sim(scenes, cam, pal)
+        ref, _, _ = sim.render()
+        n = ref.numel()
+        buf = torch.zeros(n + 64, dtype=torch.uint8, device="cuda")
+        for off in (4, 8, 16):
+            out = buf[off:off + n].view(ref.shape)
+            sim.render(rgb=out)
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref), (cam.width, off)
+        from paper_2606_19641_amd import gp
+        with pytest.raises(gp.GpError):          # the ABI asks for a 4-byte aligned image
+            sim.render(rgb=buf[1:1 + n].view(ref.shape))
+        picks = [(si, a, k) for si, s in enumerate(scenes) for a in range(0, s.n_agents, 5)
+                 for k in range(len(cam.cam_dirs))]
+        _compare_views(scenes, cam, pal, ref.cpu().numpy(), None, None, picks)
+
+
 def test_degenerate_scenes():
     """A lone agent (empty view), no roads, a huge road quad (guard band),
     zero-area and clockwise road strips, a flat box, boxes behind the camera."""
