@@ -138,6 +138,32 @@ gp_status gp_sim_step_render_graph(gp_sim *sim, const float *d_actions, uint8_t 
 gp_status gp_sim_get_state(gp_sim *sim, float *d_dst, void *stream);
 gp_status gp_sim_set_state(gp_sim *sim, const float *d_src, void *stream);
 
+/* ---- Batched step + render over several sims (continuous batching in a
+ * serving loop; no paper passage: the paper batches all worlds of one
+ * training run, App. A "High-Throughput Batched Rendering").
+ *
+ * gp_batch_required_bytes: bytes of device batch workspace (and of host
+ * staging) for a batch of n_sims sims with n_agents agents and n_views
+ * views in total; -1 on bad arguments.
+ *
+ * gp_batch_step_render: for each sims[k], one kinematic step with the host
+ * actions h_actions[k] (float [n_agents_k][2]) followed by an rgb render of
+ * every view into d_rgb[k] (device uint8 [n_views_k][H][W][3], 4-byte
+ * aligned), all sims in one step launch and at most two render launches.
+ * Each sim's result is bit-identical to gp_sim_step + gp_sim_render on that
+ * sim alone.  Every sim must have the same image size; a sim may appear once.
+ * The library packs the batch into h_staging (host memory, pinned for an
+ * asynchronous copy, 16-byte aligned) and copies it to d_ws (device,
+ * 256-byte aligned) on `stream`: the caller must leave h_staging and d_ws
+ * untouched until the stream has passed this call (record an event), and
+ * must not render the same sims on another stream meanwhile.  Launch
+ * settings are those of sims[0].  Returns GP_EINVAL / GP_ENOMEM with nothing
+ * launched on bad arguments. */
+int64_t gp_batch_required_bytes(int32_t n_sims, int64_t n_agents, int64_t n_views);
+gp_status gp_batch_step_render(gp_sim *const *sims, int32_t n_sims, const float *const *h_actions,
+                               uint8_t *const *d_rgb, void *d_ws, int64_t ws_bytes, void *h_staging,
+                               int64_t staging_bytes, void *stream);
+
 int64_t gp_sim_num_views(const gp_sim *sim);
 int64_t gp_sim_num_agents(const gp_sim *sim);
 int32_t gp_sim_num_scenes(const gp_sim *sim);

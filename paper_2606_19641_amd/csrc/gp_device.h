@@ -67,6 +67,14 @@ struct RenderOut {
     int32_t *primid;
 };
 
+// One sim of a batched (serving) launch.
+struct SimEntry {
+    DevSim s;
+    RenderOut o;
+    const float2 *act;        // the sim's actions [n_agents] (accel, steer)
+    const void *pad;
+};
+
 struct LaunchCfg {
     int band_rows;
     int batch_tris;
@@ -81,5 +89,10 @@ hipError_t launch_cs(const DevSim &s, hipStream_t st);
 hipError_t launch_render(const DevSim &s, const RenderOut &o, const LaunchCfg &c, int fast,
                          int persistent, int view_begin, int grid, hipStream_t st);
 size_t render_lds_bytes(const DevSim &s, const LaunchCfg &c, int fast);
+size_t render_lds_bytes(int width, int height, const LaunchCfg &c, int fast);
+// batched (serving) launches over a device table of sims
+hipError_t launch_step_multi(const SimEntry *tab, int n_sims, int max_agents, hipStream_t st);
+hipError_t launch_render_multi(const SimEntry *tab, const int2 *items, int n_items, uint32_t *ctl,
+                               const LaunchCfg &c, int fast, int width, int height, int grid, hipStream_t st);
 
 }  // namespace gp

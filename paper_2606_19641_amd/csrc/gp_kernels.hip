@@ -71,10 +71,8 @@ __device__ __forceinline__ void dev_sincos(float t, float &s, float &c)
 
 // ------------------------------------------------------------ agent step
 
-__global__ void k_step(DevSim s, const float2 *__restrict__ act, int begin, int count)
+__device__ __forceinline__ void step_agent(const DevSim &s, const float2 *act, int i)
 {
-    const int i = begin + blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= begin + count) return;
     const float4 st = s.state[i];
     const float L = s.dims[i].x;
     const float2 u = act[i];
@@ -94,6 +92,23 @@ __global__ void k_step(DevSim s, const float2 *__restrict__ act, int begin, int 
     dev_sincos(psi, sp, cp);
     s.state[i] = make_float4(fmaf(vdt, cp, st.x), fmaf(vdt, sp, st.y), psi, v1);
     s.cs[i] = make_float2(cp, sp);
+}
+
+__global__ void k_step(DevSim s, const float2 *__restrict__ act, int begin, int count)
+{
+    const int i = begin + blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= begin + count) return;
+    step_agent(s, act, i);
+}
+
+// batch of sims: sim blockIdx.y, its actions indexed from its first agent
+__global__ void k_step_multi(const SimEntry *__restrict__ tab)
+{
+    const SimEntry &e = tab[blockIdx.y];
+    const DevSim s = e.s;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= s.n_agents) return;
+    step_agent(s, e.act, i);
 }
 
 __global__ void k_cs(DevSim s)
@@ -1235,25 +1250,20 @@ __device__ void render_view(const DevSim &s, const RenderOut &o, const LaunchCfg
     }
 }
 
-// BLOCK is the launch's block size: the bound lets the register allocator
-// use what a BLOCK-thread workgroup can have instead of assuming 1024 threads.
-template <int FAST, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_render(DevSim s, RenderOut o, LaunchCfg lc, int persistent,
-                                                  int view_begin)
+// LDS layout of a render workgroup for W x H images (sizes as render_lds_bytes)
+__device__ __forceinline__ void carve_lds(unsigned char *smem, Lds &L, int W, int H, const LaunchCfg &lc, int fast)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    Lds L;
-    list_caps(FAST, lc.batch_tris, L.tcap, L.rcap);
-    L.nw = (s.width + 63) >> 6;
+    list_caps(fast, lc.batch_tris, L.tcap, L.rcap);
+    L.nw = (W + 63) >> 6;
     size_t off = 0;
     L.tris = (lptr<TriRec>)(smem + off);
     off += sizeof(TriRec) * (size_t)L.tcap;
     L.rtris = (lptr<TriGeo>)(smem + off);
     off += sizeof(TriGeo) * (size_t)L.rcap;
     L.zb = (lptr<unsigned long long>)(smem + off);
-    off += 8u * (size_t)lc.band_rows * s.width;
+    off += 8u * (size_t)lc.band_rows * W;
     L.road = (lptr<unsigned long long>)(smem + off);
-    off += FAST ? 8u * (size_t)s.height * L.nw : 0;
+    off += fast ? 8u * (size_t)H * L.nw : 0;
     L.scan = (lptr<int32_t>)(smem + off);
     off += 4u * (size_t)(max(L.tcap, L.rcap) + 4);
     L.surv = (lptr<int32_t>)(smem + off);
@@ -1268,10 +1278,16 @@ __global__ __launch_bounds__(BLOCK) void k_render(DevSim s, RenderOut o, LaunchC
     off += 4u * 256;
     off = (off + 15) & ~(size_t)15;
     L.lut = (lptr<uint32_t>)(smem + off);
+}
+
+// The sim's palette, and for the rgb kernel its road/background pattern
+// table, into LDS; published by the caller's next barrier.
+__device__ __forceinline__ void load_palette(const DevSim &s, Lds &L, int fast)
+{
     for (int p = threadIdx.x; p < 256; p += blockDim.x)
         L.pal[p] = (uint32_t)s.palette[3 * p] | ((uint32_t)s.palette[3 * p + 1] << 8) |
                    ((uint32_t)s.palette[3 * p + 2] << 16);
-    if (FAST && threadIdx.x < 16) {
+    if (fast && threadIdx.x < 16) {
         // pattern b: pixel k is road where bit k of b is set, background elsewhere
         auto rgb_of = [&](int idx) -> uint32_t {
             return (uint32_t)s.palette[3 * idx] | ((uint32_t)s.palette[3 * idx + 1] << 8) |
@@ -1286,6 +1302,18 @@ __global__ __launch_bounds__(BLOCK) void k_render(DevSim s, RenderOut o, LaunchC
         L.lut[4 * b + 2] = (c2 >> 16) | (c3 << 8);
         L.lut[4 * b + 3] = 0u;
     }
+}
+
+// BLOCK is the launch's block size: the bound lets the register allocator
+// use what a BLOCK-thread workgroup can have instead of assuming 1024 threads.
+template <int FAST, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_render(DevSim s, RenderOut o, LaunchCfg lc, int persistent,
+                                                  int view_begin)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    Lds L;
+    carve_lds(smem, L, s.width, s.height, lc, FAST);
+    load_palette(s, L, FAST);
     __shared__ int s_item;
     if (!persistent) {
         __syncthreads();
@@ -1331,18 +1359,66 @@ __global__ __launch_bounds__(BLOCK) void k_render(DevSim s, RenderOut o, LaunchC
     }
 }
 
+
+// Batched render over several sims (serving): items are (sim, view) pairs,
+// workgroups pull them from one queue.  ctl[0] is the queue head, ctl[1]
+// counts the workgroups that have left; the last one zeroes both.  Every sim
+// of the batch has W x H images; the palette is reloaded when the sim changes.
+template <int FAST, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_render_multi(const SimEntry *__restrict__ tab,
+                                                        const int2 *__restrict__ items, int n_items,
+                                                        uint32_t *ctl, LaunchCfg lc, int W, int H)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    Lds L;
+    carve_lds(smem, L, W, H, lc, FAST);
+    __shared__ int s_item;
+    int cur = -1;                                 // sim whose palette is in LDS
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(&ctl[0], 1u);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
+        if (it >= n_items) break;
+        const int2 item = items[it];
+        const int k = __builtin_amdgcn_readfirstlane(item.x), view = __builtin_amdgcn_readfirstlane(item.y);
+        const DevSim s = tab[k].s;
+        const RenderOut o = tab[k].o;
+        if (k != cur) {
+            load_palette(s, L, FAST);
+            cur = k;
+            __syncthreads();
+        }
+        render_view<FAST>(s, o, lc, L, view);
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t done = atomicAdd(&ctl[1], 1u);
+        if (done == gridDim.x - 1) {
+            atomicExch(&ctl[0], 0u);
+            atomicExch(&ctl[1], 0u);
+            __threadfence();
+        }
+    }
+}
+
 // ------------------------------------------------------------ launchers
 
-size_t render_lds_bytes(const DevSim &s, const LaunchCfg &c, int fast)
+size_t render_lds_bytes(int width, int height, const LaunchCfg &c, int fast)
 {
     int tcap, rcap;
     list_caps(fast, c.batch_tris, tcap, rcap);
-    const size_t nw = (size_t)(s.width + 63) / 64;
+    const size_t nw = (size_t)(width + 63) / 64;
     size_t b = sizeof(TriRec) * (size_t)tcap + sizeof(TriGeo) * (size_t)rcap +
-               8u * (size_t)c.band_rows * s.width + 4u * (size_t)(max(tcap, rcap) + 4) +
+               8u * (size_t)c.band_rows * width + 4u * (size_t)(max(tcap, rcap) + 4) +
                8u * (size_t)c.block_threads + 64u + 64u + 1024u + 16u + 256u;
-    if (fast) b += 8u * (size_t)s.height * nw;
+    if (fast) b += 8u * (size_t)height * nw;
     return b;
+}
+
+size_t render_lds_bytes(const DevSim &s, const LaunchCfg &c, int fast)
+{
+    return render_lds_bytes(s.width, s.height, c, fast);
 }
 
 hipError_t launch_step(const DevSim &s, const float *actions, int agent_begin, int agent_count,
@@ -1352,6 +1428,38 @@ hipError_t launch_step(const DevSim &s, const float *actions, int agent_begin, i
     const int B = 256;
     hipLaunchKernelGGL(k_step, dim3((agent_count + B - 1) / B), dim3(B), 0, st, s,
                        reinterpret_cast<const float2 *>(actions), agent_begin, agent_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_multi(const SimEntry *tab, int n_sims, int max_agents, hipStream_t st)
+{
+    if (n_sims <= 0 || max_agents <= 0) return hipSuccess;
+    const int B = 256;
+    hipLaunchKernelGGL(k_step_multi, dim3((max_agents + B - 1) / B, n_sims), dim3(B), 0, st, tab);
+    return hipGetLastError();
+}
+
+hipError_t launch_render_multi(const SimEntry *tab, const int2 *items, int n_items, uint32_t *ctl,
+                               const LaunchCfg &c, int fast, int width, int height, int grid, hipStream_t st)
+{
+    if (n_items <= 0 || grid <= 0) return hipSuccess;
+    const size_t lds = render_lds_bytes(width, height, c, fast);
+#define GP_LAUNCH(F, B)                                                                                 \
+    hipLaunchKernelGGL((k_render_multi<F, B>), dim3(grid), dim3(B), lds, st, tab, items, n_items, ctl, c, width, height)
+    switch (c.block_threads) {
+    case 256:
+        if (fast) GP_LAUNCH(1, 256); else GP_LAUNCH(0, 256);
+        break;
+    case 512:
+        if (fast) GP_LAUNCH(1, 512); else GP_LAUNCH(0, 512);
+        break;
+    case 1024:
+        if (fast) GP_LAUNCH(1, 1024); else GP_LAUNCH(0, 1024);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef GP_LAUNCH
     return hipGetLastError();
 }
 

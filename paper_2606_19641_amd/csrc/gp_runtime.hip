@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <climits>
 #include <cstring>
 #include <new>
 #include <numeric>
@@ -544,6 +545,118 @@ gp_status gp_sim_step_render_graph(gp_sim *sim, const float *d_actions, uint8_t 
     }
     hipError_t e = hipGraphLaunch(sim->gexec, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "graph launch");
+    return GP_OK;
+}
+
+// ---- batched step + render over several sims (serving)
+
+namespace {
+
+struct BatchLayout {
+    int64_t ctl, table, items, actions, total;
+};
+
+BatchLayout batch_layout(int32_t n_sims, int64_t n_agents, int64_t n_views)
+{
+    BatchLayout B{};
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) { int64_t at = o; o = align_up(o + std::max<int64_t>(bytes, 1)); return at; };
+    B.ctl = take(4 * 4);                                   // two queue heads + exit counters
+    B.table = take((int64_t)sizeof(gp::SimEntry) * n_sims);
+    B.items = take(8 * n_views);
+    B.actions = take(8 * n_agents);
+    B.total = o;
+    return B;
+}
+
+}  // namespace
+
+int64_t gp_batch_required_bytes(int32_t n_sims, int64_t n_agents, int64_t n_views)
+{
+    if (n_sims < 1 || n_agents < 0 || n_views < 0) return -1;
+    return batch_layout(n_sims, n_agents, n_views).total;
+}
+
+gp_status gp_batch_step_render(gp_sim *const *sims, int32_t n_sims, const float *const *h_actions,
+                               uint8_t *const *d_rgb, void *d_ws, int64_t ws_bytes, void *h_staging,
+                               int64_t staging_bytes, void *stream)
+{
+    if (!sims || !h_actions || !d_rgb || !d_ws || !h_staging) return fail(GP_EINVAL, "NULL argument");
+    if (n_sims < 1) return fail(GP_EINVAL, "n_sims must be >= 1");
+    if (reinterpret_cast<uintptr_t>(d_ws) % kAlign != 0 || reinterpret_cast<uintptr_t>(h_staging) % 16 != 0)
+        return fail(GP_EINVAL, "batch workspace must be %lld-byte aligned, staging 16-byte aligned",
+                    (long long)kAlign);
+    int64_t n_agents = 0, n_views = 0;
+    int max_agents = 0;
+    for (int k = 0; k < n_sims; ++k) {
+        const gp_sim *sim = sims[k];
+        if (!sim || !h_actions[k] || !d_rgb[k]) return fail(GP_EINVAL, "NULL entry %d", k);
+        if (reinterpret_cast<uintptr_t>(d_rgb[k]) % 4 != 0) return fail(GP_EINVAL, "rgb %d must be 4-byte aligned", k);
+        if (sim->cfg.width != sims[0]->cfg.width || sim->cfg.height != sims[0]->cfg.height)
+            return fail(GP_EINVAL, "every sim of a batch must have the same image size");
+        if (sim->device != sims[0]->device) return fail(GP_EINVAL, "every sim of a batch must be on one device");
+        for (int j = 0; j < k; ++j)
+            if (sims[j] == sim) return fail(GP_EINVAL, "sim %d appears twice in the batch", k);
+        n_agents += sim->lay.n_agents;
+        n_views += sim->lay.n_views;
+        max_agents = std::max<int>(max_agents, (int)sim->lay.n_agents);
+    }
+    const BatchLayout B = batch_layout(n_sims, n_agents, n_views);
+    if (ws_bytes < B.total || staging_bytes < B.total)
+        return fail(GP_ENOMEM, "batch needs %lld bytes of workspace and staging", (long long)B.total);
+    if (n_views > INT32_MAX) return fail(GP_EINVAL, "too many views in one batch");
+
+    // host image of the batch buffer: zeroed queue counters, the sim table,
+    // the (sim, view) items (rgb-kernel sims first), the packed actions
+    unsigned char *h = static_cast<unsigned char *>(h_staging);
+    unsigned char *d = static_cast<unsigned char *>(d_ws);
+    std::memset(h + B.ctl, 0, 16);
+    auto *tab = reinterpret_cast<gp::SimEntry *>(h + B.table);
+    auto *items = reinterpret_cast<int32_t *>(h + B.items);
+    auto *act = reinterpret_cast<float *>(h + B.actions);
+    int64_t a0 = 0, n_fast = 0;
+    for (int k = 0; k < n_sims; ++k) {
+        const gp_sim *sim = sims[k];
+        gp::SimEntry e{};
+        e.s = sim->dev;
+        e.o = gp::RenderOut{d_rgb[k], nullptr, nullptr};
+        e.act = reinterpret_cast<const float2 *>(d + B.actions + 8 * a0);
+        std::memcpy(&tab[k], &e, sizeof(e));
+        std::memcpy(act + 2 * a0, h_actions[k], 8 * (size_t)sim->lay.n_agents);
+        a0 += sim->lay.n_agents;
+        if (sim->dev.road_color_uniform) n_fast += sim->lay.n_views;
+    }
+    int64_t qf = 0, qg = n_fast;
+    for (int k = 0; k < n_sims; ++k) {
+        const gp_sim *sim = sims[k];
+        int64_t &q = sim->dev.road_color_uniform ? qf : qg;
+        for (int64_t v = 0; v < sim->lay.n_views; ++v) {
+            items[2 * q] = k;
+            items[2 * q + 1] = (int32_t)v;
+            ++q;
+        }
+    }
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(d, h, (size_t)B.total, hipMemcpyHostToDevice, hs);
+    if (e != hipSuccess) return hip_fail(e, "batch upload");
+    const auto *dtab = reinterpret_cast<const gp::SimEntry *>(d + B.table);
+    const auto *ditems = reinterpret_cast<const int2 *>(d + B.items);
+    auto *ctl = reinterpret_cast<uint32_t *>(d + B.ctl);
+    e = gp::launch_step_multi(dtab, n_sims, max_agents, hs);
+    if (e != hipSuccess) return hip_fail(e, "batch step launch");
+    const gp_launch &l = sims[0]->launch;
+    const gp::LaunchCfg c = launch_cfg(l);
+    const int W = sims[0]->cfg.width, H = sims[0]->cfg.height;
+    for (int fast = 1; fast >= 0; --fast) {
+        const int64_t n = fast ? n_fast : n_views - n_fast;
+        if (n == 0) continue;
+        if (gp::render_lds_bytes(W, H, c, fast) > sims[0]->max_lds)
+            return fail(GP_EINVAL, "launch setting needs more LDS than the device has");
+        const int grid = (int)std::min<int64_t>(n, (int64_t)l.blocks_per_cu * sims[0]->n_cu);
+        e = gp::launch_render_multi(dtab, ditems + (fast ? 0 : n_fast), (int)n, ctl + (fast ? 0 : 2), c, fast, W,
+                                    H, grid, hs);
+        if (e != hipSuccess) return hip_fail(e, "batch render launch");
+    }
     return GP_OK;
 }
 

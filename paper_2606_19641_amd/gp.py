@@ -22,7 +22,7 @@ MAX_CAMS = 4
 EXPORTS = ("gp_sim_required_bytes", "gp_sim_create", "gp_sim_set_launch", "gp_sim_get_launch",
            "gp_sim_step", "gp_sim_render", "gp_sim_step_render_graph", "gp_sim_get_state",
            "gp_sim_set_state", "gp_sim_num_views", "gp_sim_num_agents", "gp_sim_num_scenes",
-           "gp_sim_destroy", "gp_last_error")
+           "gp_sim_destroy", "gp_last_error", "gp_batch_required_bytes", "gp_batch_step_render")
 
 
 class GpError(RuntimeError):
@@ -84,7 +84,11 @@ def lib() -> C.CDLL:
         L.gp_sim_destroy.argtypes = [vp]
         L.gp_sim_destroy.restype = None
         L.gp_last_error.restype = C.c_char_p
-        for name in ("gp_sim_create", "gp_sim_set_launch", "gp_sim_get_launch", "gp_sim_step",
+        L.gp_batch_required_bytes.argtypes = [i32, i64, i64]
+        L.gp_batch_required_bytes.restype = i64
+        L.gp_batch_step_render.argtypes = [C.POINTER(vp), i32, C.POINTER(vp), C.POINTER(vp), vp, i64,
+                                           vp, i64, vp]
+        for name in ("gp_batch_step_render", "gp_sim_create", "gp_sim_set_launch", "gp_sim_get_launch", "gp_sim_step",
                      "gp_sim_render", "gp_sim_step_render_graph", "gp_sim_get_state",
                      "gp_sim_set_state"):
             getattr(L, name).restype = C.c_int
@@ -121,33 +125,54 @@ def _stream_handle(stream) -> Optional[int]:
     return s.cuda_stream
 
 
+def _scene_descs(scenes: Sequence):
+    """ctypes scene descriptors plus the host arrays they point into."""
+    keep = []
+    descs = (SceneDesc * len(scenes))()
+    for i, s in enumerate(scenes):
+        st = np.ascontiguousarray(s.agent_state, dtype=np.float32)
+        dm = np.ascontiguousarray(s.agent_dims, dtype=np.float32)
+        ac = np.ascontiguousarray(s.agent_color, dtype=np.uint8)
+        rx = np.ascontiguousarray(s.road_xy, dtype=np.float32)
+        rc = np.ascontiguousarray(s.road_color, dtype=np.uint8)
+        keep += [st, dm, ac, rx, rc]
+        descs[i] = SceneDesc(st.shape[0], rx.shape[0] if rx.size else 0, st.ctypes.data,
+                             dm.ctypes.data, ac.ctypes.data, rx.ctypes.data if rx.size else None,
+                             rc.ctypes.data if rc.size else None)
+    return descs, keep
+
+
+def required_bytes(scenes: Sequence, camera, palette, dt: float = 0.1) -> int:
+    """Workspace bytes gp_sim_create needs for these scenes."""
+    descs, _keep = _scene_descs(scenes)
+    cfg = make_config(camera, palette, dt)
+    n = lib().gp_sim_required_bytes(C.byref(cfg), descs, len(scenes))
+    if n < 0:
+        raise GpError(GP_EINVAL, lib().gp_last_error().decode())
+    return int(n)
+
+
 class Sim:
-    """A batch of scenes resident on the GPU (workspace owned by this object)."""
+    """A batch of scenes resident on the GPU.  The workspace is allocated here
+    unless a device uint8 tensor (256-byte aligned, large enough) is given."""
 
     def __init__(self, scenes: Sequence, camera, palette, dt: float = 0.1, device: str = "cuda",
-                 stream=None):
+                 stream=None, workspace=None):
         import torch
         self.camera = camera
         self.device = torch.device(device)
-        self._keep = []
-        descs = (SceneDesc * len(scenes))()
-        for i, s in enumerate(scenes):
-            st = np.ascontiguousarray(s.agent_state, dtype=np.float32)
-            dm = np.ascontiguousarray(s.agent_dims, dtype=np.float32)
-            ac = np.ascontiguousarray(s.agent_color, dtype=np.uint8)
-            rx = np.ascontiguousarray(s.road_xy, dtype=np.float32)
-            rc = np.ascontiguousarray(s.road_color, dtype=np.uint8)
-            self._keep += [st, dm, ac, rx, rc]
-            descs[i] = SceneDesc(st.shape[0], rx.shape[0] if rx.size else 0, st.ctypes.data,
-                                 dm.ctypes.data, ac.ctypes.data, rx.ctypes.data if rx.size else None,
-                                 rc.ctypes.data if rc.size else None)
+        descs, self._keep = _scene_descs(scenes)
         self.cfg = make_config(camera, palette, dt)
         L = lib()
         nbytes = L.gp_sim_required_bytes(C.byref(self.cfg), descs, len(scenes))
         if nbytes < 0:
             raise GpError(GP_EINVAL, L.gp_last_error().decode())
         with torch.cuda.device(self.device):
-            self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+            if workspace is None:
+                workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+            elif workspace.numel() < nbytes:
+                raise GpError(GP_ENOMEM, f"workspace has {workspace.numel()} bytes, {nbytes} needed")
+            self.workspace = workspace
             h = C.c_void_p()
             _check(L.gp_sim_create(C.byref(self.cfg), descs, len(scenes), self.workspace.data_ptr(),
                                    int(nbytes), _stream_handle(stream), C.byref(h)))
@@ -233,3 +258,33 @@ def view_index(scenes, scene: int, agent: int, cam: int, n_cams: int) -> int:
     """Image index of (scene, agent, camera) in the (scene, agent, camera) order."""
     base = sum(s.n_agents for s in scenes[:scene])
     return (base + agent) * n_cams + cam
+
+
+def batch_required_bytes(sims: Sequence["Sim"]) -> int:
+    n = lib().gp_batch_required_bytes(len(sims), sum(x.n_agents for x in sims), sum(x.n_views for x in sims))
+    if n < 0:
+        raise GpError(GP_EINVAL, lib().gp_last_error().decode())
+    return int(n)
+
+
+def batch_step_render(sims: Sequence["Sim"], actions: Sequence[np.ndarray], rgbs, ws, staging,
+                      stream=None):
+    """One step + rgb render of every sim in one batched launch (serving).
+
+    actions[k]: host float32 [n_agents_k, 2]; rgbs[k]: device uint8 images of
+    sim k; ws: device uint8 tensor, staging: pinned host uint8 tensor, both at
+    least batch_required_bytes(sims).  The caller keeps ws / staging untouched
+    until the stream has passed this call."""
+    n = len(sims)
+    if not (len(actions) == len(rgbs) == n):
+        raise ValueError("one action array and one image tensor per sim")
+    acts = [np.ascontiguousarray(a, dtype=np.float32) for a in actions]
+    for a, sim, rgb in zip(acts, sims, rgbs):
+        if a.shape != (sim.n_agents, 2):
+            raise ValueError(f"actions must be [{sim.n_agents}, 2], got {a.shape}")
+        sim._check_tensor(rgb, (sim.n_views, sim.camera.height, sim.camera.width, 3), "uint8")
+    hs = (C.c_void_p * n)(*[x._h.value for x in sims])
+    ha = (C.c_void_p * n)(*[a.ctypes.data for a in acts])
+    hr = (C.c_void_p * n)(*[r.data_ptr() for r in rgbs])
+    _check(lib().gp_batch_step_render(hs, n, ha, hr, ws.data_ptr(), ws.numel(), staging.data_ptr(),
+                                      staging.numel(), _stream_handle(stream)))

@@ -1,0 +1,201 @@
+"""Serving scheduler on the CPU: arena allocator, admission by footprint,
+per-rollout FIFO with at most one request in flight, continuous batching,
+rejection and cancellation, under a virtual clock with an oracle-backed
+executor (each request's images must not depend on how requests were
+batched)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_19641_amd import scenegen as g
+from paper_2606_19641_amd import serve
+
+
+# ------------------------------------------------------------------ arena
+
+def test_arena_first_fit_alignment_and_coalescing():
+    a = serve.Arena(10 * 256)
+    x = a.alloc(1)            # rounds up to one block
+    y = a.alloc(300)          # two blocks
+    z = a.alloc(256)
+    assert (x, y, z) == (0, 256, 768)
+    assert a.used_bytes == 4 * 256 and a.free_bytes == 6 * 256
+    assert a.alloc(7 * 256) is None
+    a.free(y)
+    assert a.alloc(512) == 256          # first fit reuses the hole
+    a.free(256)
+    a.free(x)
+    a.free(z)
+    assert a.used_bytes == 0 and a.largest_free() == 10 * 256   # holes merged back
+    assert a.alloc(10 * 256) == 0
+
+
+def test_arena_random_sequence_keeps_invariants():
+    rng = np.random.default_rng(3)
+    a = serve.Arena(1 << 20)
+    live = {}
+    for _ in range(2000):
+        if live and rng.random() < 0.45:
+            off = list(live)[rng.integers(len(live))]
+            a.free(off)
+            del live[off]
+        else:
+            n = int(rng.integers(1, 40000))
+            off = a.alloc(n)
+            if off is not None:
+                assert off % 256 == 0
+                live[off] = (n + 255) // 256 * 256
+        spans = sorted(live.items())
+        for (o1, s1), (o2, _) in zip(spans, spans[1:]):
+            assert o1 + s1 <= o2                       # no overlap
+        assert a.used_bytes == sum(live.values())
+        assert a.used_bytes + sum(s for _, s in a._free) == a.capacity
+
+
+# ------------------------------------------------------------------ scheduler
+
+def _tiny_scene(seed, n_agents=4, n_roads=12):
+    return g.crowded_scene(seed, n_agents=n_agents, n_roads=n_roads, radius=15.0)
+
+
+class Recorder:
+    """Oracle-backed run callback: steps the rollout's scene and renders its
+    views, remembering what each request produced."""
+
+    def __init__(self, camera, palette):
+        self.cam, self.pal = camera, palette
+        self.state = {}
+        self.frames = {}
+        self.order = []
+
+    def __call__(self, handle, actions):
+        sc = handle["scene"]
+        key = handle["id"]
+        st = self.state.get(key, sc.agent_state)
+        st, _ = oracle.step(st, sc.agent_dims, actions, 0.1)
+        self.state[key] = st
+        cur = g.Scene(agent_state=st, agent_dims=sc.agent_dims, agent_color=sc.agent_color,
+                      road_xy=sc.road_xy, road_color=sc.road_color)
+        imgs = np.stack([oracle.render_scene_view(cur, self.cam, self.pal, a, k).rgb
+                         for a in range(cur.n_agents) for k in range(len(self.cam.cam_dirs))])
+        self.frames.setdefault(key, []).append(imgs)
+        self.order.append((key, actions.copy()))
+
+
+def _virtual_clock():
+    t = [0.0]
+    return (lambda: t[0]), (lambda v: t.__setitem__(0, v))
+
+
+def test_admission_by_footprint_waits_then_admits():
+    ex = serve.VirtualExecutor(footprint_fn=lambda sc: 1000)
+    srv = serve.Server(ex, budget_bytes=2 * 1024)      # two 1 KiB blocks
+    a, b, c = (srv.open(_tiny_scene(i)) for i in range(3))
+    assert srv.admitted(a) and srv.admitted(b) and not srv.admitted(c)
+    srv.close(a)                                         # nothing pending: freed at once
+    assert srv.admitted(c)
+    with pytest.raises(serve.ServeError):               # larger than the whole arena
+        serve.Server(ex, budget_bytes=512).open(_tiny_scene(9))
+
+
+def test_fifo_one_in_flight_and_batch_independence():
+    cam = g.camera_for(24)
+    pal = g.mixed_palette()
+    rec = Recorder(cam, pal)
+    ex = serve.VirtualExecutor(n_slots=2, base=1e-3, per_view=1e-5, run=rec)
+    srv = serve.Server(ex, budget_bytes=1 << 30, max_batch_rollouts=3)
+    scenes = [_tiny_scene(20 + i, n_agents=3 + i) for i in range(5)]
+    ids = [srv.open(s) for s in scenes]
+    arrivals = serve.poisson_arrivals(rate=4000.0, duration=0.02, seed=5)
+    rng = np.random.default_rng(11)
+    picks = rng.integers(0, len(ids), size=len(arrivals))
+    acts = {}
+
+    def actions_for(i, rid):
+        a = g.actions(77, i, np.full(scenes[rid].n_agents, rid), np.arange(scenes[rid].n_agents))
+        acts.setdefault(rid, []).append(a)
+        return a
+
+    clock, advance = _virtual_clock()
+    serve.drive(srv, arrivals, lambda i: ids[picks[i]], actions_for, clock, advance)
+    assert srv.idle()
+    ok = [q for q in srv.done if q.status == serve.OK]
+    assert len(ok) == len(arrivals)
+    # per rollout: executed in arrival order, never two in one batch or overlapping
+    by_roll = {}
+    for q in ok:
+        by_roll.setdefault(q.rollout, []).append(q)
+    for rid, qs in by_roll.items():
+        qs.sort(key=lambda q: q.t_arrival)
+        for q1, q2 in zip(qs, qs[1:]):
+            assert q1.batch < q2.batch and q1.t_done <= q2.t_done
+    # the recorder saw each rollout's actions in submission order
+    seen = {}
+    for key, a in rec.order:
+        seen.setdefault(key, []).append(a)
+    for rid in ids:
+        assert len(seen.get(rid, [])) == len(acts.get(rid, []))
+        for x, y in zip(seen.get(rid, []), acts.get(rid, [])):
+            assert np.array_equal(x, y)
+    # images equal a sequential replay of the same rollout (batching changes nothing)
+    for rid in ids:
+        sc = scenes[rid]
+        st = sc.agent_state
+        for n, a in enumerate(acts.get(rid, [])):
+            st, _ = oracle.step(st, sc.agent_dims, a, 0.1)
+            cur = g.Scene(agent_state=st, agent_dims=sc.agent_dims, agent_color=sc.agent_color,
+                          road_xy=sc.road_xy, road_color=sc.road_color)
+            ref = oracle.render_scene_view(cur, cam, pal, 0, 0).rgb
+            assert np.array_equal(rec.frames[rid][n][0], ref)
+    assert max(srv.batch_sizes) <= 3
+    summ = srv.summary(0.0, 0.02)
+    assert summ["completed"] == len(arrivals) and summ["p99_ms"] >= summ["p50_ms"] > 0
+
+
+def test_invalid_requests_rejected_others_unaffected():
+    ex = serve.VirtualExecutor()
+    srv = serve.Server(ex, budget_bytes=1 << 20)
+    sc = _tiny_scene(3, n_agents=5)
+    rid = srv.open(sc)
+    good = np.zeros((5, 2), np.float32)
+    bad_shape = np.zeros((4, 2), np.float32)
+    bad_nan = good.copy()
+    bad_nan[2, 1] = np.nan
+    q1 = srv.submit(rid, good, 0.0)
+    q2 = srv.submit(rid, bad_shape, 0.0)
+    q3 = srv.submit(rid, bad_nan, 0.0)
+    q4 = srv.submit(999, good, 0.0)
+    q5 = srv.submit(rid, good, 0.0)
+    assert [q.status for q in (q2, q3, q4)] == [serve.REJECTED] * 3
+    t = 0.0
+    while not srv.idle():
+        srv.pump(t)
+        t += 1e-3
+    assert q1.status == serve.OK and q5.status == serve.OK
+    assert q1.batch < q5.batch
+
+
+def test_cancel_drops_pending_and_frees_memory():
+    ex = serve.VirtualExecutor(n_slots=1, base=1.0, footprint_fn=lambda sc: 1000)
+    srv = serve.Server(ex, budget_bytes=1024)
+    a = srv.open(_tiny_scene(1))
+    b = srv.open(_tiny_scene(2))
+    assert not srv.admitted(b)
+    acts = np.zeros((4, 2), np.float32)
+    qs = [srv.submit(a, acts, 0.0) for _ in range(3)]
+    srv.pump(0.0)                                   # first request in flight
+    srv.cancel(a)
+    assert [q.status for q in qs[1:]] == [serve.CANCELLED] * 2
+    assert not srv.admitted(b)                      # still held by the in-flight request
+    srv.pump(2.0)                                   # it completes; memory is freed
+    assert qs[0].status == serve.OK
+    assert srv.admitted(b) and a not in srv.rollouts
+    assert ex.live == {1}
+
+
+def test_poisson_arrivals_rate_and_order():
+    t = serve.poisson_arrivals(rate=5000.0, duration=2.0, seed=1)
+    assert np.all(np.diff(t) > 0) and t[-1] < 2.0
+    assert abs(len(t) - 10000) < 5 * np.sqrt(10000)
+    gaps = np.diff(t)
+    assert abs(gaps.mean() - 1 / 5000.0) < 0.05 / 5000.0 * 20
