@@ -13,6 +13,7 @@ needs no communication and this benchmark runs on one GPU only.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -140,6 +141,97 @@ def cpu_baseline(w, budget_s: float):
                       f"{d1} views in {t1:.1f} s"}
 
 
+def serve_bench(args):
+    """Serving at Poisson load: resident rollouts (agents U{8..128}, road quads
+    U{500..8000}, one 128x128 forward view per agent), requests = one step +
+    render of a rollout; one JSON line with the per-rate results."""
+    import torch
+    from paper_2606_19641_amd import scenegen as g
+    from paper_2606_19641_amd import serve
+    pool = g.workload("serve", n_scenes=args.serve_pool)
+    pal = g.default_palette()
+    budget = args.serve_budget_gib << 30
+    ex = serve.GpuExecutor(pool.camera, pal, budget_bytes=budget, n_streams=args.serve_streams,
+                           max_batch_agents=args.serve_resident * 128, max_batch_rollouts=args.serve_resident)
+    rates = [float(r) for r in args.serve_rates.split(",")]
+    rows = []
+    # request payloads are generated before the timed runs (the client's cost,
+    # not the server's): 8 action sets per scene of the pool, used in turn
+    bank = [[g.actions(pool.seed, k, np.full(sc.n_agents, si), np.arange(sc.n_agents)) for k in range(8)]
+            for si, sc in enumerate(pool.scenes)]
+    scene_of = {}
+    for ri, rate in enumerate(rates):
+        srv = serve.Server(ex, budget_bytes=budget, max_batch_rollouts=args.serve_resident)
+        nxt = [0]
+        open_ids = []
+
+        def open_one():
+            si = nxt[0] % len(pool.scenes)
+            nxt[0] += 1
+            rid = srv.open(pool.scenes[si])
+            scene_of[rid] = si
+            open_ids.append(rid)
+
+        for _ in range(args.serve_resident):
+            open_one()
+        torch.cuda.synchronize()
+        life = args.serve_life
+        count = {}
+        rng = np.random.default_rng(1000 + ri)
+        arrivals = serve.poisson_arrivals(rate, args.serve_seconds, seed=2000 + ri)
+
+        retiring = []
+
+        def pick(i):
+            while retiring:                        # their last request is queued: close, replace
+                srv.close(retiring.pop())
+                open_one()
+            k = int(rng.integers(len(open_ids)))
+            rid = open_ids[k]
+            count[rid] = count.get(rid, 0) + 1
+            if count[rid] == life:
+                open_ids.pop(k)
+                retiring.append(rid)
+            return rid
+
+        def actions_for(i, rid):
+            return bank[scene_of[rid]][i % len(bank[0])]
+
+        gc.collect()
+        gc.disable()                               # no collector pauses inside the timed run
+        try:
+            t0 = serve.drive(srv, arrivals, pick, actions_for, time.perf_counter)
+            t1 = time.perf_counter() - t0
+        finally:
+            gc.enable()
+        torch.cuda.synchronize()
+        summ = srv.summary(0.0, max(args.serve_seconds, t1))
+        summ.update({"offered_per_s": rate, "wall_s": t1, "admitted_rollouts": nxt[0]})
+        rows.append(summ)
+        print(f"serve rate {rate:.0f}/s: {summ['completed_per_s']:.0f} done/s, p50 {summ['p50_ms']:.3f} ms, "
+              f"p99 {summ['p99_ms']:.3f} ms, mean batch {summ['mean_batch_rollouts']:.1f}", file=sys.stderr,
+              flush=True)
+        for rid in list(srv.rollouts):
+            srv.cancel(rid)
+        srv.pump(time.perf_counter())
+        torch.cuda.synchronize()
+        srv.pump(time.perf_counter())
+    top = rows[-1]
+    out = {
+        "metric": "serving: completed requests/s at Poisson load (one step + 128x128 render of a rollout "
+                  "per request); p50/p99 latency arrival-to-completion",
+        "value": top["completed_per_s"], "unit": "requests/s", "n_gpus": 1, "higher_is_better": True,
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded scenes standing in for nuPlan)",
+        "config": {"workload": f"serve: {args.serve_resident} resident rollouts from a pool of "
+                               f"{len(pool.scenes)} scenes (agents U{{8..128}}, road quads U{{500..8000}}), "
+                               f"128x128 forward view, rollout life {args.serve_life} requests, "
+                               f"{args.serve_streams} streams, {args.serve_seconds} s per rate",
+                   "seed": pool.seed},
+        "rates": rows,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +245,13 @@ def main():
     ap.add_argument("--tuned", default="", help="launch settings JSON from the autotuner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device-to-device copy (reference for HBM counters)")
+    ap.add_argument("--serve-rates", default="1000,2000,5000,10000,20000")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-resident", type=int, default=64)
+    ap.add_argument("--serve-pool", type=int, default=256)
+    ap.add_argument("--serve-life", type=int, default=1000)
+    ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--serve-budget-gib", type=int, default=16)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -160,6 +259,10 @@ def main():
               "inter-GPU communication and each GPU owns whole scenes, so N GPUs give N times the "
               "one-GPU figure by construction, which this benchmark does not claim.", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "serve":
+        serve_bench(args)
+        return
 
     import torch
     from paper_2606_19641_amd import gp

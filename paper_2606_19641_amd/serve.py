@@ -138,6 +138,7 @@ class Server:
         self.done: List[Request] = []
         self.batches: Dict[int, Tuple[List[Rollout], List[Request]]] = {}
         self.batch_sizes: List[int] = []
+        self._ready: Dict[int, Rollout] = {}      # admitted, a request pending, none in flight
         self._next_rollout = 0
         self._next_request = 0
         self._next_batch = 0
@@ -173,6 +174,7 @@ class Server:
             q = r.pending.popleft()
             q.status = CANCELLED
             self.done.append(q)
+        self._mark(r)
         self.close(rid)
 
     def _admit(self):
@@ -184,6 +186,13 @@ class Server:
             self.waiting.popleft()
             r.offset = off
             r.handle = self.ex.create(r.scene, off, r.footprint)
+            self._mark(r)
+
+    def _mark(self, r: Rollout):
+        if r.handle is not None and r.inflight is None and r.pending:
+            self._ready[r.id] = r
+        else:
+            self._ready.pop(r.id, None)
 
     def _maybe_release(self, r: Rollout):
         if r.closing and not r.pending and r.inflight is None:
@@ -214,6 +223,7 @@ class Server:
             return q
         q.actions = np.ascontiguousarray(a)
         r.pending.append(q)
+        self._mark(r)
         return q
 
     # -- the loop
@@ -230,17 +240,17 @@ class Server:
                 self.done.append(q)
                 if self.on_complete:
                     self.on_complete(q, r)
+                self._mark(r)
                 self._maybe_release(r)
         self._admit()
         launched = 0
         while self.ex.free_slots() > 0:
-            ready = [r for r in self.rollouts.values()
-                     if r.handle is not None and r.inflight is None and r.pending]
-            if not ready:
+            if not self._ready:
                 break
-            ready.sort(key=lambda r: r.pending[0].t_arrival)
-            ready = ready[:self.max_batch]
+            ready = sorted(self._ready.values(), key=lambda r: r.pending[0].t_arrival)[:self.max_batch]
             reqs = [r.pending.popleft() for r in ready]
+            for r in ready:
+                del self._ready[r.id]
             token = self._next_batch
             self._next_batch += 1
             for r, q in zip(ready, reqs):
