@@ -663,7 +663,11 @@ __device__ __noinline__ void raster_roads(Lds L, int W, int n)
     for (int t = threadIdx.x; t < n; t += blockDim.x) L.scan[t] = L.rtris[t].j1 - L.rtris[t].j0 + 1;
     __syncthreads();
     const int total = block_scan(L, n);
-    for (int gi = threadIdx.x; gi < total; gi += blockDim.x) {
+    // row items dealt to the waves in turn, so a partial last pass is shared
+    const int nwv = (int)blockDim.x >> 6, wv = (int)threadIdx.x >> 6, ln = (int)lane_id();
+    for (int g0 = 0; g0 < total; g0 += blockDim.x) {
+        const int gi = g0 + ln * nwv + wv;
+        if (gi >= total) continue;
         const int t = find_row_owner(L, n, gi);
         const TriGeo tg = lds_load(L.rtris + t);
         const int j = tg.j0 + (gi - L.scan[t]);
@@ -682,6 +686,9 @@ __device__ __noinline__ void raster_roads(Lds L, int W, int n)
 }
 
 // Fragments of listed triangles in rows [b0, b1) folded into the key band.
+// Row items are dealt to the waves in turn (item g goes to wave g mod the
+// wave count); each wave then fills its items' spans together, 64 pixels per
+// pass, so a long span is not left to one lane.
 __device__ __noinline__ void raster_tris(Lds L, int W, float cx, float cy, int n, int b0, int b1)
 {
     if (n <= 0) return;
@@ -691,19 +698,35 @@ __device__ __noinline__ void raster_tris(Lds L, int W, float cx, float cy, int n
     }
     __syncthreads();
     const int total = block_scan(L, n);
-    for (int gi = threadIdx.x; gi < total; gi += blockDim.x) {
-        const int t = find_row_owner(L, n, gi);
-        const TriRec tr = lds_load(L.tris + t);
-        const int j = max((int)tr.g.j0, b0) + (gi - L.scan[t]);
-        int xl, xr;
-        if (!row_span(tr.g, j, W, xl, xr)) continue;
-        const float dv = ((float)j + 0.5f) - cy;
-        lptr<unsigned long long> row = L.zb + (size_t)(j - b0) * W;
-        for (int i = xl; i <= xr; ++i) {
-            const float du = ((float)i + 0.5f) - cx;
-            const float invz = fmaf(tr.A, du, fmaf(tr.B, dv, tr.C));
-            if (!(invz > 0.0f)) continue;
-            lds_max64(row + i, ((unsigned long long)__float_as_uint(invz) << 32) | tr.keylo);
+    const int nwv = (int)blockDim.x >> 6, wv = (int)threadIdx.x >> 6, ln = (int)lane_id();
+    for (int g0 = 0; g0 < total; g0 += blockDim.x) {
+        const int gi = g0 + ln * nwv + wv;
+        int xl = 0, xr = -1, j = 0;
+        float A = 0.0f, B = 0.0f, Cc = 0.0f;
+        uint32_t key = 0u;
+        bool has = false;
+        if (gi < total) {
+            const int t = find_row_owner(L, n, gi);
+            const TriRec tr = lds_load(L.tris + t);
+            j = max((int)tr.g.j0, b0) + (gi - L.scan[t]);
+            has = row_span(tr.g, j, W, xl, xr);
+            A = tr.A; B = tr.B; Cc = tr.C; key = tr.keylo;
+        }
+        unsigned long long m = __ballot(has);
+        while (m) {
+            const int src = __ffsll((long long)m) - 1;
+            m &= m - 1ull;
+            const int sxl = __shfl(xl, src), sxr = __shfl(xr, src), sj = __shfl(j, src);
+            const float sA = __shfl(A, src), sB = __shfl(B, src), sC = __shfl(Cc, src);
+            const uint32_t skey = (uint32_t)__shfl((int)key, src);
+            const float dv = ((float)sj + 0.5f) - cy;
+            lptr<unsigned long long> row = L.zb + (size_t)(sj - b0) * W;
+            for (int i = sxl + ln; i <= sxr; i += 64) {
+                const float du = ((float)i + 0.5f) - cx;
+                const float invz = fmaf(sA, du, fmaf(sB, dv, sC));
+                if (!(invz > 0.0f)) continue;
+                lds_max64(row + i, ((unsigned long long)__float_as_uint(invz) << 32) | skey);
+            }
         }
     }
     __syncthreads();
@@ -866,6 +889,8 @@ __device__ __forceinline__ void clip_wave(const Cam &cam, const Poly &P, const S
         const float da = plane_dist(pl, cam, v), db = plane_dist(pl, cam, b);
         const bool act = lane < n;
         const bool ia = da >= 0.0f, ib = db >= 0.0f;
+        // every vertex inside: the walk would emit the polygon unchanged
+        if (__ballot(act && !ia) == 0ull) continue;
         const bool e0 = act && ia, e1 = act && (ia != ib);
         V3 r = v;
         if (e1) {
