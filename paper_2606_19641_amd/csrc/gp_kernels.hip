@@ -528,12 +528,16 @@ __device__ __forceinline__ bool row_span(const TriGeo &t, int j, int W, int &xl_
 enum { C_TRIS = 0, C_RTRIS, C_OVF, C_CLIPQ, C_SURV, C_PR0, C_PR1, C_PT0, C_PT1, C_BMIN, C_BMAX, C_NCNT = 16 };
 
 // List capacities: the general kernel keeps every triangle in one list of
-// batch_tris entries; the rgb kernel keeps road triangles in a list of
-// batch_tris entries and box triangles (far fewer) in one of batch_tris / 2.
-__host__ __device__ inline void list_caps(int fast, int batch_tris, int &tcap, int &rcap)
+// batch_tris entries.  The rgb kernel keeps box triangles (far fewer) in a
+// list of batch_tris / 2 entries and road triangles in a list that shares the
+// key band's memory: the band is idle while the road list is in use (setup
+// ends with a final flush of the road list, and the band-by-band redo after a
+// box-list overflow appends no road triangle).
+constexpr int kMaxRoadList = 1024;
+__host__ __device__ inline void list_caps(int fast, int batch_tris, int band_bytes, int &tcap, int &rcap)
 {
     tcap = fast ? max(128, batch_tris / 2) : batch_tris;
-    rcap = fast ? batch_tris : 0;
+    rcap = fast ? min(kMaxRoadList, band_bytes / 32) : 0;
 }
 
 // Pointers into LDS keep their address space in the type, so every access
@@ -716,9 +720,13 @@ __device__ __noinline__ void raster_tris(Lds L, int W, float cx, float cy, int n
         while (m) {
             const int src = __ffsll((long long)m) - 1;
             m &= m - 1ull;
-            const int sxl = __shfl(xl, src), sxr = __shfl(xr, src), sj = __shfl(j, src);
-            const float sA = __shfl(A, src), sB = __shfl(B, src), sC = __shfl(Cc, src);
-            const uint32_t skey = (uint32_t)__shfl((int)key, src);
+            // src is wave-uniform: read the item out of its lane with scalar reads
+            const int sxl = __builtin_amdgcn_readlane(xl, src), sxr = __builtin_amdgcn_readlane(xr, src);
+            const int sj = __builtin_amdgcn_readlane(j, src);
+            const float sA = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(A), src));
+            const float sB = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(B), src));
+            const float sC = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(Cc), src));
+            const uint32_t skey = (uint32_t)__builtin_amdgcn_readlane((int)key, src);
             const float dv = ((float)sj + 0.5f) - cy;
             lptr<unsigned long long> row = L.zb + (size_t)(sj - b0) * W;
             for (int i = sxl + ln; i <= sxr; i += 64) {
@@ -1278,14 +1286,13 @@ __device__ void render_view(const DevSim &s, const RenderOut &o, const LaunchCfg
 // LDS layout of a render workgroup for W x H images (sizes as render_lds_bytes)
 __device__ __forceinline__ void carve_lds(unsigned char *smem, Lds &L, int W, int H, const LaunchCfg &lc, int fast)
 {
-    list_caps(fast, lc.batch_tris, L.tcap, L.rcap);
+    list_caps(fast, lc.batch_tris, 8 * lc.band_rows * W, L.tcap, L.rcap);
     L.nw = (W + 63) >> 6;
     size_t off = 0;
     L.tris = (lptr<TriRec>)(smem + off);
     off += sizeof(TriRec) * (size_t)L.tcap;
-    L.rtris = (lptr<TriGeo>)(smem + off);
-    off += sizeof(TriGeo) * (size_t)L.rcap;
     L.zb = (lptr<unsigned long long>)(smem + off);
+    L.rtris = (lptr<TriGeo>)(smem + off);       // rgb kernel: shares the band's memory
     off += 8u * (size_t)lc.band_rows * W;
     L.road = (lptr<unsigned long long>)(smem + off);
     off += fast ? 8u * (size_t)H * L.nw : 0;
@@ -1432,9 +1439,9 @@ __global__ __launch_bounds__(BLOCK) void k_render_multi(const SimEntry *__restri
 size_t render_lds_bytes(int width, int height, const LaunchCfg &c, int fast)
 {
     int tcap, rcap;
-    list_caps(fast, c.batch_tris, tcap, rcap);
+    list_caps(fast, c.batch_tris, 8 * c.band_rows * width, tcap, rcap);
     const size_t nw = (size_t)(width + 63) / 64;
-    size_t b = sizeof(TriRec) * (size_t)tcap + sizeof(TriGeo) * (size_t)rcap +
+    size_t b = sizeof(TriRec) * (size_t)tcap +
                8u * (size_t)c.band_rows * width + 4u * (size_t)(max(tcap, rcap) + 4) +
                8u * (size_t)c.block_threads + 64u + 64u + 1024u + 16u + 256u;
     if (fast) b += 8u * (size_t)height * nw;

@@ -473,9 +473,9 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
     l.sched = GP_SCHED_PERSISTENT;
     l.band_rows = 64;
     while (l.band_rows > 8 && 8LL * l.band_rows * cfg->width > 32768) l.band_rows /= 2;
-    l.batch_tris = 512;
+    l.batch_tris = 256;
     l.block_threads = 256;
-    l.blocks_per_cu = 2;
+    l.blocks_per_cu = 3;
     sim->launch = l;
     if (check_lds(sim, l) != GP_OK) { delete sim; return GP_EINVAL; }
     e = hipStreamCreateWithFlags(&sim->capture_stream, hipStreamNonBlocking);
