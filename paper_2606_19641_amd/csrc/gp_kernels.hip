@@ -696,23 +696,55 @@ __device__ __noinline__ void raster_roads(Lds L, int W, int n)
 __device__ __noinline__ void raster_tris(Lds L, int W, float cx, float cy, int n, int b0, int b1)
 {
     if (n <= 0) return;
-    for (int t = threadIdx.x; t < n; t += blockDim.x) {
-        const int j0 = max((int)L.tris[t].g.j0, b0), j1 = min((int)L.tris[t].g.j1, b1 - 1);
-        L.scan[t] = max(0, j1 - j0 + 1);
-    }
-    __syncthreads();
-    const int total = block_scan(L, n);
     const int nwv = (int)blockDim.x >> 6, wv = (int)threadIdx.x >> 6, ln = (int)lane_id();
+    // Row counts per triangle and their prefix.  Up to 64 triangles every wave
+    // scans them in registers (no barrier); more go through the block scan.
+    const bool small = n <= 64;
+    int cnt = 0, incl = 0, total;
+    if (small) {
+        if (ln < n) {
+            const int j0 = max((int)L.tris[ln].g.j0, b0), j1 = min((int)L.tris[ln].g.j1, b1 - 1);
+            cnt = max(0, j1 - j0 + 1);
+        }
+        incl = cnt;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_up(incl, o);
+            if (ln >= o) incl += u;
+        }
+        total = __builtin_amdgcn_readlane(incl, 63);
+        if (ln >= n) incl = INT_MAX;
+    } else {
+        for (int t = threadIdx.x; t < n; t += blockDim.x) {
+            const int j0 = max((int)L.tris[t].g.j0, b0), j1 = min((int)L.tris[t].g.j1, b1 - 1);
+            L.scan[t] = max(0, j1 - j0 + 1);
+        }
+        __syncthreads();
+        total = block_scan(L, n);
+    }
     for (int g0 = 0; g0 < total; g0 += blockDim.x) {
         const int gi = g0 + ln * nwv + wv;
+        int t = 0, start = 0;
+        if (small) {
+            // owner: the number of triangles whose inclusive prefix is <= gi
+            // (branchless search over the 64 lanes, every lane active)
+#pragma unroll
+            for (int step = 32; step > 0; step >>= 1)
+                if (__shfl(incl, t + step - 1) <= gi) t += step;
+            const int tt = min(t, 63);
+            start = __shfl(incl, tt) - __shfl(cnt, tt);
+        }
         int xl = 0, xr = -1, j = 0;
         float A = 0.0f, B = 0.0f, Cc = 0.0f;
         uint32_t key = 0u;
         bool has = false;
         if (gi < total) {
-            const int t = find_row_owner(L, n, gi);
+            if (!small) {
+                t = find_row_owner(L, n, gi);
+                start = L.scan[t];
+            }
             const TriRec tr = lds_load(L.tris + t);
-            j = max((int)tr.g.j0, b0) + (gi - L.scan[t]);
+            j = max((int)tr.g.j0, b0) + (gi - start);
             has = row_span(tr.g, j, W, xl, xr);
             A = tr.A; B = tr.B; Cc = tr.C; key = tr.keylo;
         }
