@@ -242,7 +242,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--tuned", default="", help="launch settings JSON from the autotuner")
+    ap.add_argument("--tuned", default="", help="launch settings JSON (skips the autotuner)")
+    ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch settings")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device-to-device copy (reference for HBM counters)")
     ap.add_argument("--serve-rates", default="1000,2000,5000,10000,20000")
@@ -276,6 +277,10 @@ def main():
     sim = gp.Sim(w.scenes, w.camera, pal, device="cuda:0")
     if args.tuned:
         sim.set_launch(**json.loads(args.tuned))
+    elif not args.no_tune:
+        # the autotuner: fastest of the result-identical launch settings (a7)
+        from paper_2606_19641_amd import tune
+        tune.tune(sim, w.scenes, space=tune.BENCH_SPACE, reps=5, cache=None)
     launch = sim.get_launch()
     launch["sched"] = gp.SCHED_PERSISTENT
     sim.set_launch(**launch)

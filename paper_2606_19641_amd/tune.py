@@ -22,6 +22,14 @@ DEFAULT_SPACE = {
     "blocks_per_cu": (1, 2, 3, 4),
 }
 
+# the short search the benchmark runs before timing (a few hundred renders)
+BENCH_SPACE = {
+    "band_rows": (16, 32),
+    "batch_tris": (256, 512),
+    "block_threads": (256,),
+    "blocks_per_cu": (2, 3, 4),
+}
+
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_launch.json")
 
 
