@@ -9,7 +9,7 @@
 namespace gp {
 
 constexpr int kMaxCams = 4;
-constexpr int kBinQuads = 64;            // road strips per culling bin
+constexpr int kBinQuads = 16;            // road strips per culling bin
 constexpr int kMaxPrims = 1 << 23;       // primitives per scene (key packs 23 bits)
 constexpr int kQueues = 8;               // work-queue segments, one per XCD of the MI355X
 

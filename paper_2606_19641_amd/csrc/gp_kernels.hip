@@ -499,7 +499,12 @@ __device__ __forceinline__ bool row_span(const TriGeo &t, int j, int W, int &xl_
                 continue;
             }
             const double D = 256.0 * (double)dY;
-            const double q = (P - tk) / D;
+            // estimate of (P - tk) / D from a binary32 reciprocal: relative
+            // error below 2^-21, so within 1 of the quotient wherever the
+            // quotient lies in [-2, W + 1]; outside that range the clamp
+            // below decides, and the exact test that follows moves the
+            // estimate by at most one to the exact boundary
+            const double q = (double)((float)(P - tk) * __builtin_amdgcn_rcpf((float)D));
             if (dY > 0) {            // E decreases with i: i <= q
                 double ic = fmin(fmax(floor(q), -1.0), (double)W);
                 if (P - D * ic < tk) ic -= 1.0;
