@@ -530,7 +530,8 @@ __device__ __forceinline__ bool row_span(const TriGeo &t, int j, int W, int &xl_
 // LDS counters: list lengths, overflow flag, clip-queue and survivor counts,
 // pending triangles of the current round (two parities, roads / others), and
 // the row range touched by box triangles (rgb kernel)
-enum { C_TRIS = 0, C_RTRIS, C_OVF, C_CLIPQ, C_SURV, C_PR0, C_PR1, C_PT0, C_PT1, C_BMIN, C_BMAX, C_NCNT = 16 };
+enum { C_TRIS = 0, C_RTRIS, C_OVF, C_CLIPQ, C_SURV, C_PR0, C_PR1, C_PT0, C_PT1, C_BMIN, C_BMAX, C_CLIPQ1,
+       C_NCNT = 16 };
 
 // List capacities: the general kernel keeps every triangle in one list of
 // batch_tris entries.  The rgb kernel keeps box triangles (far fewer) in a
@@ -558,7 +559,7 @@ struct Lds {
     lptr<unsigned long long> road;  // rgb kernel: per-row road coverage bits [H][nw]
     lptr<int32_t> scan;             // [cap + 4] row-count prefix
     lptr<int32_t> surv;             // [B] surviving boxes / bins
-    lptr<int32_t> clipq;            // [B] candidates that need clipping
+    lptr<int32_t> clipq;            // [2][B] candidates that need clipping, a ring per round parity
     lptr<int32_t> cnt;              // counters (C_*)
     lptr<int32_t> wsum;             // [16] per-wave partial sums
     lptr<uint32_t> pal;             // [256] RGB as u32
@@ -804,13 +805,16 @@ __device__ __forceinline__ void flush_roads(const Cam &cam, Lds &L)
 // Called by every thread after a barrier.  The decision is read by every
 // thread before the second barrier and acted on only after it, so a wave that
 // appends right after this call cannot change another wave's decision.
-__device__ __forceinline__ void make_room(const Cam &cam, Lds &L, const Sink &K, int need_r, int need_t)
+// Returns the road list's length after the call (the same for every thread).
+__device__ __forceinline__ int make_room(const Cam &cam, Lds &L, const Sink &K, int need_r, int need_t)
 {
-    const bool fr = K.fast && L.cnt[C_RTRIS] + need_r > L.rcap;
+    const int cr = L.cnt[C_RTRIS];
+    const bool fr = K.fast && cr + need_r > L.rcap;
     const bool ft = K.flush_tris && L.cnt[C_TRIS] + need_t > L.tcap;
     __syncthreads();
     if (fr) flush_roads(cam, L);
     if (ft) flush_tris(cam, L, K);
+    return fr ? 0 : cr;
 }
 
 // Append with one LDS atomic per wave; lanes whose triangle does not fit
@@ -1012,6 +1016,14 @@ __device__ void setup_source(const DevSim &s, const SceneRec &sc, const Cam &cam
     // flushing a round adds at most 2 triangles per lane, so keep it below half
     const int fcap = road ? L.rcap : L.tcap;
     const int per_round = can_flush ? max(1, min(B, fcap / 2)) : B;
+    // The clip queue is two rings of B entries, one per round parity, whose
+    // counters only grow during a view: a round queues at most B candidates
+    // and clips them before the round ends.  A round reads its parity's
+    // counter after its last barrier; the next append to that ring comes two
+    // rounds later, after the next round's barrier, so every thread reads the
+    // same value without a barrier at the end of the round.
+    int head[2] = {L.cnt[C_CLIPQ], L.cnt[C_CLIPQ1]};
+    int r_up = L.cnt[C_RTRIS];                   // bound on the road list's length
     for (int u0 = 0; u0 < n_units; u0 += B) {
         // ---- cull units, compact the survivors
         // survivors are recorded as the agent index (boxes) or as the bin's
@@ -1088,19 +1100,28 @@ __device__ void setup_source(const DevSim &s, const SceneRec &sc, const Cam &cam
             bool v0 = false, v1 = false, clip = false;
             if (live) fast_poly<!road>(cam, P, K, t0, v0, t1, v1, clip);
             if (clip) {
-                const int q = lds_add(L.cnt + C_CLIPQ, 1);
-                L.clipq[q] = code;
+                const int q = lds_add(L.cnt + (par ? C_CLIPQ1 : C_CLIPQ), 1);
+                L.clipq[par * B + q % B] = code;
             }
             if (can_flush) {
-                // count this round's triangles, flush first if they would not fit
-                const int nr = __popcll(__ballot(v0 && road)) + __popcll(__ballot(v1 && road));
-                const int nt = __popcll(__ballot(v0 && !road)) + __popcll(__ballot(v1 && !road));
-                if (lane_id() == 0 && (nr | nt)) {
-                    lds_add(L.cnt + C_PR0 + par, nr);
-                    lds_add(L.cnt + C_PT0 + par, nt);
+                // While the bound r_up on the road list's length leaves room
+                // for two triangles per candidate, the round needs no check
+                // (and no barrier); otherwise count this round's triangles and
+                // flush first if they would not fit.  r_up is computed from
+                // values every thread sees alike, so the choice is uniform.
+                if (K.fast && !K.flush_tris && r_up + 2 * per_round <= L.rcap) {
+                    r_up += 2 * per_round;
+                } else {
+                    const int nr = __popcll(__ballot(v0 && road)) + __popcll(__ballot(v1 && road));
+                    const int nt = __popcll(__ballot(v0 && !road)) + __popcll(__ballot(v1 && !road));
+                    if (lane_id() == 0 && (nr | nt)) {
+                        lds_add(L.cnt + C_PR0 + par, nr);
+                        lds_add(L.cnt + C_PT0 + par, nt);
+                    }
+                    __syncthreads();
+                    const int pr = L.cnt[C_PR0 + par];
+                    r_up = make_room(cam, L, K, pr, L.cnt[C_PT0 + par]) + pr;
                 }
-                __syncthreads();
-                make_room(cam, L, K, L.cnt[C_PR0 + par], L.cnt[C_PT0 + par]);
                 if (tid == 0) { L.cnt[C_PR0 + (par ^ 1)] = 0; L.cnt[C_PT0 + (par ^ 1)] = 0; }
             }
             if (road) append_wave(L, C_RTRIS, v0, t0, v1, t1);
@@ -1110,22 +1131,22 @@ __device__ void setup_source(const DevSim &s, const SceneRec &sc, const Cam &cam
                 if (v1) { lds_min(L.cnt + C_BMIN, (int)t1.g.j0); lds_max(L.cnt + C_BMAX, (int)t1.g.j1); }
             }
             __syncthreads();
-            const int nq = L.cnt[C_CLIPQ];
+            // this round's clip candidates are entries [head, tail) of its parity's ring
+            const int tail = L.cnt[par ? C_CLIPQ1 : C_CLIPQ], nq = tail - head[par];
             // the clipper may emit up to kMaxTrisPerCand triangles per candidate
             const int chunk = can_flush ? max(1, fcap / kMaxTrisPerCand) : B;
             // one wave per queued candidate
             for (int q0 = 0; q0 < nq; q0 += chunk) {
                 const int qn = min(chunk, nq - q0);
-                if (can_flush) make_room(cam, L, K, qn * kMaxTrisPerCand, qn * kMaxTrisPerCand);
+                if (can_flush) r_up = make_room(cam, L, K, qn * kMaxTrisPerCand, qn * kMaxTrisPerCand) + qn * kMaxTrisPerCand;
                 for (int q = q0 + (tid >> 6); q < q0 + qn; q += B >> 6) {
                     Poly Q;
-                    build_code(s, sc, cam, L.clipq[q], Q);
+                    build_code(s, sc, cam, L.clipq[par * B + (head[par] + q) % B], Q);
                     clip_wave(cam, Q, K, L);
                 }
                 __syncthreads();
             }
-            if (tid == 0) L.cnt[C_CLIPQ] = 0;
-            __syncthreads();
+            head[par] = tail;
         }
     }
 }
@@ -1338,7 +1359,7 @@ __device__ __forceinline__ void carve_lds(unsigned char *smem, Lds &L, int W, in
     L.surv = (lptr<int32_t>)(smem + off);
     off += 4u * blockDim.x;
     L.clipq = (lptr<int32_t>)(smem + off);
-    off += 4u * blockDim.x;
+    off += 8u * blockDim.x;
     L.cnt = (lptr<int32_t>)(smem + off);
     off += 4u * 16;
     L.wsum = (lptr<int32_t>)(smem + off);
@@ -1480,7 +1501,7 @@ size_t render_lds_bytes(int width, int height, const LaunchCfg &c, int fast)
     const size_t nw = (size_t)(width + 63) / 64;
     size_t b = sizeof(TriRec) * (size_t)tcap +
                8u * (size_t)c.band_rows * width + 4u * (size_t)(max(tcap, rcap) + 4) +
-               8u * (size_t)c.block_threads + 64u + 64u + 1024u + 16u + 256u;
+               12u * (size_t)c.block_threads + 64u + 64u + 1024u + 16u + 256u;
     if (fast) b += 8u * (size_t)height * nw;
     return b;
 }
