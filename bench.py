@@ -66,6 +66,8 @@ def _workload(args):
     from paper_2606_19641_amd import scenegen as g
     if args.workload == "sweep":
         return g.workload("sweep", resolution=args.res)
+    if args.workload == "student":
+        return g.workload("student", resolution=args.res if args.res in (210, 434) else 210)
     return g.workload(args.workload)
 
 
@@ -237,7 +239,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="uniform", choices=["small", "uniform", "uneven", "sweep", "serve"])
+    ap.add_argument("--workload", default="uniform",
+                    choices=["small", "uniform", "uneven", "sweep", "serve", "student"])
     ap.add_argument("--res", type=int, default=128)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -1201,18 +1201,48 @@ __device__ void resolve_fast(const DevSim &s, const Cam &cam, Lds &L, uint8_t *r
             out[2] = ((c2 >> 16) & 0xFFu) | (c3 << 8);
         }
     } else {
-        const int npix = (r1 - r0) * W;
-        for (int p = threadIdx.x; p < npix; p += blockDim.x) {
-            const int j = r0 + p / W, i = p - (p / W) * W;
+        // rows are not a whole number of dwords: walk the rows' pixels as one
+        // flat run, 4 pixels (3 dwords) per thread; a group may cross a row
+        // end.  The whole groups need a 4-byte aligned image (W * H a multiple
+        // of 4); the partial groups at the run's two ends are written bytewise.
+        auto pixel = [&](int j, int i) -> uint32_t {
             const float dv = ((float)j + 0.5f) - cam.cy;
             const float rz = fmaf(cam.road.B, dv, cam.road.C);
             const bool road = rz > 0.0f && ((L.road[(size_t)j * L.nw + (i >> 6)] >> (i & 63)) & 1ull);
             lptr<unsigned long long> kp = L.zb + (KEYS ? (size_t)(j - zb0) * W + i : 0);
-            const uint32_t c = color_of(road, rz, kp, 0);
-            uint8_t *dst = rgb + 3 * (img + (int64_t)j * W + i);
+            return color_of(road, rz, kp, 0);
+        };
+        auto put_bytes = [&](int p) {               // flat pixel p of the run's rows
+            const int j = p / W, i = p - j * W;
+            const uint32_t c = pixel(j, i);
+            uint8_t *dst = rgb + 3 * (img + (int64_t)p);
             dst[0] = (uint8_t)c;
             dst[1] = (uint8_t)(c >> 8);
             dst[2] = (uint8_t)(c >> 16);
+        };
+        const int pbeg = r0 * W, pend = r1 * W;
+        const bool dwords = ((W * cam.H) & 3) == 0;
+        const int g0 = dwords ? (pbeg + 3) >> 2 : 0, g1 = dwords ? pend >> 2 : 0;
+        if (g0 < g1) {
+            uint32_t *base = reinterpret_cast<uint32_t *>(rgb + 3 * img);
+            for (int g = g0 + (int)threadIdx.x; g < g1; g += blockDim.x) {
+                int j = (4 * g) / W, i = 4 * g - j * W;
+                uint32_t c[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    c[k] = pixel(j, i);
+                    if (++i == W) { i = 0; ++j; }
+                }
+                uint32_t *out = base + 3 * (size_t)g;
+                out[0] = (c[0] & 0xFFFFFFu) | (c[1] << 24);
+                out[1] = ((c[1] >> 8) & 0xFFFFu) | (c[2] << 16);
+                out[2] = ((c[2] >> 16) & 0xFFu) | (c[3] << 8);
+            }
+            const int head = 4 * g0 - pbeg, tail = pend - 4 * g1;   // 0..3 pixels each
+            if ((int)threadIdx.x < head) put_bytes(pbeg + (int)threadIdx.x);
+            else if ((int)threadIdx.x >= 4 && (int)threadIdx.x < 4 + tail) put_bytes(4 * g1 + (int)threadIdx.x - 4);
+        } else {
+            for (int p = pbeg + (int)threadIdx.x; p < pend; p += blockDim.x) put_bytes(p);
         }
     }
 }

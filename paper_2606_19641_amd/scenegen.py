@@ -86,6 +86,10 @@ class Camera:
 
 FRONT = ((1.0, 0.0),)
 FRONT_AND_SIDES = ((1.0, 0.0), (0.5, 0.8660254), (0.5, -0.8660254))   # 0, +60, -60 degrees
+# the student's rig (App. B): front, front-left, front-right, rear; the paper
+# gives no yaw offsets, so the side cameras take +-60 degrees as above
+STUDENT_RIG = ((1.0, 0.0), (0.5, 0.8660254), (0.5, -0.8660254), (-1.0, 0.0))
+STUDENT_RESOLUTIONS = ((210, 126), (434, 252))
 
 
 def default_palette() -> np.ndarray:
@@ -273,7 +277,7 @@ def batch_actions(seed: int, step: int, scenes: List[Scene]) -> np.ndarray:
 # ---------------------------------------------------------------- workloads
 
 SEEDS = {"small": 0x5EED0001, "uniform": 0x5EED0002, "uneven": 0x5EED0003,
-         "sweep": 0x5EED0004, "serve": 0x5EED0005}
+         "sweep": 0x5EED0004, "serve": 0x5EED0005, "student": 0x5EED0006}
 
 
 @dataclasses.dataclass
@@ -301,6 +305,8 @@ def workload(name: str, resolution: int | None = None, n_scenes: int | None = No
     uneven:  256 scenes, agents U{4..128}, quads U{500..8000}, 3 cameras, 128x128
     sweep:   64 scenes x 64 agents, 4,000 quads, one camera at `resolution`
     serve:   pool of scenes with agents U{8..128}, quads U{500..8000}, 128x128
+    student: 64 scenes x 32 agents, 2,000 quads, the 4-camera student rig at
+             210x126 (resolution=210) or 434x252 (resolution=434)
     `n_scenes` truncates a workload (used for small samples of a large one).
     """
     seed = SEEDS[name]
@@ -325,6 +331,12 @@ def workload(name: str, resolution: int | None = None, n_scenes: int | None = No
         na, nq = uneven_counts(seed, n, agents=(8, 128))
         scenes = [make_scene(seed, s, int(na[s]), int(nq[s])) for s in range(n)]
         cam, steps = camera_for(128), 100
+    elif name == "student":
+        n = 64 if n_scenes is None else n_scenes
+        scenes = [make_scene(seed, s, 32, 2000) for s in range(n)]
+        h = dict(STUDENT_RESOLUTIONS)[210 if resolution is None else resolution]
+        w = 210 if resolution is None else resolution
+        cam, steps = Camera(width=w, height=h, focal_px=w / 2.0, cam_dirs=STUDENT_RIG), 100
     else:
         raise KeyError(name)
     if n_scenes is not None and name == "small":

@@ -226,6 +226,25 @@ def test_image_pointer_alignment_and_pattern_widths():
         _compare_views(scenes, cam, pal, ref.cpu().numpy(), None, None, picks)
 
 
+def test_student_rig_four_cameras_both_resolutions():
+    """The student's rig (App. B): front, front-left, front-right and rear
+    cameras at 210x126 and 434x252 (rows not a whole number of dwords)."""
+    scenes = [g.crowded_scene(71, n_agents=16, n_roads=60), g.workload("student", n_scenes=1).scenes[0]]
+    scenes[0].road_color[:] = 1
+    pal = g.mixed_palette()
+    for w, h in g.STUDENT_RESOLUTIONS:
+        cam = g.Camera(width=w, height=h, focal_px=w / 2.0, cam_dirs=g.STUDENT_RIG)
+        sim = _sim(scenes, cam, pal)
+        fast, _, _ = sim.render()
+        gen, depth, prim = sim.render(depth=True, primid=True)
+        torch.cuda.synchronize()
+        assert torch.equal(fast, gen)
+        picks = [(0, a, k) for a in range(0, 16, 5) for k in range(4)]
+        picks += [(1, a, k) for a in range(0, scenes[1].n_agents, 11) for k in range(4)]
+        _compare_views(scenes, cam, pal, fast.cpu().numpy(), depth.cpu().numpy(), prim.cpu().numpy(), picks,
+                       f"{w}x{h}")
+
+
 def test_degenerate_scenes():
     """A lone agent (empty view), no roads, a huge road quad (guard band),
     zero-area and clockwise road strips, a flat box, boxes behind the camera."""
