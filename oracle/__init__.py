@@ -53,7 +53,12 @@ def lib():
             build()
         L = C.CDLL(_LIB)
         L.gpo_sincos.argtypes = [C.c_float, C.POINTER(C.c_float), C.POINTER(C.c_float)]
-        L.gpo_step.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_float, C.c_void_p]
+        L.gpo_step.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_float, C.c_void_p,
+                               C.c_void_p]
+        L.gpo_overlap.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.gpo_in_strip.argtypes = [C.c_void_p, C.c_float, C.c_float]
+        L.gpo_infractions.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                                      C.c_void_p]
         L.gpo_render_view.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.c_int, C.c_float,
                                       C.c_float, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.POINTER(C.c_longlong)]
@@ -73,14 +78,42 @@ def sincos(t: float):
     return np.float32(s.value), np.float32(c.value)
 
 
-def step(state: np.ndarray, dims: np.ndarray, act: np.ndarray, dt: float = 0.1):
-    """One kinematic step; returns (new_state [n,4], cos/sin psi [n,2]); inputs untouched."""
+def step(state: np.ndarray, dims: np.ndarray, act: np.ndarray, dt: float = 0.1, halted=None):
+    """One kinematic step; returns (new_state [n,4], cos/sin psi [n,2]); inputs untouched.
+    Agents flagged in `halted` (uint8 [n]) keep their state."""
     st = np.ascontiguousarray(state, dtype=np.float32).copy()
     dm = np.ascontiguousarray(dims, dtype=np.float32)
     ac = np.ascontiguousarray(act, dtype=np.float32)
+    hl = None if halted is None else np.ascontiguousarray(halted, dtype=np.uint8)
     cs = np.empty((st.shape[0], 2), dtype=np.float32)
-    lib().gpo_step(st.shape[0], _ptr(st), _ptr(dm), _ptr(ac), C.c_float(dt), _ptr(cs))
+    lib().gpo_step(st.shape[0], _ptr(st), _ptr(dm), _ptr(ac), C.c_float(dt), _ptr(cs), _ptr(hl))
     return st, cs
+
+
+def overlap(state_i, dims_i, state_j, dims_j) -> bool:
+    """Footprints of two agents overlap with positive area (separating axes)."""
+    a = [np.ascontiguousarray(x, dtype=np.float32) for x in (state_i, dims_i, state_j, dims_j)]
+    return bool(lib().gpo_overlap(*[_ptr(x) for x in a]))
+
+
+def in_strip(quad, px: float, py: float) -> bool:
+    """The point lies in the road strip (on or inside each edge, either winding)."""
+    q = np.ascontiguousarray(quad, dtype=np.float32).reshape(8)
+    return bool(lib().gpo_in_strip(_ptr(q), C.c_float(px), C.c_float(py)))
+
+
+def infractions(scene_state, dims, road_xy, halted):
+    """Collision / off-road check of one scene: returns (state with newly halted
+    agents' speed zeroed, halted, flags) with flags bit 0 collision, bit 1
+    off-road, bit 2 halted; inputs untouched."""
+    st = np.ascontiguousarray(scene_state, dtype=np.float32).copy()
+    dm = np.ascontiguousarray(dims, dtype=np.float32)
+    rx = np.ascontiguousarray(road_xy, dtype=np.float32).reshape(-1, 8)
+    hl = np.ascontiguousarray(halted, dtype=np.uint8).copy()
+    fl = np.zeros(st.shape[0], dtype=np.uint8)
+    lib().gpo_infractions(st.shape[0], _ptr(st), _ptr(dm), rx.shape[0], _ptr(rx) if rx.size else None,
+                          _ptr(hl), _ptr(fl))
+    return st, hl, fl
 
 
 def cover_tri(X, Y, W: int, H: int, count=None) -> np.ndarray:

@@ -97,10 +97,17 @@ static float clampf(float x, float lo, float hi) { return fminf(fmaxf(x, lo), hi
  *   kappa = sin(delta) / (cos(delta) * 0.6 L)        (App. A wheelbase)
  *   psi' = psi + v' dt kappa, wrapped once into (-pi, pi]
  *   x' = x + v' dt cos psi',  y' = y + v' dt sin psi'
+ * An agent flagged in `halted` (optional) keeps its state (App. A: an agent
+ * that commits an infraction is halted in place).
  */
-void gpo_step(int n, float *state, const float *dims, const float *act, float dt, float *cs_out)
+void gpo_step(int n, float *state, const float *dims, const float *act, float dt, float *cs_out,
+              const uint8_t *halted)
 {
     for (int i = 0; i < n; ++i) {
+        if (halted && halted[i]) {              /* halted in place: state unchanged */
+            if (cs_out) gpo_sincos(state[4 * i + 2], &cs_out[2 * i + 1], &cs_out[2 * i + 0]);
+            continue;
+        }
         float x = state[4 * i + 0], y = state[4 * i + 1];
         float psi = state[4 * i + 2], v = state[4 * i + 3];
         float L = dims[3 * i + 0];
@@ -490,4 +497,82 @@ long long gpo_render_view(const gpo_scene *sc, const gpo_camera *cam, int ego, f
     }
     if (frags_out) *frags_out = t.frags;
     return ntri;
+}
+
+
+/* ----------------------------------------------------------- infractions
+ * App. A ("halted in place ... continues to receive observations"): an agent
+ * that collides with another vehicle or leaves the drivable area is halted,
+ * its speed zeroed, for the rest of the episode.  The paper gives no
+ * geometric definitions; the readings are:
+ *   - collision: the two footprints (length x width rectangles about the box
+ *     centre, along the heading) overlap with positive area.  Tested with the
+ *     separating axes of both rectangles; boxes that only touch do not collide.
+ *   - off-road: the agent's centre lies in no road strip of its scene (a strip
+ *     contains the point when the point is on the inner side of, or on, each
+ *     of its four edges, in either winding).
+ * Heading cos/sin come from gpo_sincos.  binary32 throughout, fused
+ * operations written as fmaf.
+ *
+ * One scene: state [n][4] (v zeroed for newly halted agents), dims [n][3],
+ * roads [n_roads][4][2], halted [n] (in/out), flags [n] (out):
+ * bit 0 collision now, bit 1 off-road now, bit 2 halted after this check.
+ */
+static float dot2(float ax, float ay, float bx, float by) { return fmaf(ax, bx, ay * by); }
+
+/* half-extent of a rectangle (half sizes hl along u, hw along v) on axis a */
+static float reach(float hl, float hw, float ux, float uy, float ax, float ay)
+{
+    /* v = (-uy, ux) */
+    return fmaf(hl, fabsf(dot2(ux, uy, ax, ay)), hw * fabsf(dot2(-uy, ux, ax, ay)));
+}
+
+int gpo_overlap(const float *si, const float *di, const float *sj, const float *dj)
+{
+    float ci, sni, cj, snj;
+    gpo_sincos(si[2], &sni, &ci);
+    gpo_sincos(sj[2], &snj, &cj);
+    const float hli = 0.5f * di[0], hwi = 0.5f * di[1], hlj = 0.5f * dj[0], hwj = 0.5f * dj[1];
+    const float dx = sj[0] - si[0], dy = sj[1] - si[1];
+    const float ax[4] = {ci, -sni, cj, -snj}, ay[4] = {sni, ci, snj, cj};
+    for (int k = 0; k < 4; ++k) {
+        const float ri = reach(hli, hwi, ci, sni, ax[k], ay[k]);
+        const float rj = reach(hlj, hwj, cj, snj, ax[k], ay[k]);
+        if (fabsf(dot2(dx, dy, ax[k], ay[k])) >= ri + rj) return 0;   /* separated (or touching) */
+    }
+    return 1;
+}
+
+int gpo_in_strip(const float *q, float px, float py)
+{
+    int pos = 0, neg = 0;
+    for (int k = 0; k < 4; ++k) {
+        const int k1 = (k + 1) & 3;
+        const float ex = q[2 * k1] - q[2 * k], ey = q[2 * k1 + 1] - q[2 * k + 1];
+        const float wx = px - q[2 * k], wy = py - q[2 * k + 1];
+        const float c = fmaf(ex, wy, -(ey * wx));
+        pos |= c > 0.0f;
+        neg |= c < 0.0f;
+    }
+    return !(pos && neg);
+}
+
+void gpo_infractions(int n, float *state, const float *dims, int n_roads, const float *roads,
+                     uint8_t *halted, uint8_t *flags)
+{
+    for (int i = 0; i < n; ++i) {
+        int col = 0;
+        for (int j = 0; j < n && !col; ++j)
+            if (j != i) col = gpo_overlap(state + 4 * i, dims + 3 * i, state + 4 * j, dims + 3 * j);
+        int on = 0;
+        for (int r = 0; r < n_roads && !on; ++r) on = gpo_in_strip(roads + 8 * r, state[4 * i], state[4 * i + 1]);
+        flags[i] = (uint8_t)(col | (on ? 0 : 2));
+    }
+    for (int i = 0; i < n; ++i) {
+        if (flags[i]) halted[i] = 1;
+        if (halted[i]) {
+            state[4 * i + 3] = 0.0f;
+            flags[i] |= 4;
+        }
+    }
 }
