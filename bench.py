@@ -320,6 +320,19 @@ def main():
     torch.cuda.synchronize()
     render_ms = float(np.mean([a.elapsed_time(b) for a, b in rev]))
 
+    # ---- the infraction check (collision / off-road, halting) on the same state,
+    # timed apart: it is not part of the step + render graph
+    flags = torch.empty(sim.n_agents, dtype=torch.uint8, device=dev)
+    state0 = sim.get_state()
+    iev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
+    for a, b in iev:
+        a.record(stream)
+        sim.check_infractions(flags)
+        b.record(stream)
+    torch.cuda.synchronize()
+    infr_ms = float(np.mean([a.elapsed_time(b) for a, b in iev]))
+    sim.set_state(state0)               # the check halted offenders: restore the state
+
     # ---- plain: per-scene launches of the same kernels, no graph
     plain = None
     if not args.no_plain:
@@ -373,6 +386,7 @@ def main():
         "p50_step_ms": float(np.percentile(lat_ms, 50)),
         "p99_step_ms": float(np.percentile(lat_ms, 99)),
         "render_kernel_ms": render_ms,
+        "infraction_check_ms": infr_ms,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": meas["traffic"] if meas else None,
                      "kernel": "k_render", "bytes_per_launch": rb,

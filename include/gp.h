@@ -134,7 +134,8 @@ gp_status gp_sim_render(gp_sim *sim, uint8_t *d_rgb, float *d_depth, int32_t *d_
 gp_status gp_sim_step_render_graph(gp_sim *sim, const float *d_actions, uint8_t *d_rgb, void *stream);
 
 /* Copy the agent state [total_agents][4] out of / into the sim (device to
- * device, stream-ordered).  set_state also refreshes the heading cosines. */
+ * device, stream-ordered).  set_state also refreshes the heading cosines and
+ * clears every agent's halted flag (a new episode). */
 gp_status gp_sim_get_state(gp_sim *sim, float *d_dst, void *stream);
 gp_status gp_sim_set_state(gp_sim *sim, const float *d_src, void *stream);
 
@@ -163,6 +164,24 @@ int64_t gp_batch_required_bytes(int32_t n_sims, int64_t n_agents, int64_t n_view
 gp_status gp_batch_step_render(gp_sim *const *sims, int32_t n_sims, const float *const *h_actions,
                                uint8_t *const *d_rgb, void *d_ws, int64_t ws_bytes, void *h_staging,
                                int64_t staging_bytes, void *stream);
+
+/* Infraction check of the current state (App. A, "Action Space and
+ * Dynamics" / episode rules: an agent that collides or leaves the drivable
+ * area is halted in place, speed zeroed, and keeps being observed).  An agent
+ * collides when its footprint (length x width rectangle about the box centre,
+ * along the heading) overlaps another agent's of the same scene with positive
+ * area; it is off-road when its centre lies in no road strip of its scene.
+ * Offending agents become halted: their speed is set to 0 and gp_sim_step
+ * leaves them in place until gp_sim_set_state.  d_flags (optional, device
+ * uint8 [total_agents]) receives bit 0 collision, bit 1 off-road (this check),
+ * bit 2 halted (after it).  Stream-ordered. */
+gp_status gp_sim_check_infractions(gp_sim *sim, uint8_t *d_flags, void *stream);
+
+/* Fork: make dst's dynamic state (agent state, heading cosines, halted flags)
+ * a copy of src's (the paper rolls a teacher out in a forked copy of the
+ * simulator, Sec. 3 "Pixel-based student training").  Both sims must have
+ * been created over the same scenes.  Device-to-device, stream-ordered. */
+gp_status gp_sim_fork(gp_sim *dst, const gp_sim *src, void *stream);
 
 int64_t gp_sim_num_views(const gp_sim *sim);
 int64_t gp_sim_num_agents(const gp_sim *sim);

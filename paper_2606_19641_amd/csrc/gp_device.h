@@ -57,6 +57,8 @@ struct DevSim {
     int32_t road_color_uniform;   // 1 if every road strip has the colour road_color0
     int32_t road_color0;
     float road_zmax;          // no pixel sample sees the road plane beyond this depth
+    uint8_t *halted;          // [A] 1 once the agent committed an infraction (frozen in place)
+    uint8_t *infr;            // [A] infractions found by the last check (bit 0 collision, 1 off-road)
     float cam_dir[kMaxCams][2];
     float focal, cam_height, z_near, z_far, dt;
 };
@@ -84,7 +86,10 @@ struct LaunchCfg {
 // Host-side launch helpers (defined in gp_kernels.hip).
 hipError_t launch_step(const DevSim &s, const float *actions, int agent_begin, int agent_count,
                        hipStream_t st);
-hipError_t launch_cs(const DevSim &s, hipStream_t st);
+hipError_t launch_cs(const DevSim &s, int clear_halted, hipStream_t st);
+// infraction check of every agent; flags_out (optional) [A] gets bit 0
+// collision, bit 1 off-road, bit 2 halted after the check
+hipError_t launch_infractions(const DevSim &s, int max_agents, uint8_t *flags_out, hipStream_t st);
 // fast = 1: rgb-only kernel for a uniform road colour; fast = 0: general kernel
 hipError_t launch_render(const DevSim &s, const RenderOut &o, const LaunchCfg &c, int fast,
                          int persistent, int view_begin, int grid, hipStream_t st);

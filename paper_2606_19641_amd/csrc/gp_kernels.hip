@@ -73,6 +73,7 @@ __device__ __forceinline__ void dev_sincos(float t, float &s, float &c)
 
 __device__ __forceinline__ void step_agent(const DevSim &s, const float2 *act, int i)
 {
+    if (s.halted[i]) return;                      // halted in place (App. A): state unchanged
     const float4 st = s.state[i];
     const float L = s.dims[i].x;
     const float2 u = act[i];
@@ -111,13 +112,109 @@ __global__ void k_step_multi(const SimEntry *__restrict__ tab)
     step_agent(s, e.act, i);
 }
 
-__global__ void k_cs(DevSim s)
+__global__ void k_cs(DevSim s, int clear_halted)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= s.n_agents) return;
+    if (clear_halted) s.halted[i] = 0;
     float sp, cp;
     dev_sincos(s.state[i].z, sp, cp);
     s.cs[i] = make_float2(cp, sp);
+}
+
+// ------------------------------------------------------------ infractions
+//
+// App. A: an agent that collides with another vehicle or leaves the drivable
+// area is halted in place (speed zeroed) and keeps being observed.  Readings:
+// a collision is a positive-area overlap of two footprints (length x width
+// rectangles about the box centres along the headings), tested on the four
+// separating axes of the pair, touching not counting; an agent is off-road
+// when its centre lies in no road strip of its scene (on or inside each of
+// the strip's four edges, either winding).  binary32 with every fused
+// operation written as fmaf; heading cos/sin from the state's cosines.
+
+__device__ __forceinline__ float dot2(float ax, float ay, float bx, float by) { return fmaf(ax, bx, ay * by); }
+
+__device__ __forceinline__ float reach(float hl, float hw, float ux, float uy, float ax, float ay)
+{
+    return fmaf(hl, fabsf(dot2(ux, uy, ax, ay)), hw * fabsf(dot2(-uy, ux, ax, ay)));
+}
+
+// Strips' bounding boxes are widened by this much before the exact test: the
+// binary32 edge test can only call a point inside when it lies within about
+// 1e-5 m of the strip, far inside the margin.
+#define GP_STRIP_MARGIN 0.01f
+
+// flags of agent (scene blockIdx.y, local index) into s.infr
+__global__ void k_infr_flags(DevSim s)
+{
+    const SceneRec sc = s.scenes[blockIdx.y];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= sc.n_agents) return;
+    const int gi = sc.agent_base + i;
+    const float4 si = s.state[gi];
+    const float2 ci = s.cs[gi];
+    const float4 di = s.dims[gi];
+    const float hli = 0.5f * di.x, hwi = 0.5f * di.y;
+    uint8_t f = 0;
+    for (int j = 0; j < sc.n_agents; ++j) {
+        if (j == i) continue;
+        const int gj = sc.agent_base + j;
+        const float4 sj = s.state[gj];
+        const float2 cj = s.cs[gj];
+        const float4 dj = s.dims[gj];
+        const float hlj = 0.5f * dj.x, hwj = 0.5f * dj.y;
+        const float dx = sj.x - si.x, dy = sj.y - si.y;
+        const float ax[4] = {ci.x, -ci.y, cj.x, -cj.y}, ay[4] = {ci.y, ci.x, cj.y, cj.x};
+        bool sep = false;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float ri = reach(hli, hwi, ci.x, ci.y, ax[k], ay[k]);
+            const float rj = reach(hlj, hwj, cj.x, cj.y, ax[k], ay[k]);
+            sep = sep || (fabsf(dot2(dx, dy, ax[k], ay[k])) >= ri + rj);
+        }
+        if (!sep) { f = 1; break; }
+    }
+    bool on = false;
+    for (int b = 0; b < sc.n_bins && !on; ++b) {
+        const RoadBin bn = s.bins[sc.bin_base + b];
+        if (si.x < bn.xmin - GP_STRIP_MARGIN || si.x > bn.xmax + GP_STRIP_MARGIN ||
+            si.y < bn.ymin - GP_STRIP_MARGIN || si.y > bn.ymax + GP_STRIP_MARGIN)
+            continue;
+        for (int k = 0; k < bn.count && !on; ++k) {
+            const int g = sc.road_base + bn.start + k;
+            const float4 q0 = s.roads[2 * g], q1 = s.roads[2 * g + 1];
+            const float qx[4] = {q0.x, q0.z, q1.x, q1.z}, qy[4] = {q0.y, q0.w, q1.y, q1.w};
+            bool pos = false, neg = false;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int e1 = (e + 1) & 3;
+                const float ex = qx[e1] - qx[e], ey = qy[e1] - qy[e];
+                const float wx = si.x - qx[e], wy = si.y - qy[e];
+                const float c = fmaf(ex, wy, -(ey * wx));
+                pos = pos || c > 0.0f;
+                neg = neg || c < 0.0f;
+            }
+            on = !(pos && neg);
+        }
+    }
+    if (!on) f |= 2;
+    s.infr[gi] = f;
+}
+
+// latch halted, zero the speed of halted agents, report flags
+__global__ void k_infr_apply(DevSim s, uint8_t *flags_out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= s.n_agents) return;
+    const uint8_t f = s.infr[i];
+    uint8_t h = s.halted[i];
+    if (f) {
+        h = 1;
+        s.halted[i] = 1;
+    }
+    if (h) s.state[i].w = 0.0f;
+    if (flags_out) flags_out[i] = (uint8_t)(f | (h ? 4 : 0));
 }
 
 // ------------------------------------------------------------ geometry
@@ -1583,10 +1680,21 @@ hipError_t launch_render_multi(const SimEntry *tab, const int2 *items, int n_ite
     return hipGetLastError();
 }
 
-hipError_t launch_cs(const DevSim &s, hipStream_t st)
+hipError_t launch_cs(const DevSim &s, int clear_halted, hipStream_t st)
 {
     const int B = 256;
-    hipLaunchKernelGGL(k_cs, dim3((s.n_agents + B - 1) / B), dim3(B), 0, st, s);
+    hipLaunchKernelGGL(k_cs, dim3((s.n_agents + B - 1) / B), dim3(B), 0, st, s, clear_halted);
+    return hipGetLastError();
+}
+
+hipError_t launch_infractions(const DevSim &s, int max_agents, uint8_t *flags_out, hipStream_t st)
+{
+    if (s.n_agents <= 0) return hipSuccess;
+    const int B = 256;
+    hipLaunchKernelGGL(k_infr_flags, dim3((max_agents + B - 1) / B, s.n_scenes), dim3(B), 0, st, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_infr_apply, dim3((s.n_agents + B - 1) / B), dim3(B), 0, st, s, flags_out);
     return hipGetLastError();
 }
 

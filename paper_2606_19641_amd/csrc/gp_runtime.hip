@@ -44,6 +44,7 @@ int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int64_t n_bins_of(int32_t n_roads) { return (n_roads + gp::kBinQuads - 1) / gp::kBinQuads; }
 
 struct Layout {
+    int64_t halted, infr;
     int64_t scenes, views, state, cs, dims, agent_color, roads, road_index, road_color, bins, palette,
         queue, counter;
     int64_t total;
@@ -115,6 +116,8 @@ Layout make_layout(const gp_config *cfg, const gp_scene_desc *sc, int32_t n)
     L.road_color = take(L.n_roads);
     L.bins = take(sizeof(gp::RoadBin) * L.n_bins);
     L.palette = take(768);
+    L.halted = take(L.n_agents);
+    L.infr = take(L.n_agents);
     L.queue = take(4 * L.n_views);
     L.counter = take(4 * (gp::kQueues + 2));
     L.total = o;
@@ -430,6 +433,8 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
     D.road_color = base + L.road_color;
     D.bins = reinterpret_cast<const gp::RoadBin *>(base + L.bins);
     D.palette = base + L.palette;
+    D.halted = base + L.halted;
+    D.infr = base + L.infr;
     D.queue = reinterpret_cast<const int32_t *>(base + L.queue);
     D.counter = reinterpret_cast<uint32_t *>(base + L.counter);
     D.n_scenes = n_scenes;
@@ -465,7 +470,7 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
         D.road_zmax = (float)(zmax * 1.02);
     }
 
-    e = gp::launch_cs(D, hs);
+    e = gp::launch_cs(D, 0, hs);
     if (e != hipSuccess) { delete sim; return hip_fail(e, "heading cosines"); }
 
     // default launch: persistent queue, a band buffer of at most 32 KB
@@ -675,8 +680,33 @@ gp_status gp_sim_set_state(gp_sim *sim, const float *d_src, void *stream)
     hipError_t e = hipMemcpyAsync(sim->dev.state, d_src, 16 * (size_t)sim->lay.n_agents,
                                   hipMemcpyDeviceToDevice, hs);
     if (e != hipSuccess) return hip_fail(e, "set_state copy");
-    e = gp::launch_cs(sim->dev, hs);
+    e = gp::launch_cs(sim->dev, 1, hs);
     return e == hipSuccess ? GP_OK : hip_fail(e, "heading cosines");
+}
+
+gp_status gp_sim_check_infractions(gp_sim *sim, uint8_t *d_flags, void *stream)
+{
+    if (!sim) return fail(GP_EINVAL, "NULL argument");
+    int max_agents = 0;
+    for (const gp::SceneRec &r : sim->scenes) max_agents = std::max(max_agents, r.n_agents);
+    hipError_t e = gp::launch_infractions(sim->dev, max_agents, d_flags, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? GP_OK : hip_fail(e, "infraction check launch");
+}
+
+gp_status gp_sim_fork(gp_sim *dst, const gp_sim *src, void *stream)
+{
+    if (!dst || !src) return fail(GP_EINVAL, "NULL argument");
+    if (dst == src) return GP_OK;
+    if (dst->n_scenes != src->n_scenes) return fail(GP_EINVAL, "fork needs sims over the same scenes");
+    for (int k = 0; k < src->n_scenes; ++k)
+        if (dst->scenes[k].n_agents != src->scenes[k].n_agents || dst->scenes[k].n_roads != src->scenes[k].n_roads)
+            return fail(GP_EINVAL, "fork needs sims over the same scenes (scene %d differs)", k);
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const size_t n = (size_t)src->lay.n_agents;
+    hipError_t e = hipMemcpyAsync(dst->dev.state, src->dev.state, 16 * n, hipMemcpyDeviceToDevice, hs);
+    if (e == hipSuccess) e = hipMemcpyAsync(dst->dev.cs, src->dev.cs, 8 * n, hipMemcpyDeviceToDevice, hs);
+    if (e == hipSuccess) e = hipMemcpyAsync(dst->dev.halted, src->dev.halted, n, hipMemcpyDeviceToDevice, hs);
+    return e == hipSuccess ? GP_OK : hip_fail(e, "fork copy");
 }
 
 int64_t gp_sim_num_views(const gp_sim *sim) { return sim ? sim->lay.n_views : -1; }

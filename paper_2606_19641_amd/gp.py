@@ -22,7 +22,8 @@ MAX_CAMS = 4
 EXPORTS = ("gp_sim_required_bytes", "gp_sim_create", "gp_sim_set_launch", "gp_sim_get_launch",
            "gp_sim_step", "gp_sim_render", "gp_sim_step_render_graph", "gp_sim_get_state",
            "gp_sim_set_state", "gp_sim_num_views", "gp_sim_num_agents", "gp_sim_num_scenes",
-           "gp_sim_destroy", "gp_last_error", "gp_batch_required_bytes", "gp_batch_step_render")
+           "gp_sim_destroy", "gp_last_error", "gp_batch_required_bytes", "gp_batch_step_render",
+           "gp_sim_check_infractions", "gp_sim_fork")
 
 
 class GpError(RuntimeError):
@@ -88,7 +89,9 @@ def lib() -> C.CDLL:
         L.gp_batch_required_bytes.restype = i64
         L.gp_batch_step_render.argtypes = [C.POINTER(vp), i32, C.POINTER(vp), C.POINTER(vp), vp, i64,
                                            vp, i64, vp]
-        for name in ("gp_batch_step_render", "gp_sim_create", "gp_sim_set_launch", "gp_sim_get_launch", "gp_sim_step",
+        L.gp_sim_check_infractions.argtypes = [vp, vp, vp]
+        L.gp_sim_fork.argtypes = [vp, vp, vp]
+        for name in ("gp_sim_check_infractions", "gp_sim_fork", "gp_batch_step_render", "gp_sim_create", "gp_sim_set_launch", "gp_sim_get_launch", "gp_sim_step",
                      "gp_sim_render", "gp_sim_step_render_graph", "gp_sim_get_state",
                      "gp_sim_set_state"):
             getattr(L, name).restype = C.c_int
@@ -245,6 +248,20 @@ class Sim:
     def set_state(self, state, stream=None):
         self._check_tensor(state, (self.n_agents, 4), "float32")
         _check(lib().gp_sim_set_state(self._h, state.data_ptr(), _stream_handle(stream)))
+
+    def check_infractions(self, flags=None, stream=None):
+        """Collision / off-road check; halts offenders.  Returns uint8 flags
+        [n_agents]: bit 0 collision, bit 1 off-road, bit 2 halted."""
+        import torch
+        if flags is None:
+            flags = torch.empty(self.n_agents, dtype=torch.uint8, device=self.device)
+        self._check_tensor(flags, (self.n_agents,), "uint8")
+        _check(lib().gp_sim_check_infractions(self._h, flags.data_ptr(), _stream_handle(stream)))
+        return flags
+
+    def fork_from(self, src: "Sim", stream=None):
+        """Copy src's agent state, heading cosines and halted flags into this sim."""
+        _check(lib().gp_sim_fork(self._h, src._h, _stream_handle(stream)))
 
     def _check_tensor(self, t, shape, dtype):
         import torch
