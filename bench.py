@@ -310,9 +310,12 @@ def main():
     lat_ms = np.array([a.elapsed_time(b) for a, b in ev])
     batched = V * K / wall
 
-    # ---- the render kernel alone (eager, persistent), events on its stream
+    # ---- the render kernel alone (eager, persistent), events on its stream; a
+    # short spin kernel first lets the launches queue up, so host launch gaps
+    # do not enter the event times of short kernels
     rk = max(10, min(K, 50))
     rev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(rk)]
+    torch.cuda._sleep(1_000_000)
     for k in range(rk):
         rev[k][0].record(stream)
         sim.render(rgb=rgb)
@@ -325,6 +328,7 @@ def main():
     flags = torch.empty(sim.n_agents, dtype=torch.uint8, device=dev)
     state0 = sim.get_state()
     iev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
+    torch.cuda._sleep(1_000_000)
     for a, b in iev:
         a.record(stream)
         sim.check_infractions(flags)

@@ -145,61 +145,99 @@ __device__ __forceinline__ float reach(float hl, float hw, float ux, float uy, f
 // 1e-5 m of the strip, far inside the margin.
 #define GP_STRIP_MARGIN 0.01f
 
-// flags of agent (scene blockIdx.y, local index) into s.infr
-__global__ void k_infr_flags(DevSim s)
+// Flags of every agent of scene blockIdx.x into s.infr.  The scene's agents
+// and culling bins are staged through LDS in chunks, so each pair test and
+// bin test reads LDS; only the strips of bins whose box holds the agent's
+// centre are read from global memory.
+constexpr int kInfrAgents = 512;    // agents per LDS chunk
+constexpr int kInfrBins = 512;      // culling bins per LDS chunk
+
+__global__ __launch_bounds__(256) void k_infr_flags(DevSim s)
 {
-    const SceneRec sc = s.scenes[blockIdx.y];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= sc.n_agents) return;
-    const int gi = sc.agent_base + i;
-    const float4 si = s.state[gi];
-    const float2 ci = s.cs[gi];
-    const float4 di = s.dims[gi];
-    const float hli = 0.5f * di.x, hwi = 0.5f * di.y;
-    uint8_t f = 0;
-    for (int j = 0; j < sc.n_agents; ++j) {
-        if (j == i) continue;
-        const int gj = sc.agent_base + j;
-        const float4 sj = s.state[gj];
-        const float2 cj = s.cs[gj];
-        const float4 dj = s.dims[gj];
-        const float hlj = 0.5f * dj.x, hwj = 0.5f * dj.y;
-        const float dx = sj.x - si.x, dy = sj.y - si.y;
-        const float ax[4] = {ci.x, -ci.y, cj.x, -cj.y}, ay[4] = {ci.y, ci.x, cj.y, cj.x};
-        bool sep = false;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const float ri = reach(hli, hwi, ci.x, ci.y, ax[k], ay[k]);
-            const float rj = reach(hlj, hwj, cj.x, cj.y, ax[k], ay[k]);
-            sep = sep || (fabsf(dot2(dx, dy, ax[k], ay[k])) >= ri + rj);
+    __shared__ float4 pose[kInfrAgents];     // x, y, cos, sin
+    __shared__ float2 half[kInfrAgents];     // half length, half width
+    __shared__ float4 bbox[kInfrBins];       // xmin, ymin, xmax, ymax (widened)
+    __shared__ int2 brange[kInfrBins];       // first slot, count
+    const SceneRec sc = s.scenes[blockIdx.x];
+    const int n = sc.n_agents, B = blockDim.x, tid = threadIdx.x;
+    for (int i0 = 0; i0 < n; i0 += B) {
+        const int i = i0 + tid;
+        const bool valid = i < n;
+        float4 si = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        float2 ci = make_float2(1.0f, 0.0f);
+        float hli = 0.0f, hwi = 0.0f;
+        if (valid) {
+            const int gi = sc.agent_base + i;
+            si = s.state[gi];
+            ci = s.cs[gi];
+            const float4 di = s.dims[gi];
+            hli = 0.5f * di.x;
+            hwi = 0.5f * di.y;
         }
-        if (!sep) { f = 1; break; }
-    }
-    bool on = false;
-    for (int b = 0; b < sc.n_bins && !on; ++b) {
-        const RoadBin bn = s.bins[sc.bin_base + b];
-        if (si.x < bn.xmin - GP_STRIP_MARGIN || si.x > bn.xmax + GP_STRIP_MARGIN ||
-            si.y < bn.ymin - GP_STRIP_MARGIN || si.y > bn.ymax + GP_STRIP_MARGIN)
-            continue;
-        for (int k = 0; k < bn.count && !on; ++k) {
-            const int g = sc.road_base + bn.start + k;
-            const float4 q0 = s.roads[2 * g], q1 = s.roads[2 * g + 1];
-            const float qx[4] = {q0.x, q0.z, q1.x, q1.z}, qy[4] = {q0.y, q0.w, q1.y, q1.w};
-            bool pos = false, neg = false;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int e1 = (e + 1) & 3;
-                const float ex = qx[e1] - qx[e], ey = qy[e1] - qy[e];
-                const float wx = si.x - qx[e], wy = si.y - qy[e];
-                const float c = fmaf(ex, wy, -(ey * wx));
-                pos = pos || c > 0.0f;
-                neg = neg || c < 0.0f;
+        bool col = false;
+        for (int j0 = 0; j0 < n; j0 += kInfrAgents) {
+            const int nj = min(kInfrAgents, n - j0);
+            __syncthreads();
+            for (int k = tid; k < nj; k += B) {
+                const int g = sc.agent_base + j0 + k;
+                const float4 st = s.state[g];
+                const float2 cs = s.cs[g];
+                const float4 dm = s.dims[g];
+                pose[k] = make_float4(st.x, st.y, cs.x, cs.y);
+                half[k] = make_float2(0.5f * dm.x, 0.5f * dm.y);
             }
-            on = !(pos && neg);
+            __syncthreads();
+            for (int k = 0; valid && !col && k < nj; ++k) {
+                if (j0 + k == i) continue;
+                const float4 pj = pose[k];
+                const float2 hj = half[k];
+                const float dx = pj.x - si.x, dy = pj.y - si.y;
+                const float ax[4] = {ci.x, -ci.y, pj.z, -pj.w}, ay[4] = {ci.y, ci.x, pj.w, pj.z};
+                bool sep = false;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float ri = reach(hli, hwi, ci.x, ci.y, ax[e], ay[e]);
+                    const float rj = reach(hj.x, hj.y, pj.z, pj.w, ax[e], ay[e]);
+                    sep = sep || (fabsf(dot2(dx, dy, ax[e], ay[e])) >= ri + rj);
+                }
+                col = !sep;
+            }
         }
+        bool on = false;
+        for (int b0 = 0; b0 < sc.n_bins; b0 += kInfrBins) {
+            const int nb = min(kInfrBins, sc.n_bins - b0);
+            __syncthreads();
+            for (int k = tid; k < nb; k += B) {
+                const RoadBin bn = s.bins[sc.bin_base + b0 + k];
+                bbox[k] = make_float4(bn.xmin - GP_STRIP_MARGIN, bn.ymin - GP_STRIP_MARGIN,
+                                      bn.xmax + GP_STRIP_MARGIN, bn.ymax + GP_STRIP_MARGIN);
+                brange[k] = make_int2(bn.start, bn.count);
+            }
+            __syncthreads();
+            for (int k = 0; valid && !on && k < nb; ++k) {
+                const float4 bb = bbox[k];
+                if (si.x < bb.x || si.x > bb.z || si.y < bb.y || si.y > bb.w) continue;
+                const int2 rg = brange[k];
+                for (int q = 0; q < rg.y && !on; ++q) {
+                    const int g = sc.road_base + rg.x + q;
+                    const float4 q0 = s.roads[2 * g], q1 = s.roads[2 * g + 1];
+                    const float qx[4] = {q0.x, q0.z, q1.x, q1.z}, qy[4] = {q0.y, q0.w, q1.y, q1.w};
+                    bool pos = false, neg = false;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int e1 = (e + 1) & 3;
+                        const float ex = qx[e1] - qx[e], ey = qy[e1] - qy[e];
+                        const float wx = si.x - qx[e], wy = si.y - qy[e];
+                        const float c = fmaf(ex, wy, -(ey * wx));
+                        pos = pos || c > 0.0f;
+                        neg = neg || c < 0.0f;
+                    }
+                    on = !(pos && neg);
+                }
+            }
+        }
+        if (valid) s.infr[sc.agent_base + i] = (uint8_t)((col ? 1 : 0) | (on ? 0 : 2));
     }
-    if (!on) f |= 2;
-    s.infr[gi] = f;
 }
 
 // latch halted, zero the speed of halted agents, report flags
@@ -1119,7 +1157,7 @@ __device__ void setup_source(const DevSim &s, const SceneRec &sc, const Cam &cam
     // counter after its last barrier; the next append to that ring comes two
     // rounds later, after the next round's barrier, so every thread reads the
     // same value without a barrier at the end of the round.
-    int head[2] = {L.cnt[C_CLIPQ], L.cnt[C_CLIPQ1]};
+    int head0 = L.cnt[C_CLIPQ], head1 = L.cnt[C_CLIPQ1];   // two scalars (no indexed array)
     int r_up = L.cnt[C_RTRIS];                   // bound on the road list's length
     for (int u0 = 0; u0 < n_units; u0 += B) {
         // ---- cull units, compact the survivors
@@ -1229,7 +1267,8 @@ __device__ void setup_source(const DevSim &s, const SceneRec &sc, const Cam &cam
             }
             __syncthreads();
             // this round's clip candidates are entries [head, tail) of its parity's ring
-            const int tail = L.cnt[par ? C_CLIPQ1 : C_CLIPQ], nq = tail - head[par];
+            const int head = par ? head1 : head0;
+            const int tail = L.cnt[par ? C_CLIPQ1 : C_CLIPQ], nq = tail - head;
             // the clipper may emit up to kMaxTrisPerCand triangles per candidate
             const int chunk = can_flush ? max(1, fcap / kMaxTrisPerCand) : B;
             // one wave per queued candidate
@@ -1238,12 +1277,13 @@ __device__ void setup_source(const DevSim &s, const SceneRec &sc, const Cam &cam
                 if (can_flush) r_up = make_room(cam, L, K, qn * kMaxTrisPerCand, qn * kMaxTrisPerCand) + qn * kMaxTrisPerCand;
                 for (int q = q0 + (tid >> 6); q < q0 + qn; q += B >> 6) {
                     Poly Q;
-                    build_code(s, sc, cam, L.clipq[par * B + (head[par] + q) % B], Q);
+                    build_code(s, sc, cam, L.clipq[par * B + (head + q) % B], Q);
                     clip_wave(cam, Q, K, L);
                 }
                 __syncthreads();
             }
-            head[par] = tail;
+            if (par) head1 = tail;
+            else head0 = tail;
         }
     }
 }
@@ -1262,6 +1302,38 @@ __device__ __forceinline__ void clear_band(Lds &L, int npix)
 // 1/z of pixel (i, j) is fma(A, du, y) = y for y = fma(B, dv, C) != 0: one
 // value per row, positive exactly below the horizon.  A box fragment beats
 // the road where its 1/z is not smaller (agents rank above roads on ties).
+// colour of a pixel of the rgb kernel: a box fragment wins where its 1/z is
+// not below the road's (agents rank above roads on ties); else road or
+// background by the coverage bit
+template <bool KEYS>
+__device__ __forceinline__ uint32_t fast_color(const Lds &L, bool road, float rz, unsigned long long kb,
+                                              uint32_t road_rgb, uint32_t bg_rgb)
+{
+    if (KEYS) {
+        const bool box = kb != 0ull && (!road || (uint32_t)(kb >> 32) >= __float_as_uint(rz));
+        if (box) return L.pal[(uint32_t)kb & 0xFFu];
+    }
+    return road ? road_rgb : bg_rgb;
+}
+
+template <bool KEYS>
+__device__ __forceinline__ uint32_t fast_pixel(const Cam &cam, const Lds &L, int j, int i, int zb0,
+                                              uint32_t road_rgb, uint32_t bg_rgb)
+{
+    const float dv = ((float)j + 0.5f) - cam.cy;
+    const float rz = fmaf(cam.road.B, dv, cam.road.C);
+    const bool road = rz > 0.0f && ((L.road[(size_t)j * L.nw + (i >> 6)] >> (i & 63)) & 1ull);
+    const unsigned long long kb = KEYS ? L.zb[(size_t)(j - zb0) * cam.W + i] : 0ull;
+    return fast_color<KEYS>(L, road, rz, kb, road_rgb, bg_rgb);
+}
+
+__device__ __forceinline__ void put_rgb(uint8_t *dst, uint32_t c)
+{
+    dst[0] = (uint8_t)c;
+    dst[1] = (uint8_t)(c >> 8);
+    dst[2] = (uint8_t)(c >> 16);
+}
+
 template <bool KEYS>
 __device__ void resolve_fast(const DevSim &s, const Cam &cam, Lds &L, uint8_t *rgb, int64_t view, int r0,
                              int r1, int zb0)
@@ -1270,14 +1342,6 @@ __device__ void resolve_fast(const DevSim &s, const Cam &cam, Lds &L, uint8_t *r
     const int64_t img = view * (int64_t)W * cam.H;
     const uint32_t road_rgb = L.pal[s.road_color0];
     const uint32_t bg_rgb = L.pal[0];
-    auto color_of = [&](bool road, float rz, lptr<unsigned long long> kp, int m) -> uint32_t {
-        if (KEYS) {
-            const unsigned long long kb = kp[m];
-            const bool box = kb != 0ull && (!road || (uint32_t)(kb >> 32) >= __float_as_uint(rz));
-            if (box) return L.pal[(uint32_t)kb & 0xFFu];
-        }
-        return road ? road_rgb : bg_rgb;
-    };
     if ((W & 3) == 0) {
         const int tpr = W >> 2;                       // threads per row, 4 pixels each
         const int rpi = (int)blockDim.x / tpr;        // rows per pass (W <= 4 * blockDim)
@@ -1290,56 +1354,51 @@ __device__ void resolve_fast(const DevSim &s, const Cam &cam, Lds &L, uint8_t *r
             const bool rowok = rz > 0.0f;
             const uint32_t bits = rowok ? (uint32_t)(L.road[(size_t)j * L.nw + (i >> 6)] >> (i & 63)) & 0xFu : 0u;
             lptr<unsigned long long> kp = L.zb + (KEYS ? (size_t)(j - zb0) * W + i : 0);
-            const uint32_t c0 = color_of(bits & 1u, rz, kp, 0), c1 = color_of(bits & 2u, rz, kp, 1);
-            const uint32_t c2 = color_of(bits & 4u, rz, kp, 2), c3 = color_of(bits & 8u, rz, kp, 3);
+            uint32_t c[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                c[m] = fast_color<KEYS>(L, (bits >> m) & 1u, rz, KEYS ? kp[m] : 0ull, road_rgb, bg_rgb);
             uint32_t *out = reinterpret_cast<uint32_t *>(rgb + 3 * (img + (int64_t)j * W + i));
-            out[0] = (c0 & 0xFFFFFFu) | (c1 << 24);
-            out[1] = ((c1 >> 8) & 0xFFFFu) | (c2 << 16);
-            out[2] = ((c2 >> 16) & 0xFFu) | (c3 << 8);
+            out[0] = (c[0] & 0xFFFFFFu) | (c[1] << 24);
+            out[1] = ((c[1] >> 8) & 0xFFFFu) | (c[2] << 16);
+            out[2] = ((c[2] >> 16) & 0xFFu) | (c[3] << 8);
+        }
+        return;
+    }
+    // rows are not a whole number of dwords: walk the rows' pixels as one
+    // flat run, 4 pixels (3 dwords) per thread; a group may cross a row end.
+    // The whole groups need a 4-byte aligned image (W * H a multiple of 4);
+    // the partial groups at the run's two ends are written bytewise.
+    const int pbeg = r0 * W, pend = r1 * W;
+    const bool dwords = ((W * cam.H) & 3) == 0;
+    const int g0 = dwords ? (pbeg + 3) >> 2 : 0, g1 = dwords ? pend >> 2 : 0;
+    if (g0 < g1) {
+        uint32_t *base = reinterpret_cast<uint32_t *>(rgb + 3 * img);
+        for (int g = g0 + (int)threadIdx.x; g < g1; g += blockDim.x) {
+            int j = (4 * g) / W, i = 4 * g - j * W;
+            uint32_t c[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                c[k] = fast_pixel<KEYS>(cam, L, j, i, zb0, road_rgb, bg_rgb);
+                if (++i == W) { i = 0; ++j; }
+            }
+            uint32_t *out = base + 3 * (size_t)g;
+            out[0] = (c[0] & 0xFFFFFFu) | (c[1] << 24);
+            out[1] = ((c[1] >> 8) & 0xFFFFu) | (c[2] << 16);
+            out[2] = ((c[2] >> 16) & 0xFFu) | (c[3] << 8);
+        }
+        const int head = 4 * g0 - pbeg, tail = pend - 4 * g1;   // 0..3 pixels each
+        int p = -1;
+        if ((int)threadIdx.x < head) p = pbeg + (int)threadIdx.x;
+        else if ((int)threadIdx.x >= 4 && (int)threadIdx.x < 4 + tail) p = 4 * g1 + (int)threadIdx.x - 4;
+        if (p >= 0) {
+            const int j = p / W, i = p - j * W;
+            put_rgb(rgb + 3 * (img + (int64_t)p), fast_pixel<KEYS>(cam, L, j, i, zb0, road_rgb, bg_rgb));
         }
     } else {
-        // rows are not a whole number of dwords: walk the rows' pixels as one
-        // flat run, 4 pixels (3 dwords) per thread; a group may cross a row
-        // end.  The whole groups need a 4-byte aligned image (W * H a multiple
-        // of 4); the partial groups at the run's two ends are written bytewise.
-        auto pixel = [&](int j, int i) -> uint32_t {
-            const float dv = ((float)j + 0.5f) - cam.cy;
-            const float rz = fmaf(cam.road.B, dv, cam.road.C);
-            const bool road = rz > 0.0f && ((L.road[(size_t)j * L.nw + (i >> 6)] >> (i & 63)) & 1ull);
-            lptr<unsigned long long> kp = L.zb + (KEYS ? (size_t)(j - zb0) * W + i : 0);
-            return color_of(road, rz, kp, 0);
-        };
-        auto put_bytes = [&](int p) {               // flat pixel p of the run's rows
+        for (int p = pbeg + (int)threadIdx.x; p < pend; p += blockDim.x) {
             const int j = p / W, i = p - j * W;
-            const uint32_t c = pixel(j, i);
-            uint8_t *dst = rgb + 3 * (img + (int64_t)p);
-            dst[0] = (uint8_t)c;
-            dst[1] = (uint8_t)(c >> 8);
-            dst[2] = (uint8_t)(c >> 16);
-        };
-        const int pbeg = r0 * W, pend = r1 * W;
-        const bool dwords = ((W * cam.H) & 3) == 0;
-        const int g0 = dwords ? (pbeg + 3) >> 2 : 0, g1 = dwords ? pend >> 2 : 0;
-        if (g0 < g1) {
-            uint32_t *base = reinterpret_cast<uint32_t *>(rgb + 3 * img);
-            for (int g = g0 + (int)threadIdx.x; g < g1; g += blockDim.x) {
-                int j = (4 * g) / W, i = 4 * g - j * W;
-                uint32_t c[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    c[k] = pixel(j, i);
-                    if (++i == W) { i = 0; ++j; }
-                }
-                uint32_t *out = base + 3 * (size_t)g;
-                out[0] = (c[0] & 0xFFFFFFu) | (c[1] << 24);
-                out[1] = ((c[1] >> 8) & 0xFFFFu) | (c[2] << 16);
-                out[2] = ((c[2] >> 16) & 0xFFu) | (c[3] << 8);
-            }
-            const int head = 4 * g0 - pbeg, tail = pend - 4 * g1;   // 0..3 pixels each
-            if ((int)threadIdx.x < head) put_bytes(pbeg + (int)threadIdx.x);
-            else if ((int)threadIdx.x >= 4 && (int)threadIdx.x < 4 + tail) put_bytes(4 * g1 + (int)threadIdx.x - 4);
-        } else {
-            for (int p = pbeg + (int)threadIdx.x; p < pend; p += blockDim.x) put_bytes(p);
+            put_rgb(rgb + 3 * (img + (int64_t)p), fast_pixel<KEYS>(cam, L, j, i, zb0, road_rgb, bg_rgb));
         }
     }
 }
@@ -1599,7 +1658,9 @@ __global__ __launch_bounds__(BLOCK) void k_render_multi(const SimEntry *__restri
         if (it >= n_items) break;
         const int2 item = items[it];
         const int k = __builtin_amdgcn_readfirstlane(item.x), view = __builtin_amdgcn_readfirstlane(item.y);
-        const DevSim s = tab[k].s;
+        // the sim's record is read in place (a local copy of it would be
+        // indexed by camera and live in scratch memory)
+        const DevSim &s = tab[k].s;
         const RenderOut o = tab[k].o;
         if (k != cur) {
             load_palette(s, L, FAST);
@@ -1691,7 +1752,8 @@ hipError_t launch_infractions(const DevSim &s, int max_agents, uint8_t *flags_ou
 {
     if (s.n_agents <= 0) return hipSuccess;
     const int B = 256;
-    hipLaunchKernelGGL(k_infr_flags, dim3((max_agents + B - 1) / B, s.n_scenes), dim3(B), 0, st, s);
+    (void)max_agents;
+    hipLaunchKernelGGL(k_infr_flags, dim3(s.n_scenes), dim3(B), 0, st, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_infr_apply, dim3((s.n_agents + B - 1) / B), dim3(B), 0, st, s, flags_out);
