@@ -145,99 +145,99 @@ __device__ __forceinline__ float reach(float hl, float hw, float ux, float uy, f
 // 1e-5 m of the strip, far inside the margin.
 #define GP_STRIP_MARGIN 0.01f
 
-// Flags of every agent of scene blockIdx.x into s.infr.  The scene's agents
-// and culling bins are staged through LDS in chunks, so each pair test and
-// bin test reads LDS; only the strips of bins whose box holds the agent's
-// centre are read from global memory.
-constexpr int kInfrAgents = 512;    // agents per LDS chunk
-constexpr int kInfrBins = 512;      // culling bins per LDS chunk
+// Flags of every agent into s.infr, one wavefront per agent.  The lanes share
+// out the scene's other agents (pair tests) and its culling bins (box tests);
+// the strips of the bins whose widened box holds the agent's centre are then
+// tested four bins at a time, lane l taking strip l % 16 of hit bin l / 16.
+constexpr int kInfrWaves = 4;   // agents per 256-thread workgroup
+
+__device__ __forceinline__ bool footprints_overlap(float4 si, float2 ci, float hli, float hwi, float4 sj,
+                                                   float2 cj, float hlj, float hwj)
+{
+    const float dx = sj.x - si.x, dy = sj.y - si.y;
+    const float ax[4] = {ci.x, -ci.y, cj.x, -cj.y}, ay[4] = {ci.y, ci.x, cj.y, cj.x};
+    bool sep = false;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const float ri = reach(hli, hwi, ci.x, ci.y, ax[e], ay[e]);
+        const float rj = reach(hlj, hwj, cj.x, cj.y, ax[e], ay[e]);
+        sep = sep || (fabsf(dot2(dx, dy, ax[e], ay[e])) >= ri + rj);
+    }
+    return !sep;
+}
+
+// the centre (x, y) is on or inside every edge of the strip, either winding
+__device__ __forceinline__ bool in_strip(float4 q0, float4 q1, float x, float y)
+{
+    const float qx[4] = {q0.x, q0.z, q1.x, q1.z}, qy[4] = {q0.y, q0.w, q1.y, q1.w};
+    bool pos = false, neg = false;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int e1 = (e + 1) & 3;
+        const float ex = qx[e1] - qx[e], ey = qy[e1] - qy[e];
+        const float wx = x - qx[e], wy = y - qy[e];
+        const float c = fmaf(ex, wy, -(ey * wx));
+        pos = pos || c > 0.0f;
+        neg = neg || c < 0.0f;
+    }
+    return !(pos && neg);
+}
 
 __global__ __launch_bounds__(256) void k_infr_flags(DevSim s)
 {
-    __shared__ float4 pose[kInfrAgents];     // x, y, cos, sin
-    __shared__ float2 half[kInfrAgents];     // half length, half width
-    __shared__ float4 bbox[kInfrBins];       // xmin, ymin, xmax, ymax (widened)
-    __shared__ int2 brange[kInfrBins];       // first slot, count
-    const SceneRec sc = s.scenes[blockIdx.x];
-    const int n = sc.n_agents, B = blockDim.x, tid = threadIdx.x;
-    for (int i0 = 0; i0 < n; i0 += B) {
-        const int i = i0 + tid;
-        const bool valid = i < n;
-        float4 si = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        float2 ci = make_float2(1.0f, 0.0f);
-        float hli = 0.0f, hwi = 0.0f;
-        if (valid) {
-            const int gi = sc.agent_base + i;
-            si = s.state[gi];
-            ci = s.cs[gi];
-            const float4 di = s.dims[gi];
-            hli = 0.5f * di.x;
-            hwi = 0.5f * di.y;
+    const int lane = (int)__lane_id();
+    const int i = blockIdx.x * kInfrWaves + (int)(threadIdx.x >> 6);   // one agent per wavefront
+    if (i >= s.n_agents) return;                                        // the whole wavefront
+    const SceneRec sc = s.scenes[s.views[(int64_t)i * s.n_cams].scene];
+    const float4 si = s.state[i];
+    const float2 ci = s.cs[i];
+    const float4 di = s.dims[i];
+    const float hli = 0.5f * di.x, hwi = 0.5f * di.y;
+
+    bool col = false;
+    for (int j0 = 0; j0 < sc.n_agents && !col; j0 += 64) {
+        const int gj = sc.agent_base + j0 + lane;
+        bool hit = false;
+        if (j0 + lane < sc.n_agents && gj != i) {
+            const float4 dj = s.dims[gj];
+            hit = footprints_overlap(si, ci, hli, hwi, s.state[gj], s.cs[gj], 0.5f * dj.x, 0.5f * dj.y);
         }
-        bool col = false;
-        for (int j0 = 0; j0 < n; j0 += kInfrAgents) {
-            const int nj = min(kInfrAgents, n - j0);
-            __syncthreads();
-            for (int k = tid; k < nj; k += B) {
-                const int g = sc.agent_base + j0 + k;
-                const float4 st = s.state[g];
-                const float2 cs = s.cs[g];
-                const float4 dm = s.dims[g];
-                pose[k] = make_float4(st.x, st.y, cs.x, cs.y);
-                half[k] = make_float2(0.5f * dm.x, 0.5f * dm.y);
-            }
-            __syncthreads();
-            for (int k = 0; valid && !col && k < nj; ++k) {
-                if (j0 + k == i) continue;
-                const float4 pj = pose[k];
-                const float2 hj = half[k];
-                const float dx = pj.x - si.x, dy = pj.y - si.y;
-                const float ax[4] = {ci.x, -ci.y, pj.z, -pj.w}, ay[4] = {ci.y, ci.x, pj.w, pj.z};
-                bool sep = false;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const float ri = reach(hli, hwi, ci.x, ci.y, ax[e], ay[e]);
-                    const float rj = reach(hj.x, hj.y, pj.z, pj.w, ax[e], ay[e]);
-                    sep = sep || (fabsf(dot2(dx, dy, ax[e], ay[e])) >= ri + rj);
-                }
-                col = !sep;
-            }
-        }
-        bool on = false;
-        for (int b0 = 0; b0 < sc.n_bins; b0 += kInfrBins) {
-            const int nb = min(kInfrBins, sc.n_bins - b0);
-            __syncthreads();
-            for (int k = tid; k < nb; k += B) {
-                const RoadBin bn = s.bins[sc.bin_base + b0 + k];
-                bbox[k] = make_float4(bn.xmin - GP_STRIP_MARGIN, bn.ymin - GP_STRIP_MARGIN,
-                                      bn.xmax + GP_STRIP_MARGIN, bn.ymax + GP_STRIP_MARGIN);
-                brange[k] = make_int2(bn.start, bn.count);
-            }
-            __syncthreads();
-            for (int k = 0; valid && !on && k < nb; ++k) {
-                const float4 bb = bbox[k];
-                if (si.x < bb.x || si.x > bb.z || si.y < bb.y || si.y > bb.w) continue;
-                const int2 rg = brange[k];
-                for (int q = 0; q < rg.y && !on; ++q) {
-                    const int g = sc.road_base + rg.x + q;
-                    const float4 q0 = s.roads[2 * g], q1 = s.roads[2 * g + 1];
-                    const float qx[4] = {q0.x, q0.z, q1.x, q1.z}, qy[4] = {q0.y, q0.w, q1.y, q1.w};
-                    bool pos = false, neg = false;
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int e1 = (e + 1) & 3;
-                        const float ex = qx[e1] - qx[e], ey = qy[e1] - qy[e];
-                        const float wx = si.x - qx[e], wy = si.y - qy[e];
-                        const float c = fmaf(ex, wy, -(ey * wx));
-                        pos = pos || c > 0.0f;
-                        neg = neg || c < 0.0f;
-                    }
-                    on = !(pos && neg);
-                }
-            }
-        }
-        if (valid) s.infr[sc.agent_base + i] = (uint8_t)((col ? 1 : 0) | (on ? 0 : 2));
+        col = __ballot(hit) != 0ull;
     }
+
+    bool on = false;
+    const int grp = lane >> 4, q = lane & 15;
+    for (int b0 = 0; b0 < sc.n_bins && !on; b0 += 64) {
+        const int b = b0 + lane;
+        bool in = false;
+        int start = 0, count = 0;
+        if (b < sc.n_bins) {
+            const RoadBin bn = s.bins[sc.bin_base + b];
+            in = !(si.x < bn.xmin - GP_STRIP_MARGIN || si.x > bn.xmax + GP_STRIP_MARGIN ||
+                   si.y < bn.ymin - GP_STRIP_MARGIN || si.y > bn.ymax + GP_STRIP_MARGIN);
+            start = bn.start;
+            count = bn.count;
+        }
+        unsigned long long m = __ballot(in);
+        while (m != 0ull && !on) {
+            // the lowest four hit bins, as lanes of this pass (-1: none)
+            int src[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                src[k] = m != 0ull ? __ffsll((long long)m) - 1 : -1;
+                m &= m - 1ull;
+            }
+            const int my = grp == 0 ? src[0] : grp == 1 ? src[1] : grp == 2 ? src[2] : src[3];
+            const int st = __shfl(start, my < 0 ? 0 : my), ct = __shfl(count, my < 0 ? 0 : my);
+            bool ok = false;
+            if (my >= 0 && q < ct) {
+                const int g = sc.road_base + st + q;
+                ok = in_strip(s.roads[2 * g], s.roads[2 * g + 1], si.x, si.y);
+            }
+            on = __ballot(ok) != 0ull;
+        }
+    }
+    if (lane == 0) s.infr[i] = (uint8_t)((col ? 1 : 0) | (on ? 0 : 2));
 }
 
 // latch halted, zero the speed of halted agents, report flags
@@ -1753,7 +1753,7 @@ hipError_t launch_infractions(const DevSim &s, int max_agents, uint8_t *flags_ou
     if (s.n_agents <= 0) return hipSuccess;
     const int B = 256;
     (void)max_agents;
-    hipLaunchKernelGGL(k_infr_flags, dim3(s.n_scenes), dim3(B), 0, st, s);
+    hipLaunchKernelGGL(k_infr_flags, dim3((s.n_agents + kInfrWaves - 1) / kInfrWaves), dim3(B), 0, st, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_infr_apply, dim3((s.n_agents + B - 1) / B), dim3(B), 0, st, s, flags_out);

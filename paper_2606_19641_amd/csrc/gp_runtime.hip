@@ -41,7 +41,10 @@ gp_status hip_fail(hipError_t e, const char *what)
 constexpr int64_t kAlign = 256;
 int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-int64_t n_bins_of(int32_t n_roads) { return (n_roads + gp::kBinQuads - 1) / gp::kBinQuads; }
+// Bins a scene of n_roads strips may use: twice the count-limited number, so
+// that bins can also be closed on extent (sort_roads).
+int64_t n_bins_of(int32_t n_roads) { return 2 * ((n_roads + gp::kBinQuads - 1) / gp::kBinQuads); }
+constexpr float kBinExtent = 32.0f;   // metres
 
 struct Layout {
     int64_t halted, infr;
@@ -148,8 +151,13 @@ uint32_t morton16(uint32_t x, uint32_t y)
 }
 
 // Order the road strips of one scene along a Morton curve of their centres
-// and cut the order into bins of kBinQuads; each bin keeps the exact float
-// bounding box of its strips' corners.  Returns the slot -> input index map.
+// and cut the order into bins of at most kBinQuads strips; each bin keeps the
+// exact float bounding box of its strips' corners.  Where the curve jumps, a
+// bin of 16 consecutive strips can span most of the map, which makes its box
+// useless for culling; so a bin is also closed before a strip that would
+// stretch its box beyond kBinExtent metres on either axis, as long as the
+// remaining strips still fit in n_bins_of(n) bins.  Returns the slot -> input
+// index map.
 std::vector<int32_t> sort_roads(const gp_scene_desc &d, std::vector<gp::RoadBin> &bins)
 {
     const int n = d.n_roads;
@@ -177,27 +185,41 @@ std::vector<int32_t> sort_roads(const gp_scene_desc &d, std::vector<gp::RoadBin>
     for (int r = 0; r < n; ++r)
         code[r] = morton16((uint32_t)((cx[r] - xmin) * sx), (uint32_t)((cy[r] - ymin) * sy));
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return code[a] < code[b]; });
-    for (int b0 = 0; b0 < n; b0 += gp::kBinQuads) {
-        gp::RoadBin bn{};
-        bn.start = b0;
-        bn.count = std::min(gp::kBinQuads, n - b0);
+    const int64_t budget = n_bins_of(n);
+    gp::RoadBin bn{};
+    bn.xmin = bn.ymin = INFINITY;
+    bn.xmax = bn.ymax = -INFINITY;
+    for (int k = 0; k < n; ++k) {
+        const int r = order[k];
         float x0 = INFINITY, y0 = INFINITY, x1 = -INFINITY, y1 = -INFINITY;
-        for (int k = 0; k < bn.count; ++k) {
-            const int r = order[b0 + k];
-            for (int c = 0; c < 4; ++c) {
-                const float x = d.road_xy[8 * r + 2 * c], y = d.road_xy[8 * r + 2 * c + 1];
-                x0 = std::min(x0, x);
-                x1 = std::max(x1, x);
-                y0 = std::min(y0, y);
-                y1 = std::max(y1, y);
+        for (int c = 0; c < 4; ++c) {
+            const float x = d.road_xy[8 * r + 2 * c], y = d.road_xy[8 * r + 2 * c + 1];
+            x0 = std::min(x0, x);
+            x1 = std::max(x1, x);
+            y0 = std::min(y0, y);
+            y1 = std::max(y1, y);
+        }
+        if (bn.count > 0) {
+            const bool full = bn.count == gp::kBinQuads;
+            const bool wide = std::max(bn.xmax, x1) - std::min(bn.xmin, x0) > kBinExtent ||
+                              std::max(bn.ymax, y1) - std::min(bn.ymin, y0) > kBinExtent;
+            // closing here leaves n - k strips for budget - (bins + 1) bins
+            const int64_t need = (int64_t)bins.size() + 1 + (n - k + gp::kBinQuads - 1) / gp::kBinQuads;
+            if (full || (wide && need <= budget)) {
+                bins.push_back(bn);
+                bn = gp::RoadBin{};
+                bn.start = k;
+                bn.xmin = bn.ymin = INFINITY;
+                bn.xmax = bn.ymax = -INFINITY;
             }
         }
-        bn.xmin = x0;
-        bn.ymin = y0;
-        bn.xmax = x1;
-        bn.ymax = y1;
-        bins.push_back(bn);
+        bn.count += 1;
+        bn.xmin = std::min(bn.xmin, x0);
+        bn.ymin = std::min(bn.ymin, y0);
+        bn.xmax = std::max(bn.xmax, x1);
+        bn.ymax = std::max(bn.ymax, y1);
     }
+    bins.push_back(bn);
     return order;
 }
 
