@@ -55,6 +55,10 @@ def lib():
         L.gpo_sincos.argtypes = [C.c_float, C.POINTER(C.c_float), C.POINTER(C.c_float)]
         L.gpo_step.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_float, C.c_void_p,
                                C.c_void_p]
+        L.gpo_step_jerk.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_float,
+                                    C.c_void_p, C.c_void_p]
+        L.gpo_atan_small.argtypes = [C.c_float]
+        L.gpo_atan_small.restype = C.c_float
         L.gpo_overlap.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.gpo_in_strip.argtypes = [C.c_void_p, C.c_float, C.c_float]
         L.gpo_infractions.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
@@ -88,6 +92,27 @@ def step(state: np.ndarray, dims: np.ndarray, act: np.ndarray, dt: float = 0.1, 
     cs = np.empty((st.shape[0], 2), dtype=np.float32)
     lib().gpo_step(st.shape[0], _ptr(st), _ptr(dm), _ptr(ac), C.c_float(dt), _ptr(cs), _ptr(hl))
     return st, cs
+
+
+def atan_small(x: float):
+    """atan for |x| <= tan(0.5), the series the jerk step uses (binary32)."""
+    return np.float32(lib().gpo_atan_small(C.c_float(x)))
+
+
+def step_jerk(state: np.ndarray, dims: np.ndarray, actuators: np.ndarray, actions: np.ndarray,
+              dt: float = 0.1, halted=None):
+    """One jerk-actuated step (App. A, twelve discrete actions); returns
+    (new_state [n,4], cos/sin psi [n,2], new_actuators [n,4] = a_lon, a_lat,
+    steering, 0); inputs untouched.  Agents flagged in `halted` keep both."""
+    st = np.ascontiguousarray(state, dtype=np.float32).copy()
+    ac = np.ascontiguousarray(actuators, dtype=np.float32).copy()
+    dm = np.ascontiguousarray(dims, dtype=np.float32)
+    ix = np.ascontiguousarray(actions, dtype=np.uint8)
+    hl = None if halted is None else np.ascontiguousarray(halted, dtype=np.uint8)
+    assert st.shape[0] == ac.shape[0] == dm.shape[0] == ix.shape[0]
+    cs = np.empty((st.shape[0], 2), dtype=np.float32)
+    lib().gpo_step_jerk(st.shape[0], _ptr(st), _ptr(dm), _ptr(ac), _ptr(ix), C.c_float(dt), _ptr(cs), _ptr(hl))
+    return st, cs, ac
 
 
 def overlap(state_i, dims_i, state_j, dims_j) -> bool:

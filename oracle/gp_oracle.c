@@ -100,6 +100,37 @@ static float clampf(float x, float lo, float hi) { return fminf(fmaxf(x, lo), hi
  * An agent flagged in `halted` (optional) keeps its state (App. A: an agent
  * that commits an infraction is halted in place).
  */
+
+/* one bicycle update of st[4] = x, y, psi, v; writes cos/sin psi' to cs[2]
+ * (if given) and returns the path curvature kappa */
+static float bicycle(float *st, float L, float accel, float steer, float dt, float *cs)
+{
+    float x = st[0], y = st[1], psi = st[2], v = st[3];
+    float a = clampf(accel, ACC_MIN, ACC_MAX);
+    float delta = clampf(steer, -STEER_MAX, STEER_MAX);
+    float v1 = clampf(fmaf(a, dt, v), V_MIN, V_MAX);
+    float sd, cd;
+    gpo_sincos(delta, &sd, &cd);
+    float kappa = sd / (cd * (WHEELBASE_FRAC * L));
+    float vdt = v1 * dt;
+    float psi1 = fmaf(vdt, kappa, psi);
+    if (psi1 > PI_F)
+        psi1 = psi1 - TWO_PI_F;
+    else if (psi1 <= -PI_F)
+        psi1 = psi1 + TWO_PI_F;
+    float sp, cp;
+    gpo_sincos(psi1, &sp, &cp);
+    st[0] = fmaf(vdt, cp, x);
+    st[1] = fmaf(vdt, sp, y);
+    st[2] = psi1;
+    st[3] = v1;
+    if (cs) {
+        cs[0] = cp;
+        cs[1] = sp;
+    }
+    return kappa;
+}
+
 void gpo_step(int n, float *state, const float *dims, const float *act, float dt, float *cs_out,
               const uint8_t *halted)
 {
@@ -108,31 +139,104 @@ void gpo_step(int n, float *state, const float *dims, const float *act, float dt
             if (cs_out) gpo_sincos(state[4 * i + 2], &cs_out[2 * i + 1], &cs_out[2 * i + 0]);
             continue;
         }
-        float x = state[4 * i + 0], y = state[4 * i + 1];
-        float psi = state[4 * i + 2], v = state[4 * i + 3];
-        float L = dims[3 * i + 0];
-        float a = clampf(act[2 * i + 0], ACC_MIN, ACC_MAX);
-        float delta = clampf(act[2 * i + 1], -STEER_MAX, STEER_MAX);
-        float v1 = clampf(fmaf(a, dt, v), V_MIN, V_MAX);
-        float sd, cd;
-        gpo_sincos(delta, &sd, &cd);
-        float kappa = sd / (cd * (WHEELBASE_FRAC * L));
-        float vdt = v1 * dt;
-        float psi1 = fmaf(vdt, kappa, psi);
-        if (psi1 > PI_F)
-            psi1 = psi1 - TWO_PI_F;
-        else if (psi1 <= -PI_F)
-            psi1 = psi1 + TWO_PI_F;
-        float sp, cp;
-        gpo_sincos(psi1, &sp, &cp);
-        state[4 * i + 0] = fmaf(vdt, cp, x);
-        state[4 * i + 1] = fmaf(vdt, sp, y);
-        state[4 * i + 2] = psi1;
-        state[4 * i + 3] = v1;
-        if (cs_out) {
-            cs_out[2 * i + 0] = cp;
-            cs_out[2 * i + 1] = sp;
+        bicycle(state + 4 * i, dims[3 * i + 0], act[2 * i + 0], act[2 * i + 1], dt,
+                cs_out ? cs_out + 2 * i : NULL);
+    }
+}
+
+/* ------------------------------------------------------- jerk actuation
+ * App. A, "Action Space and Dynamics": twelve discrete actions, the product of
+ * the longitudinal jerks {-15, -4, 0, 4} m/s^3 and the lateral jerks
+ * {-4, 0, 4} m/s^3.  The jerks are integrated into the longitudinal and
+ * lateral accelerations, and those into the speed and the steering, with the
+ * accelerations clipped to g-force limits, the speed to the speed limit and
+ * the steering angle and its rate bounded; the wheelbase is 60% of the
+ * length.  The paper leaves the derivation and the constants to Gigaflow, so
+ * the following are readings:
+ *   - action k = 3 * lon + lat, lon indexing the longitudinal set and lat the
+ *     lateral one; an index outside 0..11 coasts (both jerks zero);
+ *   - limits: a_lon in [-6, 3] m/s^2 (as the direct step), |a_lat| <= 4 m/s^2,
+ *     |steering rate| <= 0.6 rad/s, |delta| <= 0.5 rad, v in [0, 30] m/s;
+ *   - the lateral acceleration sets the steering through the path curvature
+ *     of the bicycle, a_lat = v^2 tan(delta) / l with l = 0.6 L, the speed
+ *     floored at 1 m/s;
+ *   - the actuator state keeps the accelerations the vehicle realised:
+ *     a_lon is dropped to 0 where the speed clip cancelled it, a_lat is
+ *     v'^2 kappa of the step taken.
+ * One step, binary32 with explicit fmaf:
+ *   a_lon1 = clamp(fmaf(j_lon, dt, a_lon), -6, 3)
+ *   a_lat1 = clamp(fmaf(j_lat, dt, a_lat), -4, 4)
+ *   v1     = clamp(fmaf(a_lon1, dt, v), 0, 30)
+ *   tau    = clamp((a_lat1 * l) / max(v1 * v1, 1), -T, T),  T = binary32 tan 0.5
+ *   delta1 = clamp(atan(tau), fmaf(-R, dt, delta), fmaf(R, dt, delta)), R = 0.6,
+ *            then clamp(delta1, -0.5, 0.5)
+ *   pose   = bicycle(a_lon1, delta1) as in the direct step (its clamps are
+ *            then identities), giving kappa
+ *   actuators' = (v1 == fmaf(a_lon1, dt, v) ? a_lon1 : 0, (v1 * v1) * kappa, delta1)
+ * state [n][4] and actuators [n][4] = a_lon, a_lat, delta, 0 are updated in
+ * place; actions [n] are uint8 indices.  Halted agents keep both.
+ */
+#define JERK_LAT_ACC_MAX 4.0f
+#define JERK_STEER_RATE  0.6f
+#define JERK_V_FLOOR2    1.0f
+#define TAN_STEER_MAX    0.546302497f   /* binary32 nearest to tan(0.5) */
+
+static const float JERK_LON[4] = {-15.0f, -4.0f, 0.0f, 4.0f};
+static const float JERK_LAT[3] = {-4.0f, 0.0f, 4.0f};
+
+/* atan(x) for |x| <= tan(0.5): the Maclaurin series
+ *   atan x = x - x^3/3 + x^5/5 - ... + x^25/25
+ * (truncation below 3e-9 there), as x + x^3 Q(x^2) with Q evaluated by
+ * Horner in fmaf; each coefficient is the binary32 quotient 1 / (2k + 1). */
+float gpo_atan_small(float x)
+{
+    float u = x * x;
+    float q = 1.0f / 25.0f;
+    q = fmaf(u, q, -1.0f / 23.0f);
+    q = fmaf(u, q, 1.0f / 21.0f);
+    q = fmaf(u, q, -1.0f / 19.0f);
+    q = fmaf(u, q, 1.0f / 17.0f);
+    q = fmaf(u, q, -1.0f / 15.0f);
+    q = fmaf(u, q, 1.0f / 13.0f);
+    q = fmaf(u, q, -1.0f / 11.0f);
+    q = fmaf(u, q, 1.0f / 9.0f);
+    q = fmaf(u, q, -1.0f / 7.0f);
+    q = fmaf(u, q, 1.0f / 5.0f);
+    q = fmaf(u, q, -1.0f / 3.0f);
+    return fmaf(x * u, q, x);
+}
+
+void gpo_step_jerk(int n, float *state, const float *dims, float *actuators, const uint8_t *actions,
+                   float dt, float *cs_out, const uint8_t *halted)
+{
+    for (int i = 0; i < n; ++i) {
+        float *st = state + 4 * i, *ac = actuators + 4 * i;
+        if (halted && halted[i]) {
+            if (cs_out) gpo_sincos(st[2], &cs_out[2 * i + 1], &cs_out[2 * i + 0]);
+            continue;
         }
+        int k = actions[i];
+        float jl = 0.0f, jt = 0.0f;
+        if (k < 12) {
+            jl = JERK_LON[k / 3];
+            jt = JERK_LAT[k % 3];
+        }
+        float L = dims[3 * i + 0];
+        float l = WHEELBASE_FRAC * L;
+        float v = st[3];
+        float a_lon1 = clampf(fmaf(jl, dt, ac[0]), ACC_MIN, ACC_MAX);
+        float a_lat1 = clampf(fmaf(jt, dt, ac[1]), -JERK_LAT_ACC_MAX, JERK_LAT_ACC_MAX);
+        float v_free = fmaf(a_lon1, dt, v);
+        float v1 = clampf(v_free, V_MIN, V_MAX);
+        float tau = clampf((a_lat1 * l) / fmaxf(v1 * v1, JERK_V_FLOOR2), -TAN_STEER_MAX, TAN_STEER_MAX);
+        float d1 = clampf(gpo_atan_small(tau), fmaf(-JERK_STEER_RATE, dt, ac[2]),
+                          fmaf(JERK_STEER_RATE, dt, ac[2]));
+        d1 = clampf(d1, -STEER_MAX, STEER_MAX);
+        float kappa = bicycle(st, L, a_lon1, d1, dt, cs_out ? cs_out + 2 * i : NULL);
+        ac[0] = v1 == v_free ? a_lon1 : 0.0f;
+        ac[1] = (v1 * v1) * kappa;
+        ac[2] = d1;
+        ac[3] = 0.0f;
     }
 }
 
