@@ -133,9 +133,32 @@ gp_status gp_sim_render(gp_sim *sim, uint8_t *d_rgb, float *d_depth, int32_t *d_
  * Uses the persistent schedule whatever the current launch setting. */
 gp_status gp_sim_step_render_graph(gp_sim *sim, const float *d_actions, uint8_t *d_rgb, void *stream);
 
+/* Jerk-actuated step of every agent (App. A, "Action Space and Dynamics":
+ * twelve discrete actions, the product of longitudinal jerks {-15, -4, 0, 4}
+ * m/s^3 and lateral jerks {-4, 0, 4} m/s^3, integrated into accelerations,
+ * then into speed and steering; wheelbase 60% of the length).  d_actions:
+ * device uint8 [total_agents], index 3 * lon + lat (lon over the longitudinal
+ * set, lat over the lateral one); any index above 11 coasts (both jerks 0).
+ * The sim keeps each agent's actuators (longitudinal and lateral
+ * acceleration, steering angle), zero after create and set_state.  Limits:
+ * longitudinal acceleration in [-6, 3] m/s^2, lateral within 4 m/s^2, speed
+ * in [0, 30] m/s, steering angle within 0.5 rad moving at most 0.6 rad/s; the
+ * lateral acceleration sets the steering through the bicycle's path
+ * curvature (tan(angle) = a_lat * 0.6 L / v^2, v floored at 1 m/s).  Halted
+ * agents keep state and actuators.  gp_sim_step (direct acceleration and
+ * steering) leaves the actuators untouched.  Stream-ordered; GP_EINVAL on a
+ * NULL argument. */
+gp_status gp_sim_step_jerk(gp_sim *sim, const uint8_t *d_actions, void *stream);
+
+/* Copy the jerk actuators out: device float [total_agents][4] = longitudinal
+ * acceleration (m/s^2; 0 where the speed clip cancelled it), lateral
+ * acceleration (v^2 times the path curvature of the last jerk step), steering
+ * angle (rad), 0.  Device to device, stream-ordered. */
+gp_status gp_sim_get_actuators(gp_sim *sim, float *d_dst, void *stream);
+
 /* Copy the agent state [total_agents][4] out of / into the sim (device to
  * device, stream-ordered).  set_state also refreshes the heading cosines and
- * clears every agent's halted flag (a new episode). */
+ * clears every agent's halted flag and jerk actuators (a new episode). */
 gp_status gp_sim_get_state(gp_sim *sim, float *d_dst, void *stream);
 gp_status gp_sim_set_state(gp_sim *sim, const float *d_src, void *stream);
 
@@ -177,9 +200,9 @@ gp_status gp_batch_step_render(gp_sim *const *sims, int32_t n_sims, const float 
  * bit 2 halted (after it).  Stream-ordered. */
 gp_status gp_sim_check_infractions(gp_sim *sim, uint8_t *d_flags, void *stream);
 
-/* Fork: make dst's dynamic state (agent state, heading cosines, halted flags)
- * a copy of src's (the paper rolls a teacher out in a forked copy of the
- * simulator, Sec. 3 "Pixel-based student training").  Both sims must have
+/* Fork: make dst's dynamic state (agent state, heading cosines, halted flags,
+ * jerk actuators) a copy of src's (the paper rolls a teacher out in a forked
+ * copy of the simulator, Sec. 3 "Pixel-based student training").  Both sims must have
  * been created over the same scenes.  Device-to-device, stream-ordered. */
 gp_status gp_sim_fork(gp_sim *dst, const gp_sim *src, void *stream);
 

@@ -59,6 +59,7 @@ struct DevSim {
     float road_zmax;          // no pixel sample sees the road plane beyond this depth
     uint8_t *halted;          // [A] 1 once the agent committed an infraction (frozen in place)
     uint8_t *infr;            // [A] infractions found by the last check (bit 0 collision, 1 off-road)
+    float4 *actu;             // [A] jerk actuators: a_lon, a_lat, steering angle, 0
     float cam_dir[kMaxCams][2];
     float focal, cam_height, z_near, z_far, dt;
 };
@@ -86,7 +87,10 @@ struct LaunchCfg {
 // Host-side launch helpers (defined in gp_kernels.hip).
 hipError_t launch_step(const DevSim &s, const float *actions, int agent_begin, int agent_count,
                        hipStream_t st);
+// clear_halted = 1 also clears the halted flags and the jerk actuators
 hipError_t launch_cs(const DevSim &s, int clear_halted, hipStream_t st);
+// jerk-actuated step of every agent; actions [A] uint8 indices 0..11
+hipError_t launch_step_jerk(const DevSim &s, const uint8_t *actions, hipStream_t st);
 // infraction check of every agent; flags_out (optional) [A] gets bit 0
 // collision, bit 1 off-road, bit 2 halted after the check
 hipError_t launch_infractions(const DevSim &s, int max_agents, uint8_t *flags_out, hipStream_t st);

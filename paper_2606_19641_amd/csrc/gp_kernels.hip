@@ -2,7 +2,10 @@
 //
 //   k_step         kinematic bicycle step, one thread per agent
 //                  (App. A, "Action Space and Dynamics"; dt from App. B)
+//   k_step_jerk    jerk-actuated step over the twelve discrete actions
 //   k_cs           heading cosines of the current state (after create / set_state)
+//   k_infr_flags   collision and off-road checks, one wavefront per agent
+//   k_infr_apply   halting of the offenders
 //   k_render<0>    general ego-centric raster: rgb + optional depth and
 //                  primitive id, any road colours
 //   k_render<1>    rgb-only raster for scenes whose road strips share one colour
@@ -71,14 +74,12 @@ __device__ __forceinline__ void dev_sincos(float t, float &s, float &c)
 
 // ------------------------------------------------------------ agent step
 
-__device__ __forceinline__ void step_agent(const DevSim &s, const float2 *act, int i)
+// One bicycle update of agent i from state st (App. A: wheelbase 60% of the
+// length; acceleration, speed and steering clipped); returns the curvature.
+__device__ __forceinline__ float bicycle(const DevSim &s, int i, float4 st, float L, float accel, float steer)
 {
-    if (s.halted[i]) return;                      // halted in place (App. A): state unchanged
-    const float4 st = s.state[i];
-    const float L = s.dims[i].x;
-    const float2 u = act[i];
-    const float a = fminf(fmaxf(u.x, -6.0f), 3.0f);
-    const float delta = fminf(fmaxf(u.y, -0.5f), 0.5f);
+    const float a = fminf(fmaxf(accel, -6.0f), 3.0f);
+    const float delta = fminf(fmaxf(steer, -0.5f), 0.5f);
     const float v1 = fminf(fmaxf(fmaf(a, s.dt, st.w), 0.0f), 30.0f);
     float sd, cd;
     dev_sincos(delta, sd, cd);
@@ -93,6 +94,14 @@ __device__ __forceinline__ void step_agent(const DevSim &s, const float2 *act, i
     dev_sincos(psi, sp, cp);
     s.state[i] = make_float4(fmaf(vdt, cp, st.x), fmaf(vdt, sp, st.y), psi, v1);
     s.cs[i] = make_float2(cp, sp);
+    return kappa;
+}
+
+__device__ __forceinline__ void step_agent(const DevSim &s, const float2 *act, int i)
+{
+    if (s.halted[i]) return;                      // halted in place (App. A): state unchanged
+    const float2 u = act[i];
+    (void)bicycle(s, i, s.state[i], s.dims[i].x, u.x, u.y);
 }
 
 __global__ void k_step(DevSim s, const float2 *__restrict__ act, int begin, int count)
@@ -112,11 +121,73 @@ __global__ void k_step_multi(const SimEntry *__restrict__ tab)
     step_agent(s, e.act, i);
 }
 
+// ------------------------------------------------------- jerk actuation
+//
+// App. A: twelve discrete actions, longitudinal jerk {-15, -4, 0, 4} m/s^3 x
+// lateral jerk {-4, 0, 4} m/s^3 (index 3 * lon + lat; any other index coasts
+// with both jerks zero).  The jerks integrate into the accelerations (a_lon
+// in [-6, 3], |a_lat| <= 4 m/s^2), a_lon into the speed, a_lat into the
+// steering angle whose path curvature gives that lateral acceleration
+// (tan delta = a_lat l / v^2, l = 0.6 L, v floored at 1 m/s), the angle moving
+// at most 0.6 rad/s and staying within 0.5 rad; the pose then follows the
+// bicycle.  The actuator record keeps what the vehicle realised: a_lon, or 0
+// where the speed clip cancelled it, and v^2 kappa as a_lat.  binary32, every
+// fused operation an explicit fmaf.
+
+__constant__ float kJerkLon[4] = {-15.0f, -4.0f, 0.0f, 4.0f};
+__constant__ float kJerkLat[3] = {-4.0f, 0.0f, 4.0f};
+
+// atan x for |x| <= tan 0.5 from its Maclaurin series through x^25
+// (truncation below 3e-9 there): x + x^3 Q(x^2), Q by Horner in fmaf, each
+// coefficient the binary32 quotient 1 / (2k + 1)
+__device__ __forceinline__ float atan_small(float x)
+{
+    const float u = x * x;
+    float q = 1.0f / 25.0f;
+    q = fmaf(u, q, -1.0f / 23.0f);
+    q = fmaf(u, q, 1.0f / 21.0f);
+    q = fmaf(u, q, -1.0f / 19.0f);
+    q = fmaf(u, q, 1.0f / 17.0f);
+    q = fmaf(u, q, -1.0f / 15.0f);
+    q = fmaf(u, q, 1.0f / 13.0f);
+    q = fmaf(u, q, -1.0f / 11.0f);
+    q = fmaf(u, q, 1.0f / 9.0f);
+    q = fmaf(u, q, -1.0f / 7.0f);
+    q = fmaf(u, q, 1.0f / 5.0f);
+    q = fmaf(u, q, -1.0f / 3.0f);
+    return fmaf(x * u, q, x);
+}
+
+__global__ void k_step_jerk(DevSim s, const uint8_t *__restrict__ act)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= s.n_agents || s.halted[i]) return;
+    const int k = act[i];
+    const float jl = k < 12 ? kJerkLon[k / 3] : 0.0f;
+    const float jt = k < 12 ? kJerkLat[k % 3] : 0.0f;
+    const float4 st = s.state[i];
+    const float4 ac = s.actu[i];
+    const float L = s.dims[i].x, l = 0.6f * L;
+    const float a_lon = fminf(fmaxf(fmaf(jl, s.dt, ac.x), -6.0f), 3.0f);
+    const float a_lat = fminf(fmaxf(fmaf(jt, s.dt, ac.y), -4.0f), 4.0f);
+    const float v_free = fmaf(a_lon, s.dt, st.w);
+    const float v1 = fminf(fmaxf(v_free, 0.0f), 30.0f);
+    const float tan_max = 0.546302497f;      // binary32 nearest to tan 0.5
+    const float tau = fminf(fmaxf((a_lat * l) / fmaxf(v1 * v1, 1.0f), -tan_max), tan_max);
+    float d1 = fminf(fmaxf(atan_small(tau), fmaf(-0.6f, s.dt, ac.z)), fmaf(0.6f, s.dt, ac.z));
+    d1 = fminf(fmaxf(d1, -0.5f), 0.5f);
+    const float kappa = bicycle(s, i, st, L, a_lon, d1);
+    s.actu[i] = make_float4(v1 == v_free ? a_lon : 0.0f, (v1 * v1) * kappa, d1, 0.0f);
+}
+
 __global__ void k_cs(DevSim s, int clear_halted)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= s.n_agents) return;
-    if (clear_halted) s.halted[i] = 0;
+    if (clear_halted) {
+        s.halted[i] = 0;
+        s.actu[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
     float sp, cp;
     dev_sincos(s.state[i].z, sp, cp);
     s.cs[i] = make_float2(cp, sp);
@@ -1706,6 +1777,14 @@ hipError_t launch_step(const DevSim &s, const float *actions, int agent_begin, i
     const int B = 256;
     hipLaunchKernelGGL(k_step, dim3((agent_count + B - 1) / B), dim3(B), 0, st, s,
                        reinterpret_cast<const float2 *>(actions), agent_begin, agent_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_jerk(const DevSim &s, const uint8_t *actions, hipStream_t st)
+{
+    if (s.n_agents <= 0) return hipSuccess;
+    const int B = 256;
+    hipLaunchKernelGGL(k_step_jerk, dim3((s.n_agents + B - 1) / B), dim3(B), 0, st, s, actions);
     return hipGetLastError();
 }
 

@@ -47,7 +47,7 @@ int64_t n_bins_of(int32_t n_roads) { return 2 * ((n_roads + gp::kBinQuads - 1) /
 constexpr float kBinExtent = 32.0f;   // metres
 
 struct Layout {
-    int64_t halted, infr;
+    int64_t halted, infr, actu;
     int64_t scenes, views, state, cs, dims, agent_color, roads, road_index, road_color, bins, palette,
         queue, counter;
     int64_t total;
@@ -121,6 +121,7 @@ Layout make_layout(const gp_config *cfg, const gp_scene_desc *sc, int32_t n)
     L.palette = take(768);
     L.halted = take(L.n_agents);
     L.infr = take(L.n_agents);
+    L.actu = take(16 * L.n_agents);
     L.queue = take(4 * L.n_views);
     L.counter = take(4 * (gp::kQueues + 2));
     L.total = o;
@@ -457,6 +458,7 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
     D.palette = base + L.palette;
     D.halted = base + L.halted;
     D.infr = base + L.infr;
+    D.actu = reinterpret_cast<float4 *>(base + L.actu);
     D.queue = reinterpret_cast<const int32_t *>(base + L.queue);
     D.counter = reinterpret_cast<uint32_t *>(base + L.counter);
     D.n_scenes = n_scenes;
@@ -706,6 +708,21 @@ gp_status gp_sim_set_state(gp_sim *sim, const float *d_src, void *stream)
     return e == hipSuccess ? GP_OK : hip_fail(e, "heading cosines");
 }
 
+gp_status gp_sim_step_jerk(gp_sim *sim, const uint8_t *d_actions, void *stream)
+{
+    if (!sim || !d_actions) return fail(GP_EINVAL, "NULL argument");
+    hipError_t e = gp::launch_step_jerk(sim->dev, d_actions, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? GP_OK : hip_fail(e, "jerk step launch");
+}
+
+gp_status gp_sim_get_actuators(gp_sim *sim, float *d_dst, void *stream)
+{
+    if (!sim || !d_dst) return fail(GP_EINVAL, "NULL argument");
+    hipError_t e = hipMemcpyAsync(d_dst, sim->dev.actu, 16 * (size_t)sim->lay.n_agents,
+                                  hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? GP_OK : hip_fail(e, "get_actuators copy");
+}
+
 gp_status gp_sim_check_infractions(gp_sim *sim, uint8_t *d_flags, void *stream)
 {
     if (!sim) return fail(GP_EINVAL, "NULL argument");
@@ -728,6 +745,7 @@ gp_status gp_sim_fork(gp_sim *dst, const gp_sim *src, void *stream)
     hipError_t e = hipMemcpyAsync(dst->dev.state, src->dev.state, 16 * n, hipMemcpyDeviceToDevice, hs);
     if (e == hipSuccess) e = hipMemcpyAsync(dst->dev.cs, src->dev.cs, 8 * n, hipMemcpyDeviceToDevice, hs);
     if (e == hipSuccess) e = hipMemcpyAsync(dst->dev.halted, src->dev.halted, n, hipMemcpyDeviceToDevice, hs);
+    if (e == hipSuccess) e = hipMemcpyAsync(dst->dev.actu, src->dev.actu, 16 * n, hipMemcpyDeviceToDevice, hs);
     return e == hipSuccess ? GP_OK : hip_fail(e, "fork copy");
 }
 

@@ -23,7 +23,7 @@ EXPORTS = ("gp_sim_required_bytes", "gp_sim_create", "gp_sim_set_launch", "gp_si
            "gp_sim_step", "gp_sim_render", "gp_sim_step_render_graph", "gp_sim_get_state",
            "gp_sim_set_state", "gp_sim_num_views", "gp_sim_num_agents", "gp_sim_num_scenes",
            "gp_sim_destroy", "gp_last_error", "gp_batch_required_bytes", "gp_batch_step_render",
-           "gp_sim_check_infractions", "gp_sim_fork")
+           "gp_sim_check_infractions", "gp_sim_fork", "gp_sim_step_jerk", "gp_sim_get_actuators")
 
 
 class GpError(RuntimeError):
@@ -91,7 +91,9 @@ def lib() -> C.CDLL:
                                            vp, i64, vp]
         L.gp_sim_check_infractions.argtypes = [vp, vp, vp]
         L.gp_sim_fork.argtypes = [vp, vp, vp]
-        for name in ("gp_sim_check_infractions", "gp_sim_fork", "gp_batch_step_render", "gp_sim_create", "gp_sim_set_launch", "gp_sim_get_launch", "gp_sim_step",
+        L.gp_sim_step_jerk.argtypes = [vp, vp, vp]
+        L.gp_sim_get_actuators.argtypes = [vp, vp, vp]
+        for name in ("gp_sim_check_infractions", "gp_sim_fork", "gp_sim_step_jerk", "gp_sim_get_actuators", "gp_batch_step_render", "gp_sim_create", "gp_sim_set_launch", "gp_sim_get_launch", "gp_sim_step",
                      "gp_sim_render", "gp_sim_step_render_graph", "gp_sim_get_state",
                      "gp_sim_set_state"):
             getattr(L, name).restype = C.c_int
@@ -221,6 +223,19 @@ class Sim:
         self._check_tensor(actions, (self.n_agents, 2), "float32")
         _check(lib().gp_sim_step(self._h, actions.data_ptr(), _stream_handle(stream)))
 
+    def step_jerk(self, actions, stream=None):
+        """actions: uint8 [n_agents] device tensor of jerk-action indices 0..11
+        (3 * longitudinal + lateral; larger indices coast)."""
+        self._check_tensor(actions, (self.n_agents,), "uint8")
+        _check(lib().gp_sim_step_jerk(self._h, actions.data_ptr(), _stream_handle(stream)))
+
+    def get_actuators(self, stream=None):
+        """float32 [n_agents, 4]: longitudinal and lateral acceleration, steering angle, 0."""
+        import torch
+        out = torch.empty((self.n_agents, 4), dtype=torch.float32, device=self.device)
+        _check(lib().gp_sim_get_actuators(self._h, out.data_ptr(), _stream_handle(stream)))
+        return out
+
     def render(self, rgb=None, depth=False, primid=False, stream=None):
         """Render every view; returns (rgb, depth or None, primid or None)."""
         import torch
@@ -260,7 +275,7 @@ class Sim:
         return flags
 
     def fork_from(self, src: "Sim", stream=None):
-        """Copy src's agent state, heading cosines and halted flags into this sim."""
+        """Copy src's agent state, heading cosines, halted flags and jerk actuators into this sim."""
         _check(lib().gp_sim_fork(self._h, src._h, _stream_handle(stream)))
 
     def _check_tensor(self, t, shape, dtype):
