@@ -43,7 +43,8 @@ class _Camera(C.Structure):
     _fields_ = [("width", C.c_int), ("height", C.c_int),
                 ("focal_px", C.c_float), ("cam_height", C.c_float),
                 ("z_near", C.c_float), ("z_far", C.c_float),
-                ("palette", C.c_void_p)]
+                ("palette", C.c_void_p), ("shade", C.c_int), ("light", C.c_float * 3),
+                ("ambient", C.c_float)]
 
 
 def lib():
@@ -160,8 +161,10 @@ class View:
 
 
 def render_view(state, dims, agent_color, road_xy, road_color, camera, palette,
-                ego: int, cam_dir=(1.0, 0.0)) -> View:
-    """Render one ego view.  `camera` has width, height, focal_px, cam_height, z_near, z_far."""
+                ego: int, cam_dir=(1.0, 0.0), light=None) -> View:
+    """Render one ego view.  `camera` has width, height, focal_px, cam_height, z_near, z_far.
+    `light` = (lx, ly, lz, ambient) turns on directional shading (unit direction
+    towards the light, world frame)."""
     st = np.ascontiguousarray(state, dtype=np.float32)
     dm = np.ascontiguousarray(dims, dtype=np.float32)
     ac = np.ascontiguousarray(agent_color, dtype=np.uint8)
@@ -171,6 +174,10 @@ def render_view(state, dims, agent_color, road_xy, road_color, camera, palette,
     sc = _Scene(st.shape[0], rx.shape[0], _ptr(st), _ptr(dm), _ptr(ac), _ptr(rx), _ptr(rc))
     W, H = int(camera.width), int(camera.height)
     cm = _Camera(W, H, camera.focal_px, camera.cam_height, camera.z_near, camera.z_far, _ptr(pal))
+    if light is not None:
+        cm.shade = 1
+        cm.light[0], cm.light[1], cm.light[2] = (float(np.float32(x)) for x in light[:3])
+        cm.ambient = float(np.float32(light[3]))
     key = np.empty(H * W, dtype=np.uint64)
     rgb = np.empty((H, W, 3), dtype=np.uint8)
     depth = np.empty((H, W), dtype=np.float32)
@@ -182,10 +189,10 @@ def render_view(state, dims, agent_color, road_xy, road_color, camera, palette,
     return View(rgb, depth, prim, int(nt), int(nf.value))
 
 
-def render_scene_view(scene, camera, palette, ego: int, cam: int = 0) -> View:
+def render_scene_view(scene, camera, palette, ego: int, cam: int = 0, light=None) -> View:
     """Render view (ego, cam) of a scenegen.Scene-like object."""
     return render_view(scene.agent_state, scene.agent_dims, scene.agent_color, scene.road_xy,
-                       scene.road_color, camera, palette, ego, camera.cam_dirs[cam])
+                       scene.road_color, camera, palette, ego, camera.cam_dirs[cam], light)
 
 
 def render_views(items, camera, palette, threads: int = 1):

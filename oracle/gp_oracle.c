@@ -255,6 +255,9 @@ typedef struct {
     int width, height;
     float focal_px, cam_height, z_near, z_far;
     const uint8_t *palette;       /* [256][3] */
+    int shade;                    /* 1: directional light, see shade_level */
+    float light[3];               /* unit vector towards the light, world frame */
+    float ambient;                /* in [0, 1] */
 } gpo_camera;
 
 typedef struct { float x, y, z; } v3;
@@ -507,6 +510,28 @@ static void make_view(view_t *vw, const gpo_scene *sc, const gpo_camera *cam, in
     vw->z_far = cam->z_far;
 }
 
+/* ------------------------------------------------------------- shading
+ * App. A: shading is minimal, one directional light per world with a colour
+ * per instance.  Reading: the light is a unit direction l towards the light in
+ * the world frame, the same in every ego's world, with an ambient term a; a
+ * surface with outward unit normal n is lit by
+ *     s = a + (1 - a) max(0, n . l)
+ * turned into an integer level q = floor(255 s + 0.5) (binary32, fmaf), and
+ * each colour channel c becomes (c q + 127) / 255 in integers.  The box faces'
+ * normals follow the box heading (front (c, s, 0), left (-s, c, 0), back,
+ * right, top +z, bottom -z, with (c, s) the project's sincos of the heading);
+ * road strips face +z; the background is not lit. */
+static uint32_t shade_level(const gpo_camera *cam, float nx, float ny, int face)
+{
+    float d;
+    if (face < 4)
+        d = fmaf(nx, cam->light[0], ny * cam->light[1]);
+    else
+        d = face == 4 ? cam->light[2] : -cam->light[2];
+    float s = fmaf(1.0f - cam->ambient, fmaxf(d, 0.0f), cam->ambient);
+    return (uint32_t)fmaf(s, 255.0f, 0.5f);
+}
+
 /* Render the view of agent `ego` through the camera whose yaw offset is
  * (ck, sk) = (cos, sin).  Outputs (any may be NULL): rgb [H][W][3], depth
  * [H][W] (1/invz, +inf for background), primid [H][W] (-1 for background).
@@ -592,9 +617,22 @@ long long gpo_render_view(const gpo_scene *sc, const gpo_camera *cam, int ego, f
             dep = 1.0f / invz;
         }
         if (rgb) {
-            rgb[3 * p + 0] = cam->palette[3 * color + 0];
-            rgb[3 * p + 1] = cam->palette[3 * color + 1];
-            rgb[3 * p + 2] = cam->palette[3 * color + 2];
+            uint32_t q = 255;
+            if (cam->shade && prim >= 0) {
+                if (prim < (int32_t)(6 * n_a)) {
+                    float sj, cj;
+                    gpo_sincos(sc->agent_state[4 * (prim / 6) + 2], &sj, &cj);
+                    const int f = prim % 6;
+                    const float nx[4] = { cj, -sj, -cj, sj }, ny[4] = { sj, cj, -sj, -cj };
+                    q = shade_level(cam, f < 4 ? nx[f] : 0.0f, f < 4 ? ny[f] : 0.0f, f);
+                } else {
+                    q = shade_level(cam, 0.0f, 0.0f, 4);
+                }
+            }
+            for (int ch = 0; ch < 3; ++ch) {
+                uint32_t c = cam->palette[3 * color + ch];
+                rgb[3 * p + ch] = (uint8_t)(cam->shade && prim >= 0 ? (c * q + 127u) / 255u : c);
+            }
         }
         if (depth) depth[p] = dep;
         if (primid) primid[p] = prim;
