@@ -156,6 +156,19 @@ gp_status gp_sim_step_jerk(gp_sim *sim, const uint8_t *d_actions, void *stream);
  * angle (rad), 0.  Device to device, stream-ordered. */
 gp_status gp_sim_get_actuators(gp_sim *sim, float *d_dst, void *stream);
 
+/* Directional light (App. A: shading is one directional light per world with
+ * a colour per instance).  h_light: host float[4] = unit direction towards
+ * the light in the world frame (norm within 1e-3 of 1) and the ambient term a
+ * in [0, 1], the same light in every ego's world; NULL turns shading off (the
+ * default: flat palette colours).  With the light on, a face with outward
+ * normal n shows each channel c of its palette colour as (c q + 127) / 255,
+ * q = floor(255 (a + (1 - a) max(0, n . l)) + 0.5) in binary32; box faces
+ * turn with the box heading, road strips face up, the background is unlit.
+ * Lit frames are rendered by the general kernel.  Host-side only (takes
+ * effect at the next render, drops a captured step + render graph); GP_EINVAL
+ * on a bad light. */
+gp_status gp_sim_set_light(gp_sim *sim, const float *h_light);
+
 /* Copy the agent state [total_agents][4] out of / into the sim (device to
  * device, stream-ordered).  set_state also refreshes the heading cosines and
  * clears every agent's halted flag and jerk actuators (a new episode). */

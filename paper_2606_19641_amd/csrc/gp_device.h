@@ -62,6 +62,8 @@ struct DevSim {
     float4 *actu;             // [A] jerk actuators: a_lon, a_lat, steering angle, 0
     float cam_dir[kMaxCams][2];
     float focal, cam_height, z_near, z_far, dt;
+    float light[4];           // unit direction towards the light (world frame), ambient
+    int32_t shade;            // 1: faces lit by the directional light
 };
 
 struct RenderOut {

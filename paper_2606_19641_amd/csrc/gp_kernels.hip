@@ -1373,6 +1373,48 @@ __device__ __forceinline__ void clear_band(Lds &L, int npix)
 // 1/z of pixel (i, j) is fma(A, du, y) = y for y = fma(B, dv, C) != 0: one
 // value per row, positive exactly below the horizon.  A box fragment beats
 // the road where its 1/z is not smaller (agents rank above roads on ties).
+// ------------------------------------------------------------ shading
+//
+// App. A: one directional light per world, a colour per instance.  With the
+// light on, a face with outward unit normal n is lit by
+// s = a + (1 - a) max(0, n . l) (l towards the light, world frame, a the
+// ambient term), quantised to the level q = floor(255 s + 0.5) in binary32,
+// and each channel c of its colour becomes (c q + 127) / 255.  Box normals
+// follow the heading cosines (front, left, back, right, top, bottom), road
+// strips face up; the background is not lit.  Lit frames are resolved by the
+// general kernel only.
+
+__device__ __forceinline__ uint32_t shade_level(const DevSim &s, float nx, float ny, int face)
+{
+    // the light is read into scalars first: selecting between fields of the
+    // kernel-argument record would make the compiler keep it in memory
+    const float lx = s.light[0], ly = s.light[1], lz = s.light[2], amb = s.light[3];
+    const float side = fmaf(nx, lx, ny * ly);
+    const float d = face < 4 ? side : (face == 4 ? lz : -lz);
+    const float sh = fmaf(1.0f - amb, fmaxf(d, 0.0f), amb);
+    return (uint32_t)fmaf(sh, 255.0f, 0.5f);
+}
+
+__device__ __forceinline__ uint32_t shade_rgb(uint32_t c, uint32_t q)
+{
+    const uint32_t r = ((c & 0xFFu) * q + 127u) / 255u;
+    const uint32_t g = (((c >> 8) & 0xFFu) * q + 127u) / 255u;
+    const uint32_t b = (((c >> 16) & 0xFFu) * q + 127u) / 255u;
+    return r | (g << 8) | (b << 16);
+}
+
+// lit colour c of the box face that a winning key names (agent and face from
+// the key's primitive index, the scene's agents from agent_base)
+__device__ __forceinline__ uint32_t lit_box(const DevSim &s, int agent_base, uint32_t c, unsigned long long key)
+{
+    const int prim = (kMaxPrims - 1) - (int)(((uint32_t)key >> 8) & (uint32_t)(kMaxPrims - 1));
+    const int j = prim / 6, f = prim - 6 * j;
+    const float2 cs = s.cs[agent_base + j];
+    const float nx = f == 0 ? cs.x : f == 1 ? -cs.y : f == 2 ? -cs.x : cs.y;
+    const float ny = f == 0 ? cs.y : f == 1 ? cs.x : f == 2 ? -cs.y : -cs.x;
+    return shade_rgb(c, shade_level(s, nx, ny, f));
+}
+
 // colour of a pixel of the rgb kernel: a box fragment wins where its 1/z is
 // not below the road's (agents rank above roads on ties); else road or
 // background by the coverage bit
@@ -1502,15 +1544,24 @@ __device__ void resolve_rows_lut(const Cam &cam, Lds &L, uint8_t *rgb, int64_t v
     }
 }
 
-// general kernel: key band -> colour, depth, primitive id.
-__device__ void resolve_general(const Cam &cam, Lds &L, const RenderOut &o, int64_t view, int b0, int b1)
+// general kernel: key band -> colour (lit when the light is on), depth,
+// primitive id.
+__device__ void resolve_general(const DevSim &s, const SceneRec &sc, const Cam &cam, Lds &L, const RenderOut &o,
+                                int64_t view, int b0, int b1)
 {
     const int W = cam.W;
     const int npix = (b1 - b0) * W;
     const int64_t pix0 = view * (int64_t)W * cam.H + (int64_t)b0 * W;
+    const uint32_t q_road = s.shade ? shade_level(s, 0.0f, 0.0f, 4) : 255u;
     for (int p = threadIdx.x; p < npix; p += blockDim.x) {
         const unsigned long long key = L.zb[p];
-        const uint32_t c = L.pal[key ? ((uint32_t)key & 0xFFu) : 0u];
+        uint32_t c = L.pal[key ? ((uint32_t)key & 0xFFu) : 0u];
+        if (s.shade && key) {
+            // boxes hold the primitives below 6 n_agents
+            const bool box = (((uint32_t)key >> 8) & (uint32_t)(kMaxPrims - 1)) >
+                             (uint32_t)(kMaxPrims - 1 - 6 * sc.n_agents);
+            c = box ? lit_box(s, sc.agent_base, c, key) : shade_rgb(c, q_road);
+        }
         uint8_t *dst = o.rgb + 3 * (pix0 + p);
         dst[0] = (uint8_t)c;
         dst[1] = (uint8_t)(c >> 8);
@@ -1593,7 +1644,7 @@ __device__ void render_view(const DevSim &s, const RenderOut &o, const LaunchCfg
             flush_tris(cam, L, KB);
         }
         if (FAST) resolve_fast<true>(s, cam, L, o.rgb, view, b0, b1, b0);
-        else resolve_general(cam, L, o, view, b0, b1);
+        else resolve_general(s, sc, cam, L, o, view, b0, b1);
         __syncthreads();
     }
 }

@@ -242,6 +242,7 @@ struct gp_sim {
     const float *g_act = nullptr;
     uint8_t *g_rgb = nullptr;
     gp_launch g_launch{};
+    int32_t road_uniform = 0;   // every road strip of every scene has one colour
 };
 
 namespace {
@@ -258,7 +259,7 @@ gp::LaunchCfg launch_cfg(const gp_launch &l)
 gp_status check_lds(const gp_sim *sim, const gp_launch &l)
 {
     const size_t need = std::max(gp::render_lds_bytes(sim->dev, launch_cfg(l), 0),
-                                 sim->dev.road_color_uniform ? gp::render_lds_bytes(sim->dev, launch_cfg(l), 1) : 0);
+                                 sim->road_uniform ? gp::render_lds_bytes(sim->dev, launch_cfg(l), 1) : 0);
     if (need > sim->max_lds)
         return fail(GP_EINVAL, "launch needs %zu B of LDS, the device allows %zu", need, sim->max_lds);
     return GP_OK;
@@ -467,7 +468,9 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
     D.width = cfg->width;
     D.height = cfg->height;
     D.n_cams = cfg->n_cams;
-    D.road_color_uniform = uniform ? 1 : 0;
+    sim->road_uniform = uniform ? 1 : 0;
+    D.road_color_uniform = sim->road_uniform;    // the rgb kernel needs unlit frames too
+    D.shade = 0;
     D.road_color0 = color0 < 0 ? 0 : color0;
     for (int k = 0; k < gp::kMaxCams; ++k) {
         D.cam_dir[k][0] = cfg->cam_dir[k][0];
@@ -706,6 +709,25 @@ gp_status gp_sim_set_state(gp_sim *sim, const float *d_src, void *stream)
     if (e != hipSuccess) return hip_fail(e, "set_state copy");
     e = gp::launch_cs(sim->dev, 1, hs);
     return e == hipSuccess ? GP_OK : hip_fail(e, "heading cosines");
+}
+
+gp_status gp_sim_set_light(gp_sim *sim, const float *h_light)
+{
+    if (!sim) return fail(GP_EINVAL, "NULL argument");
+    if (h_light) {
+        for (int k = 0; k < 4; ++k)
+            if (!std::isfinite(h_light[k])) return fail(GP_EINVAL, "light not finite");
+        const double n = std::sqrt((double)h_light[0] * h_light[0] + (double)h_light[1] * h_light[1] +
+                                   (double)h_light[2] * h_light[2]);
+        if (std::fabs(n - 1.0) > 1e-3) return fail(GP_EINVAL, "light direction is not a unit vector (norm %g)", n);
+        if (!(h_light[3] >= 0.0f && h_light[3] <= 1.0f)) return fail(GP_EINVAL, "ambient outside [0, 1]");
+    }
+    drop_graph(sim);            // a captured graph holds the old kernel arguments
+    sim->dev.shade = h_light ? 1 : 0;
+    for (int k = 0; k < 4; ++k) sim->dev.light[k] = h_light ? h_light[k] : 0.0f;
+    // lit frames are resolved by the general kernel
+    sim->dev.road_color_uniform = (sim->road_uniform && !h_light) ? 1 : 0;
+    return GP_OK;
 }
 
 gp_status gp_sim_step_jerk(gp_sim *sim, const uint8_t *d_actions, void *stream)

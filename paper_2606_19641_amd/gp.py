@@ -23,7 +23,8 @@ EXPORTS = ("gp_sim_required_bytes", "gp_sim_create", "gp_sim_set_launch", "gp_si
            "gp_sim_step", "gp_sim_render", "gp_sim_step_render_graph", "gp_sim_get_state",
            "gp_sim_set_state", "gp_sim_num_views", "gp_sim_num_agents", "gp_sim_num_scenes",
            "gp_sim_destroy", "gp_last_error", "gp_batch_required_bytes", "gp_batch_step_render",
-           "gp_sim_check_infractions", "gp_sim_fork", "gp_sim_step_jerk", "gp_sim_get_actuators")
+           "gp_sim_check_infractions", "gp_sim_fork", "gp_sim_step_jerk", "gp_sim_get_actuators",
+           "gp_sim_set_light")
 
 
 class GpError(RuntimeError):
@@ -93,7 +94,9 @@ def lib() -> C.CDLL:
         L.gp_sim_fork.argtypes = [vp, vp, vp]
         L.gp_sim_step_jerk.argtypes = [vp, vp, vp]
         L.gp_sim_get_actuators.argtypes = [vp, vp, vp]
-        for name in ("gp_sim_check_infractions", "gp_sim_fork", "gp_sim_step_jerk", "gp_sim_get_actuators", "gp_batch_step_render", "gp_sim_create", "gp_sim_set_launch", "gp_sim_get_launch", "gp_sim_step",
+        L.gp_sim_set_light.argtypes = [vp, vp]
+        for name in ("gp_sim_check_infractions", "gp_sim_fork", "gp_sim_step_jerk", "gp_sim_get_actuators",
+                     "gp_sim_set_light", "gp_batch_step_render", "gp_sim_create", "gp_sim_set_launch", "gp_sim_get_launch", "gp_sim_step",
                      "gp_sim_render", "gp_sim_step_render_graph", "gp_sim_get_state",
                      "gp_sim_set_state"):
             getattr(L, name).restype = C.c_int
@@ -228,6 +231,15 @@ class Sim:
         (3 * longitudinal + lateral; larger indices coast)."""
         self._check_tensor(actions, (self.n_agents,), "uint8")
         _check(lib().gp_sim_step_jerk(self._h, actions.data_ptr(), _stream_handle(stream)))
+
+    def set_light(self, light=None):
+        """light = (lx, ly, lz, ambient): unit direction towards the light (world
+        frame) and ambient term; None turns shading off."""
+        if light is None:
+            _check(lib().gp_sim_set_light(self._h, None))
+            return
+        arr = (C.c_float * 4)(*[float(x) for x in light])
+        _check(lib().gp_sim_set_light(self._h, C.cast(arr, C.c_void_p)))
 
     def get_actuators(self, stream=None):
         """float32 [n_agents, 4]: longitudinal and lateral acceleration, steering angle, 0."""
