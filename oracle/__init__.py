@@ -36,7 +36,9 @@ class _Scene(C.Structure):
     _fields_ = [("n_agents", C.c_int), ("n_roads", C.c_int),
                 ("agent_state", C.c_void_p), ("agent_dims", C.c_void_p),
                 ("agent_color", C.c_void_p), ("road_xy", C.c_void_p),
-                ("road_color", C.c_void_p)]
+                ("road_color", C.c_void_p), ("n_static", C.c_int),
+                ("static_xyp", C.c_void_p), ("static_dims", C.c_void_p),
+                ("static_color", C.c_void_p)]
 
 
 class _Camera(C.Structure):
@@ -63,7 +65,7 @@ def lib():
         L.gpo_overlap.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.gpo_in_strip.argtypes = [C.c_void_p, C.c_float, C.c_float]
         L.gpo_infractions.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
-                                      C.c_void_p]
+                                      C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         L.gpo_render_view.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.c_int, C.c_float,
                                       C.c_float, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.POINTER(C.c_longlong)]
@@ -128,18 +130,35 @@ def in_strip(quad, px: float, py: float) -> bool:
     return bool(lib().gpo_in_strip(_ptr(q), C.c_float(px), C.c_float(py)))
 
 
-def infractions(scene_state, dims, road_xy, halted):
+def infractions(scene_state, dims, road_xy, halted, static_xyp=None, static_dims=None):
     """Collision / off-road check of one scene: returns (state with newly halted
     agents' speed zeroed, halted, flags) with flags bit 0 collision, bit 1
-    off-road, bit 2 halted; inputs untouched."""
+    off-road, bit 2 halted; inputs untouched.  static_xyp [k, 3] (x, y, psi)
+    and static_dims [k, 3] are the scene's static obstacles."""
     st = np.ascontiguousarray(scene_state, dtype=np.float32).copy()
     dm = np.ascontiguousarray(dims, dtype=np.float32)
     rx = np.ascontiguousarray(road_xy, dtype=np.float32).reshape(-1, 8)
     hl = np.ascontiguousarray(halted, dtype=np.uint8).copy()
     fl = np.zeros(st.shape[0], dtype=np.uint8)
+    sx = np.zeros((0, 3), np.float32) if static_xyp is None else np.ascontiguousarray(static_xyp, np.float32)
+    sd = np.zeros((0, 3), np.float32) if static_dims is None else np.ascontiguousarray(static_dims, np.float32)
+    assert sx.shape == sd.shape
     lib().gpo_infractions(st.shape[0], _ptr(st), _ptr(dm), rx.shape[0], _ptr(rx) if rx.size else None,
-                          _ptr(hl), _ptr(fl))
+                          _ptr(hl), _ptr(fl), sx.shape[0], _ptr(sx) if sx.size else None,
+                          _ptr(sd) if sd.size else None)
     return st, hl, fl
+
+
+def scene_infractions(scene, state, halted):
+    """infractions() of a scenegen.Scene-like object with the given agent state."""
+    return infractions(state, scene.agent_dims, scene.road_xy, halted, *_statics(scene)[:2])
+
+
+def _statics(scene):
+    sx = getattr(scene, "static_xyp", None)
+    if sx is None or len(sx) == 0:
+        return None, None, None
+    return scene.static_xyp, scene.static_dims, scene.static_color
 
 
 def cover_tri(X, Y, W: int, H: int, count=None) -> np.ndarray:
@@ -161,10 +180,11 @@ class View:
 
 
 def render_view(state, dims, agent_color, road_xy, road_color, camera, palette,
-                ego: int, cam_dir=(1.0, 0.0), light=None) -> View:
+                ego: int, cam_dir=(1.0, 0.0), light=None, statics=None) -> View:
     """Render one ego view.  `camera` has width, height, focal_px, cam_height, z_near, z_far.
     `light` = (lx, ly, lz, ambient) turns on directional shading (unit direction
-    towards the light, world frame)."""
+    towards the light, world frame).  `statics` = (xyp [k, 3], dims [k, 3],
+    colour [k]) are static obstacles."""
     st = np.ascontiguousarray(state, dtype=np.float32)
     dm = np.ascontiguousarray(dims, dtype=np.float32)
     ac = np.ascontiguousarray(agent_color, dtype=np.uint8)
@@ -172,6 +192,12 @@ def render_view(state, dims, agent_color, road_xy, road_color, camera, palette,
     rc = np.ascontiguousarray(road_color, dtype=np.uint8)
     pal = np.ascontiguousarray(palette, dtype=np.uint8).reshape(256, 3)
     sc = _Scene(st.shape[0], rx.shape[0], _ptr(st), _ptr(dm), _ptr(ac), _ptr(rx), _ptr(rc))
+    if statics is not None and statics[0] is not None and len(statics[0]):
+        sx = np.ascontiguousarray(statics[0], np.float32)
+        sd = np.ascontiguousarray(statics[1], np.float32)
+        scol = np.ascontiguousarray(statics[2], np.uint8)
+        assert sx.shape == sd.shape == (scol.shape[0], 3)
+        sc.n_static, sc.static_xyp, sc.static_dims, sc.static_color = sx.shape[0], _ptr(sx), _ptr(sd), _ptr(scol)
     W, H = int(camera.width), int(camera.height)
     cm = _Camera(W, H, camera.focal_px, camera.cam_height, camera.z_near, camera.z_far, _ptr(pal))
     if light is not None:
@@ -192,7 +218,7 @@ def render_view(state, dims, agent_color, road_xy, road_color, camera, palette,
 def render_scene_view(scene, camera, palette, ego: int, cam: int = 0, light=None) -> View:
     """Render view (ego, cam) of a scenegen.Scene-like object."""
     return render_view(scene.agent_state, scene.agent_dims, scene.agent_color, scene.road_xy,
-                       scene.road_color, camera, palette, ego, camera.cam_dirs[cam], light)
+                       scene.road_color, camera, palette, ego, camera.cam_dirs[cam], light, _statics(scene))
 
 
 def render_views(items, camera, palette, threads: int = 1):

@@ -249,6 +249,10 @@ typedef struct {
     const uint8_t *agent_color;   /* [n_agents] */
     const float *road_xy;         /* [n_roads][4][2] */
     const uint8_t *road_color;    /* [n_roads] */
+    int n_static;                 /* static obstacles: cuboids that never move */
+    const float *static_xyp;      /* [n_static][3] x, y, psi */
+    const float *static_dims;     /* [n_static][3] L, W, H */
+    const uint8_t *static_color;  /* [n_static] */
 } gpo_scene;
 
 typedef struct {
@@ -535,7 +539,8 @@ static uint32_t shade_level(const gpo_camera *cam, float nx, float ny, int face)
 /* Render the view of agent `ego` through the camera whose yaw offset is
  * (ck, sk) = (cos, sin).  Outputs (any may be NULL): rgb [H][W][3], depth
  * [H][W] (1/invz, +inf for background), primid [H][W] (-1 for background).
- * Primitive index: 6*agent + face for boxes, 6*n_agents + road for roads.
+ * Primitive index: 6*b + face for box b (the agents 0..n_agents-1, then the
+ * static obstacles), 6*(n_agents + n_static) + road for roads.
  * Faces: 0 front, 1 left, 2 back, 3 right, 4 top, 5 bottom.
  * `key_scratch` must hold H*W uint64.  Returns the number of rasterised
  * triangles; *frags_out (optional) receives the fragment count. */
@@ -551,11 +556,15 @@ long long gpo_render_view(const gpo_scene *sc, const gpo_camera *cam, int ego, f
     long long ntri = 0;
     const uint32_t n_a = (uint32_t)sc->n_agents;
 
-    /* agent cuboids, the ego's own box excluded (one world per ego agent) */
-    for (int j = 0; j < sc->n_agents; ++j) {
-        if (j == ego) continue;
-        const float *st = sc->agent_state + 4 * j;
-        const float *dm = sc->agent_dims + 3 * j;
+    /* cuboids: the agents, the ego's own box excluded (one world per ego
+     * agent), then the static obstacles (Sec. 3.1: static objects are
+     * cuboids too); box b has primitives 6 b + face */
+    const uint32_t n_box = n_a + (uint32_t)sc->n_static;
+    for (uint32_t b = 0; b < n_box; ++b) {
+        if ((int)b == ego) continue;
+        const int is_static = b >= n_a;
+        const float *st = is_static ? sc->static_xyp + 3 * (b - n_a) : sc->agent_state + 4 * b;
+        const float *dm = is_static ? sc->static_dims + 3 * (b - n_a) : sc->agent_dims + 3 * b;
         float sj, cj;
         gpo_sincos(st[2], &sj, &cj);
         float ox = st[0] - vw.px, oy = st[1] - vw.py;
@@ -578,8 +587,8 @@ long long gpo_render_view(const gpo_scene *sc, const gpo_camera *cam, int ego, f
         for (int f = 0; f < 6; ++f) {
             v3 poly[MAXV];
             if (f < 4) {            /* side face over footprint edge f -> f+1 */
-                int a = f, b = (f + 1) & 3;
-                poly[0] = bot[a]; poly[1] = bot[b]; poly[2] = top[b]; poly[3] = top[a];
+                int a = f, c = (f + 1) & 3;
+                poly[0] = bot[a]; poly[1] = bot[c]; poly[2] = top[c]; poly[3] = top[a];
             } else if (f == 4) {
                 poly[0] = top[0]; poly[1] = top[1]; poly[2] = top[2]; poly[3] = top[3];
             } else {
@@ -587,7 +596,7 @@ long long gpo_render_view(const gpo_scene *sc, const gpo_camera *cam, int ego, f
             }
             v3 nc = dir_to_cam(&vw, nwx[f], nwy[f], nwz[f]);
             v3 p0 = poly[0];
-            ntri += raster_polygon(&t, poly, 4, nc, p0, 1, 1u, (uint32_t)(6 * j + f));
+            ntri += raster_polygon(&t, poly, 4, nc, p0, 1, 1u, (uint32_t)(6 * b + f));
         }
     }
     /* road quads at z = 0, two-sided */
@@ -598,7 +607,7 @@ long long gpo_render_view(const gpo_scene *sc, const gpo_camera *cam, int ego, f
             poly[k] = to_cam(&vw, q[2 * k] - vw.px, q[2 * k + 1] - vw.py, 0.0f);
         v3 nc = dir_to_cam(&vw, 0.0f, 0.0f, 1.0f);
         v3 p0 = poly[0];
-        ntri += raster_polygon(&t, poly, 4, nc, p0, 0, 0u, (uint32_t)(6 * n_a + r));
+        ntri += raster_polygon(&t, poly, 4, nc, p0, 0, 0u, (uint32_t)(6 * n_box + r));
     }
 
     /* resolve */
@@ -612,16 +621,21 @@ long long gpo_render_view(const gpo_scene *sc, const gpo_camera *cam, int ego, f
             float invz;
             memcpy(&invz, &zb, 4);
             prim = (int32_t)(0x7FFFFFFFu - (uint32_t)(key & 0x7FFFFFFFu));
-            color = (prim < (int32_t)(6 * n_a)) ? sc->agent_color[prim / 6]
-                                                : sc->road_color[prim - 6 * (int32_t)n_a];
+            const int32_t b = prim / 6;
+            color = prim >= (int32_t)(6 * n_box) ? sc->road_color[prim - 6 * (int32_t)n_box]
+                    : b < (int32_t)n_a            ? sc->agent_color[b]
+                                                  : sc->static_color[b - (int32_t)n_a];
             dep = 1.0f / invz;
         }
         if (rgb) {
             uint32_t q = 255;
             if (cam->shade && prim >= 0) {
-                if (prim < (int32_t)(6 * n_a)) {
+                if (prim < (int32_t)(6 * n_box)) {
+                    const int32_t b = prim / 6;
+                    const float psi = b < (int32_t)n_a ? sc->agent_state[4 * b + 2]
+                                                       : sc->static_xyp[3 * (b - (int32_t)n_a) + 2];
                     float sj, cj;
-                    gpo_sincos(sc->agent_state[4 * (prim / 6) + 2], &sj, &cj);
+                    gpo_sincos(psi, &sj, &cj);
                     const int f = prim % 6;
                     const float nx[4] = { cj, -sj, -cj, sj }, ny[4] = { sj, cj, -sj, -cj };
                     q = shade_level(cam, f < 4 ? nx[f] : 0.0f, f < 4 ? ny[f] : 0.0f, f);
@@ -650,6 +664,8 @@ long long gpo_render_view(const gpo_scene *sc, const gpo_camera *cam, int ego, f
  *   - collision: the two footprints (length x width rectangles about the box
  *     centre, along the heading) overlap with positive area.  Tested with the
  *     separating axes of both rectangles; boxes that only touch do not collide.
+ *     The other box is another agent of the scene or one of its static
+ *     obstacles (static_xyp [n_static][3] = x, y, psi; static_dims [n][3]).
  *   - off-road: the agent's centre lies in no road strip of its scene (a strip
  *     contains the point when the point is on the inner side of, or on, each
  *     of its four edges, in either winding).
@@ -700,12 +716,16 @@ int gpo_in_strip(const float *q, float px, float py)
 }
 
 void gpo_infractions(int n, float *state, const float *dims, int n_roads, const float *roads,
-                     uint8_t *halted, uint8_t *flags)
+                     uint8_t *halted, uint8_t *flags, int n_static, const float *static_xyp,
+                     const float *static_dims)
 {
     for (int i = 0; i < n; ++i) {
         int col = 0;
         for (int j = 0; j < n && !col; ++j)
             if (j != i) col = gpo_overlap(state + 4 * i, dims + 3 * i, state + 4 * j, dims + 3 * j);
+        /* static obstacles are vehicles' obstacles too */
+        for (int k = 0; k < n_static && !col; ++k)
+            col = gpo_overlap(state + 4 * i, dims + 3 * i, static_xyp + 3 * k, static_dims + 3 * k);
         int on = 0;
         for (int r = 0; r < n_roads && !on; ++r) on = gpo_in_strip(roads + 8 * r, state[4 * i], state[4 * i + 1]);
         flags[i] = (uint8_t)(col | (on ? 0 : 2));

@@ -63,6 +63,10 @@ class Scene:
     agent_color: np.ndarray  # [n_agents] uint8 palette index
     road_xy: np.ndarray      # [n_roads, 4, 2] corners at z = 0, counter-clockwise seen from +z
     road_color: np.ndarray   # [n_roads] uint8 palette index
+    # static obstacles (cuboids that never move): [k, 3] x, y, psi; [k, 3] L, W, H; [k] colour
+    static_xyp: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 3), np.float32))
+    static_dims: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 3), np.float32))
+    static_color: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(0, np.uint8))
 
     @property
     def n_agents(self) -> int:
@@ -71,6 +75,10 @@ class Scene:
     @property
     def n_roads(self) -> int:
         return int(self.road_xy.shape[0])
+
+    @property
+    def n_static(self) -> int:
+        return int(self.static_xyp.shape[0])
 
 
 @dataclasses.dataclass
@@ -185,12 +193,45 @@ def place_agents(seed: int, scene: int, road_xy: np.ndarray, n_agents: int) -> t
     return state, dims
 
 
-def make_scene(seed: int, scene: int, n_agents: int, n_quads: int) -> Scene:
+S_STATIC = 7
+
+
+def place_statics(seed: int, scene: int, road_xy: np.ndarray, n_static: int) -> tuple:
+    """Static obstacles on lane edges (a road's edge or the line between its two
+    lanes): parked vehicles and barriers 1.75..2.25 m to either side of a lane
+    segment's centreline, along the lane +-U(0, 10 deg); L ~ U(1, 6),
+    W ~ U(0.5, 2.2), H ~ U(0.8, 2.0) m."""
+    a = np.arange(n_static)
+    u = lambda c: keyed_uniform(seed, S_STATIC, scene, a, c)
+    nq = road_xy.shape[0]
+    qi = np.minimum((u(0) * nq).astype(np.int64), nq - 1)
+    quad = road_xy[qi].astype(np.float64)
+    back = 0.5 * (quad[:, 0] + quad[:, 3])
+    front = 0.5 * (quad[:, 1] + quad[:, 2])
+    pos = back + u(1)[:, None] * (front - back)
+    d = front - back
+    heading = np.arctan2(d[:, 1], d[:, 0])
+    side = np.where(u(2) < 0.5, -1.0, 1.0)
+    nrm = np.stack([-np.sin(heading), np.cos(heading)], axis=1)
+    pos = pos + (side * (1.75 + 0.5 * u(3)))[:, None] * nrm       # at the lane's edge
+    psi = heading + np.deg2rad(10.0) * (2.0 * u(4) - 1.0)
+    psi = np.where(psi > math.pi, psi - 2 * math.pi, psi)
+    psi = np.where(psi <= -math.pi, psi + 2 * math.pi, psi)
+    dims = np.stack([1.0 + 5.0 * u(5), 0.5 + 1.7 * u(6), 0.8 + 1.2 * u(7)], axis=1)
+    xyp = np.stack([pos[:, 0], pos[:, 1], psi], axis=1).astype(np.float32)
+    return xyp, dims.astype(np.float32)
+
+
+def make_scene(seed: int, scene: int, n_agents: int, n_quads: int, n_static: int = 0) -> Scene:
     roads = road_network(seed, scene, n_quads)
     state, dims = place_agents(seed, scene, roads, n_agents)
-    return Scene(agent_state=state, agent_dims=dims,
-                 agent_color=np.full(n_agents, COLOR_VEHICLE, dtype=np.uint8),
-                 road_xy=roads, road_color=np.full(n_quads, COLOR_ROAD, dtype=np.uint8))
+    sc = Scene(agent_state=state, agent_dims=dims,
+               agent_color=np.full(n_agents, COLOR_VEHICLE, dtype=np.uint8),
+               road_xy=roads, road_color=np.full(n_quads, COLOR_ROAD, dtype=np.uint8))
+    if n_static:
+        sc.static_xyp, sc.static_dims = place_statics(seed, scene, roads, n_static)
+        sc.static_color = np.full(n_static, COLOR_VEHICLE, dtype=np.uint8)   # agents and obstacles blue
+    return sc
 
 
 S_CROWD = 5
