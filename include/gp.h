@@ -82,6 +82,16 @@ typedef struct {
     const uint8_t *agent_color;       /* [n_agents] palette index                          */
     const float *road_xy;             /* [n_roads][4][2] corners (m) at z = 0, any winding */
     const uint8_t *road_color;        /* [n_roads] palette index                           */
+    /* Static obstacles (Sec. 3.1: static objects are cuboids like the
+     * vehicles): boxes that never move and own no view.  They are rendered,
+     * and an agent overlapping one collides (gp_sim_check_infractions).
+     * Their primitive indices follow the agents': box b = n_agents + k has
+     * primitives 6 b + face, and road r becomes 6 (n_agents + n_static) + r.
+     * All NULL / 0 for none. */
+    int32_t n_static;                 /* >= 0                                              */
+    const float *static_xyp;          /* [n_static][3] x, y (m), psi (rad)                 */
+    const float *static_dims;         /* [n_static][3] length, width, height (m)           */
+    const uint8_t *static_color;      /* [n_static] palette index                          */
 } gp_scene_desc;
 
 /* Launch settings of the renderer.  Every setting gives bit-identical images;

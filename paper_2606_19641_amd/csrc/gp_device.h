@@ -19,8 +19,17 @@ struct SceneRec {
     int32_t road_base, n_roads;     // road slots [road_base, road_base + n_roads)
     int32_t view_base;              // first view of the scene
     int32_t bin_base, n_bins;       // culling bins [bin_base, bin_base + n_bins)
-    int32_t pad;
+    int32_t static_base, n_static;  // static obstacles: box slots [static_base, static_base + n_static)
+    int32_t pad[2];
 };
+
+// Box b of a scene (the agents, then the static obstacles) -> its slot in the
+// box arrays (state, cs, dims, agent_color): every agent first, then every
+// static obstacle.
+__host__ __device__ inline int box_slot(const SceneRec &sc, int b)
+{
+    return b < sc.n_agents ? sc.agent_base + b : sc.static_base + (b - sc.n_agents);
+}
 
 // One view: scene index and (ego agent local index, camera index).
 struct ViewRec {
@@ -39,10 +48,10 @@ struct RoadBin {
 struct DevSim {
     const SceneRec *scenes;
     const ViewRec *views;
-    float4 *state;            // [A] x, y, psi, v
-    float2 *cs;               // [A] cos psi, sin psi
-    const float4 *dims;       // [A] L, W, H, 0
-    const uint8_t *agent_color;
+    float4 *state;            // [A + S] x, y, psi, v: the A agents, then the S static obstacles (v = 0)
+    float2 *cs;               // [A + S] cos psi, sin psi
+    const float4 *dims;       // [A + S] L, W, H, 0
+    const uint8_t *agent_color;   // [A + S]
     const float4 *roads;      // [R][2] corners of road slot r: (x0 y0 x1 y1) (x2 y2 x3 y3)
     const int32_t *road_index;// [R] index of road slot r in its scene's input order
     const uint8_t *road_color;// [R] colour of road slot r
@@ -53,6 +62,7 @@ struct DevSim {
                               // segment mask (all zero between launches)
     int32_t qseg[kQueues + 1];// segment q of the queue is [qseg[q], qseg[q + 1])
     int32_t n_scenes, n_agents, n_views;
+    int32_t n_boxes;          // A + S
     int32_t width, height, n_cams;
     int32_t road_color_uniform;   // 1 if every road strip has the colour road_color0
     int32_t road_color0;

@@ -183,8 +183,8 @@ __global__ void k_step_jerk(DevSim s, const uint8_t *__restrict__ act)
 __global__ void k_cs(DevSim s, int clear_halted)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= s.n_agents) return;
-    if (clear_halted) {
+    if (i >= s.n_boxes) return;                 // agents and static obstacles
+    if (clear_halted && i < s.n_agents) {
         s.halted[i] = 0;
         s.actu[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
@@ -272,6 +272,15 @@ __global__ __launch_bounds__(256) void k_infr_flags(DevSim s)
         if (j0 + lane < sc.n_agents && gj != i) {
             const float4 dj = s.dims[gj];
             hit = footprints_overlap(si, ci, hli, hwi, s.state[gj], s.cs[gj], 0.5f * dj.x, 0.5f * dj.y);
+        }
+        col = __ballot(hit) != 0ull;
+    }
+    for (int k0 = 0; k0 < sc.n_static && !col; k0 += 64) {      // static obstacles
+        bool hit = false;
+        if (k0 + lane < sc.n_static) {
+            const int gk = sc.static_base + k0 + lane;
+            const float4 dk = s.dims[gk];
+            hit = footprints_overlap(si, ci, hli, hwi, s.state[gk], s.cs[gk], 0.5f * dk.x, 0.5f * dk.y);
         }
         col = __ballot(hit) != 0ull;
     }
@@ -440,11 +449,12 @@ __device__ __forceinline__ uint32_t key_low(uint32_t cls, int prim, uint32_t col
     return (cls << 31) | ((uint32_t)(kMaxPrims - 1 - prim) << 8) | color;
 }
 
-// face f (0 front, 1 left, 2 back, 3 right, 4 top, 5 bottom) of agent j
+// face f (0 front, 1 left, 2 back, 3 right, 4 top, 5 bottom) of box j (an
+// agent, or a static obstacle for j >= n_agents)
 __device__ __forceinline__ void build_face(const DevSim &s, const SceneRec &sc, const Cam &cam, int j,
                                            int f, Poly &P)
 {
-    const int ga = sc.agent_base + j;
+    const int ga = box_slot(sc, j);
     const float4 st = s.state[ga];
     const float2 csj = s.cs[ga];
     const float4 dm = s.dims[ga];
@@ -494,7 +504,7 @@ __device__ __forceinline__ void build_road(const DevSim &s, const SceneRec &sc, 
     P.v[2] = to_cam(cam, q1.x - cam.px, q1.y - cam.py, 0.0f);
     P.v[3] = to_cam(cam, q1.z - cam.px, q1.w - cam.py, 0.0f);
     P.n = dir_to_cam(cam, 0.0f, 0.0f, 1.0f);
-    P.keylo = key_low(0u, 6 * sc.n_agents + s.road_index[g], s.road_color[g]);
+    P.keylo = key_low(0u, 6 * (sc.n_agents + sc.n_static) + s.road_index[g], s.road_color[g]);
     P.one_sided = false;
 }
 
@@ -525,7 +535,7 @@ __device__ __forceinline__ bool outside(const Cam &c, const V3 *v)
 // diagonal, height H) with the same margins as outside().
 __device__ __forceinline__ bool box_outside(const DevSim &s, const SceneRec &sc, const Cam &c, int j)
 {
-    const int ga = sc.agent_base + j;
+    const int ga = box_slot(sc, j);
     const float4 st = s.state[ga];
     const float4 dm = s.dims[ga];
     const float ox = st.x - c.px, oy = st.y - c.py;
@@ -1216,7 +1226,7 @@ __device__ void setup_source(const DevSim &s, const SceneRec &sc, const Cam &cam
     constexpr int kind = KIND;
     constexpr bool road = FAST && KIND == 1;     // triangles of this pass go to the road list
     const int B = blockDim.x, tid = threadIdx.x;
-    const int n_units = kind == 0 ? sc.n_agents : sc.n_bins;
+    const int n_units = kind == 0 ? sc.n_agents + sc.n_static : sc.n_bins;
     const bool can_flush = road || K.flush_tris;
     // the list that may be flushed during this pass, and its capacity; with
     // flushing a round adds at most 2 triangles per lane, so keep it below half
@@ -1403,13 +1413,13 @@ __device__ __forceinline__ uint32_t shade_rgb(uint32_t c, uint32_t q)
     return r | (g << 8) | (b << 16);
 }
 
-// lit colour c of the box face that a winning key names (agent and face from
-// the key's primitive index, the scene's agents from agent_base)
-__device__ __forceinline__ uint32_t lit_box(const DevSim &s, int agent_base, uint32_t c, unsigned long long key)
+// lit colour c of the box face that a winning key names (box and face from
+// the key's primitive index)
+__device__ __forceinline__ uint32_t lit_box(const DevSim &s, const SceneRec &sc, uint32_t c, unsigned long long key)
 {
     const int prim = (kMaxPrims - 1) - (int)(((uint32_t)key >> 8) & (uint32_t)(kMaxPrims - 1));
     const int j = prim / 6, f = prim - 6 * j;
-    const float2 cs = s.cs[agent_base + j];
+    const float2 cs = s.cs[box_slot(sc, j)];
     const float nx = f == 0 ? cs.x : f == 1 ? -cs.y : f == 2 ? -cs.x : cs.y;
     const float ny = f == 0 ? cs.y : f == 1 ? cs.x : f == 2 ? -cs.y : -cs.x;
     return shade_rgb(c, shade_level(s, nx, ny, f));
@@ -1557,10 +1567,10 @@ __device__ void resolve_general(const DevSim &s, const SceneRec &sc, const Cam &
         const unsigned long long key = L.zb[p];
         uint32_t c = L.pal[key ? ((uint32_t)key & 0xFFu) : 0u];
         if (s.shade && key) {
-            // boxes hold the primitives below 6 n_agents
+            // boxes hold the primitives below 6 (n_agents + n_static)
             const bool box = (((uint32_t)key >> 8) & (uint32_t)(kMaxPrims - 1)) >
-                             (uint32_t)(kMaxPrims - 1 - 6 * sc.n_agents);
-            c = box ? lit_box(s, sc.agent_base, c, key) : shade_rgb(c, q_road);
+                             (uint32_t)(kMaxPrims - 1 - 6 * (sc.n_agents + sc.n_static));
+            c = box ? lit_box(s, sc, c, key) : shade_rgb(c, q_road);
         }
         uint8_t *dst = o.rgb + 3 * (pix0 + p);
         dst[0] = (uint8_t)c;
@@ -1577,6 +1587,22 @@ __device__ void resolve_general(const DevSim &s, const SceneRec &sc, const Cam &
 
 // ------------------------------------------------------------ per view
 
+__device__ __forceinline__ SceneRec uniform_scene(const SceneRec &r)
+{
+    SceneRec u;
+    u.agent_base = __builtin_amdgcn_readfirstlane(r.agent_base);
+    u.n_agents = __builtin_amdgcn_readfirstlane(r.n_agents);
+    u.road_base = __builtin_amdgcn_readfirstlane(r.road_base);
+    u.n_roads = __builtin_amdgcn_readfirstlane(r.n_roads);
+    u.view_base = __builtin_amdgcn_readfirstlane(r.view_base);
+    u.bin_base = __builtin_amdgcn_readfirstlane(r.bin_base);
+    u.n_bins = __builtin_amdgcn_readfirstlane(r.n_bins);
+    u.static_base = __builtin_amdgcn_readfirstlane(r.static_base);
+    u.n_static = __builtin_amdgcn_readfirstlane(r.n_static);
+    u.pad[0] = u.pad[1] = 0;
+    return u;
+}
+
 __device__ __forceinline__ void reset_counts(Lds &L)
 {
     const int t = threadIdx.x;
@@ -1586,9 +1612,11 @@ __device__ __forceinline__ void reset_counts(Lds &L)
 template <int FAST>
 __device__ void render_view(const DevSim &s, const RenderOut &o, const LaunchCfg &lc, Lds &L, int view)
 {
-    const ViewRec vr = s.views[view];
-    const SceneRec sc = s.scenes[vr.scene];
-    const int ego = vr.ego_cam >> 2, k = vr.ego_cam & 3;
+    // the view's records are the same for the whole workgroup: scalar registers
+    const int scene = __builtin_amdgcn_readfirstlane(s.views[view].scene);
+    const int ego_cam = __builtin_amdgcn_readfirstlane(s.views[view].ego_cam);
+    const SceneRec sc = uniform_scene(s.scenes[scene]);
+    const int ego = ego_cam >> 2, k = ego_cam & 3;
     const Cam cam = make_cam(s, sc, ego, k);
     const int H = cam.H, W = cam.W, BR = lc.band_rows;
     reset_counts(L);
@@ -1874,7 +1902,7 @@ hipError_t launch_render_multi(const SimEntry *tab, const int2 *items, int n_ite
 hipError_t launch_cs(const DevSim &s, int clear_halted, hipStream_t st)
 {
     const int B = 256;
-    hipLaunchKernelGGL(k_cs, dim3((s.n_agents + B - 1) / B), dim3(B), 0, st, s, clear_halted);
+    hipLaunchKernelGGL(k_cs, dim3((s.n_boxes + B - 1) / B), dim3(B), 0, st, s, clear_halted);
     return hipGetLastError();
 }
 

@@ -51,7 +51,7 @@ struct Layout {
     int64_t scenes, views, state, cs, dims, agent_color, roads, road_index, road_color, bins, palette,
         queue, counter;
     int64_t total;
-    int64_t n_agents, n_roads, n_views, n_bins;
+    int64_t n_agents, n_roads, n_views, n_bins, n_static;
 };
 
 bool finite_cfg(const gp_config *c)
@@ -81,8 +81,14 @@ gp_status check_inputs(const gp_config *cfg, const gp_scene_desc *sc, int32_t n)
         const gp_scene_desc &d = sc[s];
         if (d.n_agents < 1 || d.n_roads < 0)
             return fail(GP_EINVAL, "scene %d: n_agents must be >= 1 and n_roads >= 0", s);
-        if (6LL * d.n_agents + d.n_roads >= gp::kMaxPrims)
+        if (d.n_static < 0) return fail(GP_EINVAL, "scene %d: n_static must be >= 0", s);
+        if (6LL * ((int64_t)d.n_agents + d.n_static) + d.n_roads >= gp::kMaxPrims)
             return fail(GP_EINVAL, "scene %d: more than %d primitives", s, gp::kMaxPrims);
+        if (d.n_static > 0 && (!d.static_xyp || !d.static_dims || !d.static_color))
+            return fail(GP_EINVAL, "scene %d: static obstacle arrays are NULL", s);
+        for (int64_t i = 0; i < 3LL * d.n_static; ++i)
+            if (!std::isfinite(d.static_xyp[i]) || !std::isfinite(d.static_dims[i]))
+                return fail(GP_EINVAL, "scene %d: static obstacle not finite", s);
         if (!d.agent_state || !d.agent_dims || !d.agent_color)
             return fail(GP_EINVAL, "scene %d: agent arrays are NULL", s);
         if (d.n_roads > 0 && (!d.road_xy || !d.road_color))
@@ -92,7 +98,10 @@ gp_status check_inputs(const gp_config *cfg, const gp_scene_desc *sc, int32_t n)
         na += d.n_agents;
         nr += d.n_roads;
     }
+    int64_t ns = 0;
+    for (int s = 0; s < n; ++s) ns += sc[s].n_static;
     if (na * cfg->n_cams >= (1LL << 31)) return fail(GP_EINVAL, "too many views");
+    if (na + ns >= (1LL << 31)) return fail(GP_EINVAL, "too many boxes");
     if (nr >= (1LL << 31)) return fail(GP_EINVAL, "too many roads");
     return GP_OK;
 }
@@ -102,6 +111,7 @@ Layout make_layout(const gp_config *cfg, const gp_scene_desc *sc, int32_t n)
     Layout L{};
     for (int s = 0; s < n; ++s) {
         L.n_agents += sc[s].n_agents;
+        L.n_static += sc[s].n_static;
         L.n_roads += sc[s].n_roads;
         L.n_bins += n_bins_of(sc[s].n_roads);
     }
@@ -110,10 +120,12 @@ Layout make_layout(const gp_config *cfg, const gp_scene_desc *sc, int32_t n)
     auto take = [&](int64_t bytes) { int64_t at = o; o = align_up(o + std::max<int64_t>(bytes, 1)); return at; };
     L.scenes = take(sizeof(gp::SceneRec) * (int64_t)n);
     L.views = take(sizeof(gp::ViewRec) * L.n_views);
-    L.state = take(16 * L.n_agents);
-    L.cs = take(8 * L.n_agents);
-    L.dims = take(16 * L.n_agents);
-    L.agent_color = take(L.n_agents);
+    // box arrays: the agents, then the static obstacles
+    const int64_t n_box = L.n_agents + L.n_static;
+    L.state = take(16 * n_box);
+    L.cs = take(8 * n_box);
+    L.dims = take(16 * n_box);
+    L.agent_color = take(n_box);
     L.roads = take(32 * L.n_roads);
     L.road_index = take(4 * L.n_roads);
     L.road_color = take(L.n_roads);
@@ -367,7 +379,7 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
     auto *ridx = reinterpret_cast<int32_t *>(at(L.road_index));
     auto *rcol = at(L.road_color);
     auto *bins = reinterpret_cast<gp::RoadBin *>(at(L.bins));
-    int32_t abase = 0, rbase = 0, bbase = 0;
+    int32_t abase = 0, rbase = 0, bbase = 0, sbase = (int32_t)L.n_agents;
     bool uniform = true;
     int color0 = -1;
     for (int s = 0; s < n_scenes; ++s) {
@@ -382,7 +394,18 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
         r.view_base = abase * cfg->n_cams;
         r.bin_base = bbase;
         r.n_bins = (int32_t)sb.size();
-        r.pad = 0;
+        r.static_base = sbase;
+        r.n_static = d.n_static;
+        r.pad[0] = r.pad[1] = 0;
+        for (int k = 0; k < d.n_static; ++k) {     // static obstacles: v = 0, never stepped
+            const int g = sbase + k;
+            for (int c = 0; c < 3; ++c) state[4 * g + c] = d.static_xyp[3 * k + c];
+            state[4 * g + 3] = 0.0f;
+            for (int c = 0; c < 3; ++c) dims[4 * g + c] = d.static_dims[3 * k + c];
+            dims[4 * g + 3] = 0.0f;
+            acol[g] = d.static_color[k];
+        }
+        sbase += d.n_static;
         for (int a = 0; a < d.n_agents; ++a) {
             const int g = r.agent_base + a;
             for (int k = 0; k < 4; ++k) state[4 * g + k] = d.agent_state[4 * a + k];
@@ -417,7 +440,7 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
     // and the views of a scene are adjacent.
     std::vector<int> order(n_scenes);
     std::iota(order.begin(), order.end(), 0);
-    auto view_work = [&](int s) { return 6LL * scenes[s].n_agents + scenes[s].n_roads + 64; };
+    auto view_work = [&](int s) { return 6LL * (scenes[s].n_agents + scenes[s].n_static) + scenes[s].n_roads + 64; };
     auto scene_work = [&](int s) { return view_work(s) * (int64_t)scenes[s].n_agents * cfg->n_cams; };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return scene_work(a) > scene_work(b); });
     std::vector<std::vector<int>> seg(gp::kQueues);
@@ -464,6 +487,7 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
     D.counter = reinterpret_cast<uint32_t *>(base + L.counter);
     D.n_scenes = n_scenes;
     D.n_agents = (int32_t)L.n_agents;
+    D.n_boxes = (int32_t)(L.n_agents + L.n_static);
     D.n_views = (int32_t)L.n_views;
     D.width = cfg->width;
     D.height = cfg->height;
@@ -760,7 +784,8 @@ gp_status gp_sim_fork(gp_sim *dst, const gp_sim *src, void *stream)
     if (dst == src) return GP_OK;
     if (dst->n_scenes != src->n_scenes) return fail(GP_EINVAL, "fork needs sims over the same scenes");
     for (int k = 0; k < src->n_scenes; ++k)
-        if (dst->scenes[k].n_agents != src->scenes[k].n_agents || dst->scenes[k].n_roads != src->scenes[k].n_roads)
+        if (dst->scenes[k].n_agents != src->scenes[k].n_agents || dst->scenes[k].n_roads != src->scenes[k].n_roads ||
+            dst->scenes[k].n_static != src->scenes[k].n_static)
             return fail(GP_EINVAL, "fork needs sims over the same scenes (scene %d differs)", k);
     hipStream_t hs = static_cast<hipStream_t>(stream);
     const size_t n = (size_t)src->lay.n_agents;

@@ -43,7 +43,9 @@ class Config(C.Structure):
 class SceneDesc(C.Structure):
     _fields_ = [("n_agents", C.c_int32), ("n_roads", C.c_int32),
                 ("agent_state", C.c_void_p), ("agent_dims", C.c_void_p),
-                ("agent_color", C.c_void_p), ("road_xy", C.c_void_p), ("road_color", C.c_void_p)]
+                ("agent_color", C.c_void_p), ("road_xy", C.c_void_p), ("road_color", C.c_void_p),
+                ("n_static", C.c_int32), ("static_xyp", C.c_void_p), ("static_dims", C.c_void_p),
+                ("static_color", C.c_void_p)]
 
 
 class Launch(C.Structure):
@@ -147,6 +149,17 @@ def _scene_descs(scenes: Sequence):
         descs[i] = SceneDesc(st.shape[0], rx.shape[0] if rx.size else 0, st.ctypes.data,
                              dm.ctypes.data, ac.ctypes.data, rx.ctypes.data if rx.size else None,
                              rc.ctypes.data if rc.size else None)
+        sx = getattr(s, "static_xyp", None)
+        if sx is not None and len(sx):
+            sx = np.ascontiguousarray(sx, dtype=np.float32)
+            sd = np.ascontiguousarray(s.static_dims, dtype=np.float32)
+            sc = np.ascontiguousarray(s.static_color, dtype=np.uint8)
+            if sx.shape != (sc.shape[0], 3) or sd.shape != sx.shape:
+                raise ValueError("static obstacles need xyp [k, 3], dims [k, 3], colour [k]")
+            keep += [sx, sd, sc]
+            descs[i].n_static = sx.shape[0]
+            descs[i].static_xyp, descs[i].static_dims, descs[i].static_color = (
+                sx.ctypes.data, sd.ctypes.data, sc.ctypes.data)
     return descs, keep
 
 
