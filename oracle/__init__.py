@@ -38,7 +38,8 @@ class _Scene(C.Structure):
                 ("agent_color", C.c_void_p), ("road_xy", C.c_void_p),
                 ("road_color", C.c_void_p), ("n_static", C.c_int),
                 ("static_xyp", C.c_void_p), ("static_dims", C.c_void_p),
-                ("static_color", C.c_void_p)]
+                ("static_color", C.c_void_p), ("n_signals", C.c_int),
+                ("signal_xyzr", C.c_void_p), ("signal_color", C.c_void_p)]
 
 
 class _Camera(C.Structure):
@@ -154,6 +155,13 @@ def scene_infractions(scene, state, halted):
     return infractions(state, scene.agent_dims, scene.road_xy, halted, *_statics(scene)[:2])
 
 
+def _signals(scene):
+    gx = getattr(scene, "signal_xyzr", None)
+    if gx is None or len(gx) == 0:
+        return None
+    return scene.signal_xyzr, scene.signal_color
+
+
 def _statics(scene):
     sx = getattr(scene, "static_xyp", None)
     if sx is None or len(sx) == 0:
@@ -180,11 +188,11 @@ class View:
 
 
 def render_view(state, dims, agent_color, road_xy, road_color, camera, palette,
-                ego: int, cam_dir=(1.0, 0.0), light=None, statics=None) -> View:
+                ego: int, cam_dir=(1.0, 0.0), light=None, statics=None, signals=None) -> View:
     """Render one ego view.  `camera` has width, height, focal_px, cam_height, z_near, z_far.
     `light` = (lx, ly, lz, ambient) turns on directional shading (unit direction
     towards the light, world frame).  `statics` = (xyp [k, 3], dims [k, 3],
-    colour [k]) are static obstacles."""
+    colour [k]) are static obstacles, `signals` = (xyzr [g, 4], colour [g]) traffic lights."""
     st = np.ascontiguousarray(state, dtype=np.float32)
     dm = np.ascontiguousarray(dims, dtype=np.float32)
     ac = np.ascontiguousarray(agent_color, dtype=np.uint8)
@@ -198,6 +206,11 @@ def render_view(state, dims, agent_color, road_xy, road_color, camera, palette,
         scol = np.ascontiguousarray(statics[2], np.uint8)
         assert sx.shape == sd.shape == (scol.shape[0], 3)
         sc.n_static, sc.static_xyp, sc.static_dims, sc.static_color = sx.shape[0], _ptr(sx), _ptr(sd), _ptr(scol)
+    if signals is not None and len(signals[0]):
+        gx = np.ascontiguousarray(signals[0], np.float32)
+        gc = np.ascontiguousarray(signals[1], np.uint8)
+        assert gx.shape == (gc.shape[0], 4)
+        sc.n_signals, sc.signal_xyzr, sc.signal_color = gx.shape[0], _ptr(gx), _ptr(gc)
     W, H = int(camera.width), int(camera.height)
     cm = _Camera(W, H, camera.focal_px, camera.cam_height, camera.z_near, camera.z_far, _ptr(pal))
     if light is not None:
@@ -218,7 +231,8 @@ def render_view(state, dims, agent_color, road_xy, road_color, camera, palette,
 def render_scene_view(scene, camera, palette, ego: int, cam: int = 0, light=None) -> View:
     """Render view (ego, cam) of a scenegen.Scene-like object."""
     return render_view(scene.agent_state, scene.agent_dims, scene.agent_color, scene.road_xy,
-                       scene.road_color, camera, palette, ego, camera.cam_dirs[cam], light, _statics(scene))
+                       scene.road_color, camera, palette, ego, camera.cam_dirs[cam], light, _statics(scene),
+                       _signals(scene))
 
 
 def render_views(items, camera, palette, threads: int = 1):

@@ -253,6 +253,9 @@ typedef struct {
     const float *static_xyp;      /* [n_static][3] x, y, psi */
     const float *static_dims;     /* [n_static][3] L, W, H */
     const uint8_t *static_color;  /* [n_static] */
+    int n_signals;                /* traffic lights: spheres */
+    const float *signal_xyzr;     /* [n_signals][4] x, y, z (centre, m), radius */
+    const uint8_t *signal_color;  /* [n_signals] palette index of the light's state */
 } gpo_scene;
 
 typedef struct {
@@ -444,6 +447,42 @@ static void raster_tri(target_t *t, const int32_t *X, const int32_t *Y,
     }
 }
 
+/* Sphere (a traffic light, Sec. 3.1) with camera-space centre c and radius r.
+ * Reading: the sample of pixel (i, j) casts the ray s D, D = (a, b, f) with
+ * a = (i + 0.5) - cx, b = cy - (j + 0.5); the ray meets the sphere when the
+ * centre's distance to it is below r, found from the closest approach
+ *     s0 = (D . c) / (D . D),  w = c - s0 D,  q = r^2 - w . w  (> 0: covered)
+ * and the fragment is the near hit s = s0 - sqrt(q / (D . D)) at planar depth
+ * z = s f, kept when z_near <= z <= z_far (the part of a sphere nearer than
+ * the near plane is clipped away, nothing behind it shows through).  binary32
+ * with fmaf, correctly rounded division and square root.  Spheres rank with
+ * the boxes on depth ties (class 1). */
+static void raster_sphere(target_t *t, v3 c, float r, uint32_t prim)
+{
+    const view_t *vw = t->vw;
+    const float f = vw->f, r2 = r * r, ff = f * f, fz = f * c.z;
+    for (int j = 0; j < vw->H; ++j) {
+        for (int i = 0; i < vw->W; ++i) {
+            const float a = ((float)i + 0.5f) - vw->cx;
+            const float b = vw->cy - ((float)j + 0.5f);
+            const float dd = fmaf(a, a, fmaf(b, b, ff));
+            const float dc = fmaf(a, c.x, fmaf(b, c.y, fz));
+            const float s0 = dc / dd;
+            const float wx = fmaf(-s0, a, c.x), wy = fmaf(-s0, b, c.y), wz = fmaf(-s0, f, c.z);
+            const float q = r2 - fmaf(wx, wx, fmaf(wy, wy, wz * wz));
+            if (!(q > 0.0f)) continue;
+            const float z = (s0 - sqrtf(q / dd)) * f;
+            if (!(z >= vw->z_near && z <= vw->z_far)) continue;
+            const float invz = 1.0f / z;
+            t->frags++;
+            uint64_t key = ((uint64_t)f32_bits(invz) << 32) | ((uint64_t)1u << 31)
+                         | (uint64_t)(0x7FFFFFFFu - prim);
+            uint64_t *slot = &t->key[j * vw->W + i];
+            if (key > *slot) *slot = key;
+        }
+    }
+}
+
 /* Clip, project, snap and raster one planar polygon (a box face or a road
  * quad).  nc = camera-space normal, p0 = a point of the face (camera space).
  * Boxes are one-sided: kept only if the camera is on the outer side (d < 0)
@@ -540,7 +579,9 @@ static uint32_t shade_level(const gpo_camera *cam, float nx, float ny, int face)
  * (ck, sk) = (cos, sin).  Outputs (any may be NULL): rgb [H][W][3], depth
  * [H][W] (1/invz, +inf for background), primid [H][W] (-1 for background).
  * Primitive index: 6*b + face for box b (the agents 0..n_agents-1, then the
- * static obstacles), 6*(n_agents + n_static) + road for roads.
+ * static obstacles), 6*(n_agents + n_static) + road for roads, then
+ * 6*(n_agents + n_static) + n_roads + g for traffic light g (unlit: lights
+ * are emissive).
  * Faces: 0 front, 1 left, 2 back, 3 right, 4 top, 5 bottom.
  * `key_scratch` must hold H*W uint64.  Returns the number of rasterised
  * triangles; *frags_out (optional) receives the fragment count. */
@@ -609,6 +650,12 @@ long long gpo_render_view(const gpo_scene *sc, const gpo_camera *cam, int ego, f
         v3 p0 = poly[0];
         ntri += raster_polygon(&t, poly, 4, nc, p0, 0, 0u, (uint32_t)(6 * n_box + r));
     }
+    /* traffic lights, numbered after every road */
+    const uint32_t sig0 = 6 * n_box + (uint32_t)sc->n_roads;
+    for (int g = 0; g < sc->n_signals; ++g) {
+        const float *q = sc->signal_xyzr + 4 * g;
+        raster_sphere(&t, to_cam(&vw, q[0] - vw.px, q[1] - vw.py, q[2]), q[3], sig0 + (uint32_t)g);
+    }
 
     /* resolve */
     for (int p = 0; p < W * H; ++p) {
@@ -622,14 +669,15 @@ long long gpo_render_view(const gpo_scene *sc, const gpo_camera *cam, int ego, f
             memcpy(&invz, &zb, 4);
             prim = (int32_t)(0x7FFFFFFFu - (uint32_t)(key & 0x7FFFFFFFu));
             const int32_t b = prim / 6;
-            color = prim >= (int32_t)(6 * n_box) ? sc->road_color[prim - 6 * (int32_t)n_box]
+            color = prim >= (int32_t)sig0       ? sc->signal_color[prim - (int32_t)sig0]
+                    : prim >= (int32_t)(6 * n_box) ? sc->road_color[prim - 6 * (int32_t)n_box]
                     : b < (int32_t)n_a            ? sc->agent_color[b]
                                                   : sc->static_color[b - (int32_t)n_a];
             dep = 1.0f / invz;
         }
         if (rgb) {
             uint32_t q = 255;
-            if (cam->shade && prim >= 0) {
+            if (cam->shade && prim >= 0 && prim < (int32_t)sig0) {     /* lights are emissive */
                 if (prim < (int32_t)(6 * n_box)) {
                     const int32_t b = prim / 6;
                     const float psi = b < (int32_t)n_a ? sc->agent_state[4 * b + 2]
@@ -645,7 +693,8 @@ long long gpo_render_view(const gpo_scene *sc, const gpo_camera *cam, int ego, f
             }
             for (int ch = 0; ch < 3; ++ch) {
                 uint32_t c = cam->palette[3 * color + ch];
-                rgb[3 * p + ch] = (uint8_t)(cam->shade && prim >= 0 ? (c * q + 127u) / 255u : c);
+                rgb[3 * p + ch] = (uint8_t)(cam->shade && prim >= 0 && prim < (int32_t)sig0 ? (c * q + 127u) / 255u
+                                                                                            : c);
             }
         }
         if (depth) depth[p] = dep;

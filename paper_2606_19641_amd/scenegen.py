@@ -31,6 +31,7 @@ S_ROADNET, S_SCENE, S_AGENT, S_ACTION = 1, 2, 3, 4
 
 # palette indices used by the generated scenes
 COLOR_BACKGROUND, COLOR_ROAD, COLOR_VEHICLE = 0, 1, 2
+COLOR_SIGNAL_RED, COLOR_SIGNAL_YELLOW, COLOR_SIGNAL_GREEN = 6, 7, 8
 
 
 def splitmix64(x):
@@ -67,6 +68,9 @@ class Scene:
     static_xyp: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 3), np.float32))
     static_dims: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 3), np.float32))
     static_color: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(0, np.uint8))
+    # traffic lights (spheres): [g, 4] x, y, z (centre), radius; [g] colour of the light's state
+    signal_xyzr: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 4), np.float32))
+    signal_color: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(0, np.uint8))
 
     @property
     def n_agents(self) -> int:
@@ -79,6 +83,10 @@ class Scene:
     @property
     def n_static(self) -> int:
         return int(self.static_xyp.shape[0])
+
+    @property
+    def n_signals(self) -> int:
+        return int(self.signal_xyzr.shape[0])
 
 
 @dataclasses.dataclass
@@ -105,6 +113,9 @@ def default_palette() -> np.ndarray:
     pal[COLOR_BACKGROUND] = (0, 0, 0)
     pal[COLOR_ROAD] = (128, 128, 128)
     pal[COLOR_VEHICLE] = (0, 0, 255)      # the paper colours every agent blue
+    pal[COLOR_SIGNAL_RED] = (255, 32, 32)
+    pal[COLOR_SIGNAL_YELLOW] = (255, 200, 0)
+    pal[COLOR_SIGNAL_GREEN] = (32, 224, 64)
     return pal
 
 
@@ -222,7 +233,34 @@ def place_statics(seed: int, scene: int, road_xy: np.ndarray, n_static: int) -> 
     return xyp, dims.astype(np.float32)
 
 
-def make_scene(seed: int, scene: int, n_agents: int, n_quads: int, n_static: int = 0) -> Scene:
+S_SIGNAL = 8
+SIGNAL_STATES = (COLOR_SIGNAL_RED, COLOR_SIGNAL_YELLOW, COLOR_SIGNAL_GREEN)
+
+
+def place_signals(seed: int, scene: int, road_xy: np.ndarray, n_signals: int) -> tuple:
+    """Traffic lights at lane-segment ends: 2.5..3.5 m to the side of the
+    centreline, centre 3.5..5.5 m up, radius 0.25..0.4 m, state red / yellow /
+    green with probabilities 0.45 / 0.1 / 0.45.  Returns (xyzr [g, 4], colour [g])."""
+    a = np.arange(n_signals)
+    u = lambda c: keyed_uniform(seed, S_SIGNAL, scene, a, c)
+    nq = road_xy.shape[0]
+    qi = np.minimum((u(0) * nq).astype(np.int64), nq - 1)
+    quad = road_xy[qi].astype(np.float64)
+    back = 0.5 * (quad[:, 0] + quad[:, 3])
+    front = 0.5 * (quad[:, 1] + quad[:, 2])
+    d = front - back
+    heading = np.arctan2(d[:, 1], d[:, 0])
+    nrm = np.stack([-np.sin(heading), np.cos(heading)], axis=1)
+    side = np.where(u(1) < 0.5, -1.0, 1.0)
+    pos = front + (side * (2.5 + u(2)))[:, None] * nrm
+    xyzr = np.stack([pos[:, 0], pos[:, 1], 3.5 + 2.0 * u(3), 0.25 + 0.15 * u(4)], axis=1).astype(np.float32)
+    st = u(5)
+    color = np.where(st < 0.45, COLOR_SIGNAL_RED, np.where(st < 0.55, COLOR_SIGNAL_YELLOW, COLOR_SIGNAL_GREEN))
+    return xyzr, color.astype(np.uint8)
+
+
+def make_scene(seed: int, scene: int, n_agents: int, n_quads: int, n_static: int = 0,
+               n_signals: int = 0) -> Scene:
     roads = road_network(seed, scene, n_quads)
     state, dims = place_agents(seed, scene, roads, n_agents)
     sc = Scene(agent_state=state, agent_dims=dims,
@@ -231,6 +269,8 @@ def make_scene(seed: int, scene: int, n_agents: int, n_quads: int, n_static: int
     if n_static:
         sc.static_xyp, sc.static_dims = place_statics(seed, scene, roads, n_static)
         sc.static_color = np.full(n_static, COLOR_VEHICLE, dtype=np.uint8)   # agents and obstacles blue
+    if n_signals:
+        sc.signal_xyzr, sc.signal_color = place_signals(seed, scene, roads, n_signals)
     return sc
 
 
