@@ -92,6 +92,15 @@ typedef struct {
     const float *static_xyp;          /* [n_static][3] x, y (m), psi (rad)                 */
     const float *static_dims;         /* [n_static][3] length, width, height (m)           */
     const uint8_t *static_color;      /* [n_static] palette index                          */
+    /* Traffic lights (Sec. 3.1: small spheres).  The sample of a pixel shows
+     * a light when its ray passes the centre closer than the radius; the
+     * fragment is the near intersection, at planar depth in [z_near, z_far].
+     * Light g has primitive index 6 (n_agents + n_static) + n_roads + g; its
+     * colour is the palette entry of its state (gp_sim_set_signal_colors), not
+     * lit by the directional light.  NULL / 0 for none. */
+    int32_t n_signals;                /* >= 0                                              */
+    const float *signal_xyzr;         /* [n_signals][4] x, y, z of the centre (m), radius  */
+    const uint8_t *signal_color;      /* [n_signals] palette index of the initial state    */
 } gp_scene_desc;
 
 /* Launch settings of the renderer.  Every setting gives bit-identical images;
@@ -142,6 +151,12 @@ gp_status gp_sim_render(gp_sim *sim, uint8_t *d_rgb, float *d_depth, int32_t *d_
  * on first use and re-captured when a pointer or the launch settings change.
  * Uses the persistent schedule whatever the current launch setting. */
 gp_status gp_sim_step_render_graph(gp_sim *sim, const float *d_actions, uint8_t *d_rgb, void *stream);
+
+/* Traffic-light states: d_colors, device uint8 [num_signals], the palette
+ * index of every light (scene order, then the lights' order in each scene),
+ * copied into the sim on `stream`.  fork copies the states too. */
+gp_status gp_sim_set_signal_colors(gp_sim *sim, const uint8_t *d_colors, void *stream);
+int64_t gp_sim_num_signals(const gp_sim *sim);
 
 /* Jerk-actuated step of every agent (App. A, "Action Space and Dynamics":
  * twelve discrete actions, the product of longitudinal jerks {-15, -4, 0, 4}
@@ -224,7 +239,7 @@ gp_status gp_batch_step_render(gp_sim *const *sims, int32_t n_sims, const float 
 gp_status gp_sim_check_infractions(gp_sim *sim, uint8_t *d_flags, void *stream);
 
 /* Fork: make dst's dynamic state (agent state, heading cosines, halted flags,
- * jerk actuators) a copy of src's (the paper rolls a teacher out in a forked
+ * jerk actuators, traffic-light states) a copy of src's (the paper rolls a teacher out in a forked
  * copy of the simulator, Sec. 3 "Pixel-based student training").  Both sims must have
  * been created over the same scenes.  Device-to-device, stream-ordered. */
 gp_status gp_sim_fork(gp_sim *dst, const gp_sim *src, void *stream);

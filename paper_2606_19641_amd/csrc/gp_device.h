@@ -20,7 +20,7 @@ struct SceneRec {
     int32_t view_base;              // first view of the scene
     int32_t bin_base, n_bins;       // culling bins [bin_base, bin_base + n_bins)
     int32_t static_base, n_static;  // static obstacles: box slots [static_base, static_base + n_static)
-    int32_t pad[2];
+    int32_t signal_base, n_signals; // traffic lights [signal_base, signal_base + n_signals)
 };
 
 // Box b of a scene (the agents, then the static obstacles) -> its slot in the
@@ -70,6 +70,8 @@ struct DevSim {
     uint8_t *halted;          // [A] 1 once the agent committed an infraction (frozen in place)
     uint8_t *infr;            // [A] infractions found by the last check (bit 0 collision, 1 off-road)
     float4 *actu;             // [A] jerk actuators: a_lon, a_lat, steering angle, 0
+    const float4 *signals;    // [G] traffic lights: x, y, z (centre), radius
+    uint8_t *signal_color;    // [G] palette index of each light's state
     float cam_dir[kMaxCams][2];
     float focal, cam_height, z_near, z_far, dt;
     float light[4];           // unit direction towards the light (world frame), ambient
@@ -106,14 +108,15 @@ hipError_t launch_step_jerk(const DevSim &s, const uint8_t *actions, hipStream_t
 // infraction check of every agent; flags_out (optional) [A] gets bit 0
 // collision, bit 1 off-road, bit 2 halted after the check
 hipError_t launch_infractions(const DevSim &s, int max_agents, uint8_t *flags_out, hipStream_t st);
-// fast = 1: rgb-only kernel for a uniform road colour; fast = 0: general kernel
-hipError_t launch_render(const DevSim &s, const RenderOut &o, const LaunchCfg &c, int fast,
+// kind 1: rgb-only kernel for a uniform road colour; 0: general kernel;
+// 2: general kernel with traffic lights
+hipError_t launch_render(const DevSim &s, const RenderOut &o, const LaunchCfg &c, int kind,
                          int persistent, int view_begin, int grid, hipStream_t st);
 size_t render_lds_bytes(const DevSim &s, const LaunchCfg &c, int fast);
 size_t render_lds_bytes(int width, int height, const LaunchCfg &c, int fast);
 // batched (serving) launches over a device table of sims
 hipError_t launch_step_multi(const SimEntry *tab, int n_sims, int max_agents, hipStream_t st);
 hipError_t launch_render_multi(const SimEntry *tab, const int2 *items, int n_items, uint32_t *ctl,
-                               const LaunchCfg &c, int fast, int width, int height, int grid, hipStream_t st);
+                               const LaunchCfg &c, int kind, int width, int height, int grid, hipStream_t st);
 
 }  // namespace gp

@@ -1567,10 +1567,12 @@ __device__ void resolve_general(const DevSim &s, const SceneRec &sc, const Cam &
         const unsigned long long key = L.zb[p];
         uint32_t c = L.pal[key ? ((uint32_t)key & 0xFFu) : 0u];
         if (s.shade && key) {
-            // boxes hold the primitives below 6 (n_agents + n_static)
-            const bool box = (((uint32_t)key >> 8) & (uint32_t)(kMaxPrims - 1)) >
-                             (uint32_t)(kMaxPrims - 1 - 6 * (sc.n_agents + sc.n_static));
-            c = box ? lit_box(s, sc, c, key) : shade_rgb(c, q_road);
+            // boxes hold the primitives below 6 (n_agents + n_static), then
+            // come the roads, then the (unlit) traffic lights
+            const uint32_t inv = ((uint32_t)key >> 8) & (uint32_t)(kMaxPrims - 1);
+            const int n_box = sc.n_agents + sc.n_static;
+            if (inv > (uint32_t)(kMaxPrims - 1 - 6 * n_box)) c = lit_box(s, sc, c, key);
+            else if (inv > (uint32_t)(kMaxPrims - 1 - 6 * n_box - sc.n_roads)) c = shade_rgb(c, q_road);
         }
         uint8_t *dst = o.rgb + 3 * (pix0 + p);
         dst[0] = (uint8_t)c;
@@ -1582,6 +1584,96 @@ __device__ void resolve_general(const DevSim &s, const SceneRec &sc, const Cam &
         }
         if (o.primid)
             o.primid[pix0 + p] = key ? (int32_t)(kMaxPrims - 1) - (int32_t)(((uint32_t)key >> 8) & (kMaxPrims - 1)) : -1;
+    }
+}
+
+// ------------------------------------------------------------ traffic lights
+//
+// Sec. 3.1: traffic lights are small spheres.  The sample of pixel (i, j)
+// casts the ray s D, D = (a, b, f), a = i + 0.5 - cx, b = cy - (j + 0.5); it
+// meets a sphere of camera-space centre c and radius r when, at the closest
+// approach s0 = (D . c) / (D . D), the miss w = c - s0 D has w . w < r^2; the
+// fragment is the near hit at planar depth z = (s0 - sqrt((r^2 - w . w) /
+// (D . D))) f, kept for z_near <= z <= z_far.  binary32 with fmaf and
+// correctly rounded division and square root.  Lights rank with the boxes on
+// depth ties, are numbered after the roads and are not lit (emissive).
+
+// Conservative pixel bounds of the sphere's part in [z_near, z_far]: the
+// projection of its bounding box, widened by a pixel; false if none.
+__device__ __forceinline__ bool signal_bounds(const Cam &cam, const V3 &c, float r, int &i0, int &i1, int &j0,
+                                              int &j1)
+{
+    if (c.z + r < cam.zn || c.z - r > cam.zf) return false;
+    const float zlo = fmaxf(c.z - r, cam.zn), zhi = fminf(c.z + r, cam.zf);
+    const float xm = c.x - r, xM = c.x + r, ym = c.y - r, yM = c.y + r;
+    const float xr0 = xm >= 0.0f ? xm / zhi : xm / zlo, xr1 = xM >= 0.0f ? xM / zlo : xM / zhi;
+    const float yr0 = ym >= 0.0f ? ym / zhi : ym / zlo, yr1 = yM >= 0.0f ? yM / zlo : yM / zhi;
+    const float u0 = fmaf(cam.f, xr0, cam.cx), u1 = fmaf(cam.f, xr1, cam.cx);
+    const float v0 = fmaf(-cam.f, yr1, cam.cy), v1 = fmaf(-cam.f, yr0, cam.cy);
+    const float Wf = (float)cam.W, Hf = (float)cam.H;
+    i0 = max((int)fminf(fmaxf(floorf(u0 - 0.5f) - 1.0f, -1.0f), Wf), 0);
+    i1 = min((int)fminf(fmaxf(ceilf(u1 - 0.5f) + 1.0f, -1.0f), Wf), cam.W - 1);
+    j0 = max((int)fminf(fmaxf(floorf(v0 - 0.5f) - 1.0f, -1.0f), Hf), 0);
+    j1 = min((int)fminf(fmaxf(ceilf(v1 - 0.5f) + 1.0f, -1.0f), Hf), cam.H - 1);
+    return i0 <= i1 && j0 <= j1;
+}
+
+// Lights of the scene into the key band of rows [b0, b1), in chunks staged
+// through the setup's survivor and clip-queue space (free during the band
+// pass): 8 words per light, one array per word.
+__device__ void raster_signals(const DevSim &s, const SceneRec &sc, const Cam &cam, Lds &L, int b0, int b1)
+{
+    const int B = blockDim.x, tid = threadIdx.x, W = cam.W;
+    const int cap = (12 * B) / 32;
+    lptr<float> fr = (lptr<float>)L.surv;              // xc, yc, zc, r^2, f zc: fr[k * cap + g]
+    lptr<int32_t> ir = L.surv + 5 * cap;               // key word, (i0, j0), (i1, j1)
+    const int sig0 = 6 * (sc.n_agents + sc.n_static) + sc.n_roads;
+    const float f = cam.f, ff = f * f;
+    for (int g0 = 0; g0 < sc.n_signals; g0 += cap) {
+        const int ng = min(cap, sc.n_signals - g0);
+        __syncthreads();
+        if (tid < ng) {
+            const int g = sc.signal_base + g0 + tid;
+            const float4 q = s.signals[g];
+            const V3 c = to_cam(cam, q.x - cam.px, q.y - cam.py, q.z);
+            int i0, i1, j0, j1;
+            const bool vis = signal_bounds(cam, c, q.w, i0, i1, j0, j1);
+            j0 = max(j0, b0);
+            j1 = min(j1, b1 - 1);
+            const bool keep = vis && j0 <= j1;
+            fr[tid] = c.x;
+            fr[cap + tid] = c.y;
+            fr[2 * cap + tid] = c.z;
+            fr[3 * cap + tid] = q.w * q.w;
+            fr[4 * cap + tid] = f * c.z;
+            ir[tid] = (int32_t)key_low(1u, sig0 + g0 + tid, s.signal_color[g]);
+            ir[cap + tid] = keep ? (i0 | (j0 << 16)) : 1;           // empty: i0 > i1
+            ir[2 * cap + tid] = keep ? (i1 | (j1 << 16)) : 0;
+        }
+        __syncthreads();
+        for (int k = 0; k < ng; ++k) {
+            const int p0 = ir[cap + k], p1 = ir[2 * cap + k];
+            const int i0 = p0 & 0xFFFF, j0 = p0 >> 16, i1 = p1 & 0xFFFF, j1 = p1 >> 16;
+            if (i0 > i1) continue;
+            const float xc = fr[k], yc = fr[cap + k], zc = fr[2 * cap + k], r2 = fr[3 * cap + k], fz = fr[4 * cap + k];
+            const uint32_t keylo = (uint32_t)ir[k];
+            const int w = i1 - i0 + 1, n = w * (j1 - j0 + 1);
+            for (int p = tid; p < n; p += B) {
+                const int dj = p / w, i = i0 + (p - dj * w), j = j0 + dj;
+                const float a = ((float)i + 0.5f) - cam.cx;
+                const float b = cam.cy - ((float)j + 0.5f);
+                const float dd = fmaf(a, a, fmaf(b, b, ff));
+                const float dc = fmaf(a, xc, fmaf(b, yc, fz));
+                const float s0 = dc / dd;
+                const float wx = fmaf(-s0, a, xc), wy = fmaf(-s0, b, yc), wz = fmaf(-s0, f, zc);
+                const float qq = r2 - fmaf(wx, wx, fmaf(wy, wy, wz * wz));
+                if (!(qq > 0.0f)) continue;
+                const float z = (s0 - sqrtf(qq / dd)) * f;
+                if (!(z >= cam.zn && z <= cam.zf)) continue;
+                const float invz = 1.0f / z;
+                lds_max64(L.zb + (size_t)(j - b0) * W + i, ((unsigned long long)__float_as_uint(invz) << 32) | keylo);
+            }
+        }
     }
 }
 
@@ -1599,7 +1691,8 @@ __device__ __forceinline__ SceneRec uniform_scene(const SceneRec &r)
     u.n_bins = __builtin_amdgcn_readfirstlane(r.n_bins);
     u.static_base = __builtin_amdgcn_readfirstlane(r.static_base);
     u.n_static = __builtin_amdgcn_readfirstlane(r.n_static);
-    u.pad[0] = u.pad[1] = 0;
+    u.signal_base = __builtin_amdgcn_readfirstlane(r.signal_base);
+    u.n_signals = __builtin_amdgcn_readfirstlane(r.n_signals);
     return u;
 }
 
@@ -1609,9 +1702,13 @@ __device__ __forceinline__ void reset_counts(Lds &L)
     if (t < C_NCNT) L.cnt[t] = (t == C_BMIN) ? 0x7FFFFFFF : (t == C_BMAX ? -1 : 0);
 }
 
-template <int FAST>
+// KIND 0: general kernel; 1: rgb kernel; 2: general kernel with traffic
+// lights (their code lives in its own instances so that it does not add to
+// the registers of the other two)
+template <int KIND>
 __device__ void render_view(const DevSim &s, const RenderOut &o, const LaunchCfg &lc, Lds &L, int view)
 {
+    constexpr int FAST = KIND == 1 ? 1 : 0;
     // the view's records are the same for the whole workgroup: scalar registers
     const int scene = __builtin_amdgcn_readfirstlane(s.views[view].scene);
     const int ego_cam = __builtin_amdgcn_readfirstlane(s.views[view].ego_cam);
@@ -1670,6 +1767,10 @@ __device__ void render_view(const DevSim &s, const RenderOut &o, const LaunchCfg
             setup_source<0, FAST>(s, sc, cam, ego, KB, L);
             if (!FAST) setup_source<1, FAST>(s, sc, cam, ego, KB, L);
             flush_tris(cam, L, KB);
+        }
+        if (KIND == 2 && sc.n_signals > 0) {
+            raster_signals(s, sc, cam, L, b0, b1);
+            __syncthreads();
         }
         if (FAST) resolve_fast<true>(s, cam, L, o.rgb, view, b0, b1, b0);
         else resolve_general(s, sc, cam, L, o, view, b0, b1);
@@ -1732,10 +1833,11 @@ __device__ __forceinline__ void load_palette(const DevSim &s, Lds &L, int fast)
 
 // BLOCK is the launch's block size: the bound lets the register allocator
 // use what a BLOCK-thread workgroup can have instead of assuming 1024 threads.
-template <int FAST, int BLOCK>
+template <int KIND, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_render(DevSim s, RenderOut o, LaunchCfg lc, int persistent,
                                                   int view_begin)
 {
+    constexpr int FAST = KIND == 1 ? 1 : 0;
     extern __shared__ __align__(16) unsigned char smem[];
     Lds L;
     carve_lds(smem, L, s.width, s.height, lc, FAST);
@@ -1743,7 +1845,7 @@ __global__ __launch_bounds__(BLOCK) void k_render(DevSim s, RenderOut o, LaunchC
     __shared__ int s_item;
     if (!persistent) {
         __syncthreads();
-        render_view<FAST>(s, o, lc, L, view_begin + blockIdx.x);
+        render_view<KIND>(s, o, lc, L, view_begin + blockIdx.x);
         return;
     }
     // Work queue: kQueues segments of the view order, one per XCD; a segment
@@ -1773,7 +1875,7 @@ __global__ __launch_bounds__(BLOCK) void k_render(DevSim s, RenderOut o, LaunchC
         __syncthreads();
         const int it = __builtin_amdgcn_readfirstlane(s_item);
         if (it >= s.n_views) break;
-        render_view<FAST>(s, o, lc, L, s.queue[it]);
+        render_view<KIND>(s, o, lc, L, s.queue[it]);
     }
     if (threadIdx.x == 0) {
         __threadfence();
@@ -1790,11 +1892,12 @@ __global__ __launch_bounds__(BLOCK) void k_render(DevSim s, RenderOut o, LaunchC
 // workgroups pull them from one queue.  ctl[0] is the queue head, ctl[1]
 // counts the workgroups that have left; the last one zeroes both.  Every sim
 // of the batch has W x H images; the palette is reloaded when the sim changes.
-template <int FAST, int BLOCK>
+template <int KIND, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_render_multi(const SimEntry *__restrict__ tab,
                                                         const int2 *__restrict__ items, int n_items,
                                                         uint32_t *ctl, LaunchCfg lc, int W, int H)
 {
+    constexpr int FAST = KIND == 1 ? 1 : 0;
     extern __shared__ __align__(16) unsigned char smem[];
     Lds L;
     carve_lds(smem, L, W, H, lc, FAST);
@@ -1817,7 +1920,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_multi(const SimEntry *__restri
             cur = k;
             __syncthreads();
         }
-        render_view<FAST>(s, o, lc, L, view);
+        render_view<KIND>(s, o, lc, L, view);
     }
     if (threadIdx.x == 0) {
         __threadfence();
@@ -1876,21 +1979,21 @@ hipError_t launch_step_multi(const SimEntry *tab, int n_sims, int max_agents, hi
 }
 
 hipError_t launch_render_multi(const SimEntry *tab, const int2 *items, int n_items, uint32_t *ctl,
-                               const LaunchCfg &c, int fast, int width, int height, int grid, hipStream_t st)
+                               const LaunchCfg &c, int kind, int width, int height, int grid, hipStream_t st)
 {
     if (n_items <= 0 || grid <= 0) return hipSuccess;
-    const size_t lds = render_lds_bytes(width, height, c, fast);
+    const size_t lds = render_lds_bytes(width, height, c, kind == 1);
 #define GP_LAUNCH(F, B)                                                                                 \
     hipLaunchKernelGGL((k_render_multi<F, B>), dim3(grid), dim3(B), lds, st, tab, items, n_items, ctl, c, width, height)
     switch (c.block_threads) {
     case 256:
-        if (fast) GP_LAUNCH(1, 256); else GP_LAUNCH(0, 256);
+        if (kind == 1) GP_LAUNCH(1, 256); else if (kind == 2) GP_LAUNCH(2, 256); else GP_LAUNCH(0, 256);
         break;
     case 512:
-        if (fast) GP_LAUNCH(1, 512); else GP_LAUNCH(0, 512);
+        if (kind == 1) GP_LAUNCH(1, 512); else if (kind == 2) GP_LAUNCH(2, 512); else GP_LAUNCH(0, 512);
         break;
     case 1024:
-        if (fast) GP_LAUNCH(1, 1024); else GP_LAUNCH(0, 1024);
+        if (kind == 1) GP_LAUNCH(1, 1024); else if (kind == 2) GP_LAUNCH(2, 1024); else GP_LAUNCH(0, 1024);
         break;
     default:
         return hipErrorInvalidValue;
@@ -1918,22 +2021,22 @@ hipError_t launch_infractions(const DevSim &s, int max_agents, uint8_t *flags_ou
     return hipGetLastError();
 }
 
-hipError_t launch_render(const DevSim &s, const RenderOut &o, const LaunchCfg &c, int fast,
+hipError_t launch_render(const DevSim &s, const RenderOut &o, const LaunchCfg &c, int kind,
                          int persistent, int view_begin, int grid, hipStream_t st)
 {
     if (grid <= 0) return hipSuccess;
-    const size_t lds = render_lds_bytes(s, c, fast);
+    const size_t lds = render_lds_bytes(s, c, kind == 1);
 #define GP_LAUNCH(F, B)                                                                                 \
     hipLaunchKernelGGL((k_render<F, B>), dim3(grid), dim3(B), lds, st, s, o, c, persistent, view_begin)
     switch (c.block_threads) {
     case 256:
-        if (fast) GP_LAUNCH(1, 256); else GP_LAUNCH(0, 256);
+        if (kind == 1) GP_LAUNCH(1, 256); else if (kind == 2) GP_LAUNCH(2, 256); else GP_LAUNCH(0, 256);
         break;
     case 512:
-        if (fast) GP_LAUNCH(1, 512); else GP_LAUNCH(0, 512);
+        if (kind == 1) GP_LAUNCH(1, 512); else if (kind == 2) GP_LAUNCH(2, 512); else GP_LAUNCH(0, 512);
         break;
     case 1024:
-        if (fast) GP_LAUNCH(1, 1024); else GP_LAUNCH(0, 1024);
+        if (kind == 1) GP_LAUNCH(1, 1024); else if (kind == 2) GP_LAUNCH(2, 1024); else GP_LAUNCH(0, 1024);
         break;
     default:
         return hipErrorInvalidValue;

@@ -47,11 +47,11 @@ int64_t n_bins_of(int32_t n_roads) { return 2 * ((n_roads + gp::kBinQuads - 1) /
 constexpr float kBinExtent = 32.0f;   // metres
 
 struct Layout {
-    int64_t halted, infr, actu;
+    int64_t halted, infr, actu, signals, signal_color;
     int64_t scenes, views, state, cs, dims, agent_color, roads, road_index, road_color, bins, palette,
         queue, counter;
     int64_t total;
-    int64_t n_agents, n_roads, n_views, n_bins, n_static;
+    int64_t n_agents, n_roads, n_views, n_bins, n_static, n_signals;
 };
 
 bool finite_cfg(const gp_config *c)
@@ -82,13 +82,23 @@ gp_status check_inputs(const gp_config *cfg, const gp_scene_desc *sc, int32_t n)
         if (d.n_agents < 1 || d.n_roads < 0)
             return fail(GP_EINVAL, "scene %d: n_agents must be >= 1 and n_roads >= 0", s);
         if (d.n_static < 0) return fail(GP_EINVAL, "scene %d: n_static must be >= 0", s);
-        if (6LL * ((int64_t)d.n_agents + d.n_static) + d.n_roads >= gp::kMaxPrims)
+        if (d.n_signals < 0) return fail(GP_EINVAL, "scene %d: n_signals must be >= 0", s);
+        if (6LL * ((int64_t)d.n_agents + d.n_static) + d.n_roads + d.n_signals >= gp::kMaxPrims)
             return fail(GP_EINVAL, "scene %d: more than %d primitives", s, gp::kMaxPrims);
         if (d.n_static > 0 && (!d.static_xyp || !d.static_dims || !d.static_color))
             return fail(GP_EINVAL, "scene %d: static obstacle arrays are NULL", s);
         for (int64_t i = 0; i < 3LL * d.n_static; ++i)
             if (!std::isfinite(d.static_xyp[i]) || !std::isfinite(d.static_dims[i]))
                 return fail(GP_EINVAL, "scene %d: static obstacle not finite", s);
+        if (d.n_signals > 0 && (!d.signal_xyzr || !d.signal_color))
+            return fail(GP_EINVAL, "scene %d: traffic light arrays are NULL", s);
+        for (int64_t g = 0; g < d.n_signals; ++g) {
+            for (int k = 0; k < 4; ++k)
+                if (!std::isfinite(d.signal_xyzr[4 * g + k]))
+                    return fail(GP_EINVAL, "scene %d: traffic light not finite", s);
+            if (!(d.signal_xyzr[4 * g + 3] > 0.0f) || d.signal_xyzr[4 * g + 3] > 100.0f)
+                return fail(GP_EINVAL, "scene %d: traffic light radius outside (0, 100] m", s);
+        }
         if (!d.agent_state || !d.agent_dims || !d.agent_color)
             return fail(GP_EINVAL, "scene %d: agent arrays are NULL", s);
         if (d.n_roads > 0 && (!d.road_xy || !d.road_color))
@@ -112,6 +122,7 @@ Layout make_layout(const gp_config *cfg, const gp_scene_desc *sc, int32_t n)
     for (int s = 0; s < n; ++s) {
         L.n_agents += sc[s].n_agents;
         L.n_static += sc[s].n_static;
+        L.n_signals += sc[s].n_signals;
         L.n_roads += sc[s].n_roads;
         L.n_bins += n_bins_of(sc[s].n_roads);
     }
@@ -134,6 +145,8 @@ Layout make_layout(const gp_config *cfg, const gp_scene_desc *sc, int32_t n)
     L.halted = take(L.n_agents);
     L.infr = take(L.n_agents);
     L.actu = take(16 * L.n_agents);
+    L.signals = take(16 * L.n_signals);
+    L.signal_color = take(L.n_signals);
     L.queue = take(4 * L.n_views);
     L.counter = take(4 * (gp::kQueues + 2));
     L.total = o;
@@ -282,18 +295,19 @@ gp_status render_impl(gp_sim *sim, const gp::RenderOut &o, const gp_launch &l, h
     const gp::LaunchCfg c = launch_cfg(l);
     // the rgb-only kernel serves renders without depth / primitive id when
     // every road strip has the same colour; everything else takes the general one
-    const int fast = (!o.depth && !o.primid && sim->dev.road_color_uniform) ? 1 : 0;
+    // (scenes with traffic lights take the general kernel's instances with lights)
+    const int kind = sim->lay.n_signals > 0 ? 2 : (!o.depth && !o.primid && sim->dev.road_color_uniform) ? 1 : 0;
     hipError_t e;
     if (l.sched == GP_SCHED_PLAIN) {
         for (int s = 0; s < sim->n_scenes; ++s) {
             const gp::SceneRec &r = sim->scenes[s];
-            e = gp::launch_render(sim->dev, o, c, fast, 0, r.view_base, r.n_agents * sim->cfg.n_cams, st);
+            e = gp::launch_render(sim->dev, o, c, kind, 0, r.view_base, r.n_agents * sim->cfg.n_cams, st);
             if (e != hipSuccess) return hip_fail(e, "render launch");
         }
         return GP_OK;
     }
     const int64_t grid = std::min<int64_t>(sim->lay.n_views, (int64_t)l.blocks_per_cu * sim->n_cu);
-    e = gp::launch_render(sim->dev, o, c, fast, 1, 0, (int)grid, st);
+    e = gp::launch_render(sim->dev, o, c, kind, 1, 0, (int)grid, st);
     if (e != hipSuccess) return hip_fail(e, "render launch");
     return GP_OK;
 }
@@ -379,7 +393,9 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
     auto *ridx = reinterpret_cast<int32_t *>(at(L.road_index));
     auto *rcol = at(L.road_color);
     auto *bins = reinterpret_cast<gp::RoadBin *>(at(L.bins));
-    int32_t abase = 0, rbase = 0, bbase = 0, sbase = (int32_t)L.n_agents;
+    int32_t abase = 0, rbase = 0, bbase = 0, sbase = (int32_t)L.n_agents, gbase = 0;
+    auto *sig = reinterpret_cast<float *>(at(L.signals));
+    auto *sigc = at(L.signal_color);
     bool uniform = true;
     int color0 = -1;
     for (int s = 0; s < n_scenes; ++s) {
@@ -396,7 +412,6 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
         r.n_bins = (int32_t)sb.size();
         r.static_base = sbase;
         r.n_static = d.n_static;
-        r.pad[0] = r.pad[1] = 0;
         for (int k = 0; k < d.n_static; ++k) {     // static obstacles: v = 0, never stepped
             const int g = sbase + k;
             for (int c = 0; c < 3; ++c) state[4 * g + c] = d.static_xyp[3 * k + c];
@@ -406,6 +421,13 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
             acol[g] = d.static_color[k];
         }
         sbase += d.n_static;
+        r.signal_base = gbase;
+        r.n_signals = d.n_signals;
+        if (d.n_signals > 0) {
+            std::memcpy(sig + 4 * (int64_t)gbase, d.signal_xyzr, 16 * (size_t)d.n_signals);
+            std::memcpy(sigc + gbase, d.signal_color, (size_t)d.n_signals);
+        }
+        gbase += d.n_signals;
         for (int a = 0; a < d.n_agents; ++a) {
             const int g = r.agent_base + a;
             for (int k = 0; k < 4; ++k) state[4 * g + k] = d.agent_state[4 * a + k];
@@ -440,7 +462,9 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
     // and the views of a scene are adjacent.
     std::vector<int> order(n_scenes);
     std::iota(order.begin(), order.end(), 0);
-    auto view_work = [&](int s) { return 6LL * (scenes[s].n_agents + scenes[s].n_static) + scenes[s].n_roads + 64; };
+    auto view_work = [&](int s) {
+        return 6LL * (scenes[s].n_agents + scenes[s].n_static) + scenes[s].n_roads + 4LL * scenes[s].n_signals + 64;
+    };
     auto scene_work = [&](int s) { return view_work(s) * (int64_t)scenes[s].n_agents * cfg->n_cams; };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return scene_work(a) > scene_work(b); });
     std::vector<std::vector<int>> seg(gp::kQueues);
@@ -483,6 +507,8 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
     D.halted = base + L.halted;
     D.infr = base + L.infr;
     D.actu = reinterpret_cast<float4 *>(base + L.actu);
+    D.signals = reinterpret_cast<const float4 *>(base + L.signals);
+    D.signal_color = base + L.signal_color;
     D.queue = reinterpret_cast<const int32_t *>(base + L.queue);
     D.counter = reinterpret_cast<uint32_t *>(base + L.counter);
     D.n_scenes = n_scenes;
@@ -493,7 +519,8 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
     D.height = cfg->height;
     D.n_cams = cfg->n_cams;
     sim->road_uniform = uniform ? 1 : 0;
-    D.road_color_uniform = sim->road_uniform;    // the rgb kernel needs unlit frames too
+    // the rgb kernel needs unlit frames without traffic lights
+    D.road_color_uniform = (sim->road_uniform && L.n_signals == 0) ? 1 : 0;
     D.shade = 0;
     D.road_color0 = color0 < 0 ? 0 : color0;
     for (int k = 0; k < gp::kMaxCams; ++k) {
@@ -671,6 +698,7 @@ gp_status gp_batch_step_render(gp_sim *const *sims, int32_t n_sims, const float 
     auto *items = reinterpret_cast<int32_t *>(h + B.items);
     auto *act = reinterpret_cast<float *>(h + B.actions);
     int64_t a0 = 0, n_fast = 0;
+    bool lights = false;          // the general launch takes the instances with traffic lights
     for (int k = 0; k < n_sims; ++k) {
         const gp_sim *sim = sims[k];
         gp::SimEntry e{};
@@ -681,6 +709,7 @@ gp_status gp_batch_step_render(gp_sim *const *sims, int32_t n_sims, const float 
         std::memcpy(act + 2 * a0, h_actions[k], 8 * (size_t)sim->lay.n_agents);
         a0 += sim->lay.n_agents;
         if (sim->dev.road_color_uniform) n_fast += sim->lay.n_views;
+        lights = lights || sim->lay.n_signals > 0;
     }
     int64_t qf = 0, qg = n_fast;
     for (int k = 0; k < n_sims; ++k) {
@@ -709,8 +738,8 @@ gp_status gp_batch_step_render(gp_sim *const *sims, int32_t n_sims, const float 
         if (gp::render_lds_bytes(W, H, c, fast) > sims[0]->max_lds)
             return fail(GP_EINVAL, "launch setting needs more LDS than the device has");
         const int grid = (int)std::min<int64_t>(n, (int64_t)l.blocks_per_cu * sims[0]->n_cu);
-        e = gp::launch_render_multi(dtab, ditems + (fast ? 0 : n_fast), (int)n, ctl + (fast ? 0 : 2), c, fast, W,
-                                    H, grid, hs);
+        e = gp::launch_render_multi(dtab, ditems + (fast ? 0 : n_fast), (int)n, ctl + (fast ? 0 : 2), c,
+                                    fast ? 1 : (lights ? 2 : 0), W, H, grid, hs);
         if (e != hipSuccess) return hip_fail(e, "batch render launch");
     }
     return GP_OK;
@@ -750,9 +779,20 @@ gp_status gp_sim_set_light(gp_sim *sim, const float *h_light)
     sim->dev.shade = h_light ? 1 : 0;
     for (int k = 0; k < 4; ++k) sim->dev.light[k] = h_light ? h_light[k] : 0.0f;
     // lit frames are resolved by the general kernel
-    sim->dev.road_color_uniform = (sim->road_uniform && !h_light) ? 1 : 0;
+    sim->dev.road_color_uniform = (sim->road_uniform && !h_light && sim->lay.n_signals == 0) ? 1 : 0;
     return GP_OK;
 }
+
+gp_status gp_sim_set_signal_colors(gp_sim *sim, const uint8_t *d_colors, void *stream)
+{
+    if (!sim || !d_colors) return fail(GP_EINVAL, "NULL argument");
+    if (sim->lay.n_signals == 0) return GP_OK;
+    hipError_t e = hipMemcpyAsync(sim->dev.signal_color, d_colors, (size_t)sim->lay.n_signals,
+                                  hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? GP_OK : hip_fail(e, "set_signal_colors copy");
+}
+
+int64_t gp_sim_num_signals(const gp_sim *sim) { return sim ? sim->lay.n_signals : -1; }
 
 gp_status gp_sim_step_jerk(gp_sim *sim, const uint8_t *d_actions, void *stream)
 {
@@ -785,7 +825,7 @@ gp_status gp_sim_fork(gp_sim *dst, const gp_sim *src, void *stream)
     if (dst->n_scenes != src->n_scenes) return fail(GP_EINVAL, "fork needs sims over the same scenes");
     for (int k = 0; k < src->n_scenes; ++k)
         if (dst->scenes[k].n_agents != src->scenes[k].n_agents || dst->scenes[k].n_roads != src->scenes[k].n_roads ||
-            dst->scenes[k].n_static != src->scenes[k].n_static)
+            dst->scenes[k].n_static != src->scenes[k].n_static || dst->scenes[k].n_signals != src->scenes[k].n_signals)
             return fail(GP_EINVAL, "fork needs sims over the same scenes (scene %d differs)", k);
     hipStream_t hs = static_cast<hipStream_t>(stream);
     const size_t n = (size_t)src->lay.n_agents;
@@ -793,6 +833,9 @@ gp_status gp_sim_fork(gp_sim *dst, const gp_sim *src, void *stream)
     if (e == hipSuccess) e = hipMemcpyAsync(dst->dev.cs, src->dev.cs, 8 * n, hipMemcpyDeviceToDevice, hs);
     if (e == hipSuccess) e = hipMemcpyAsync(dst->dev.halted, src->dev.halted, n, hipMemcpyDeviceToDevice, hs);
     if (e == hipSuccess) e = hipMemcpyAsync(dst->dev.actu, src->dev.actu, 16 * n, hipMemcpyDeviceToDevice, hs);
+    if (e == hipSuccess && src->lay.n_signals > 0)
+        e = hipMemcpyAsync(dst->dev.signal_color, src->dev.signal_color, (size_t)src->lay.n_signals,
+                           hipMemcpyDeviceToDevice, hs);
     return e == hipSuccess ? GP_OK : hip_fail(e, "fork copy");
 }
 

@@ -24,7 +24,7 @@ EXPORTS = ("gp_sim_required_bytes", "gp_sim_create", "gp_sim_set_launch", "gp_si
            "gp_sim_set_state", "gp_sim_num_views", "gp_sim_num_agents", "gp_sim_num_scenes",
            "gp_sim_destroy", "gp_last_error", "gp_batch_required_bytes", "gp_batch_step_render",
            "gp_sim_check_infractions", "gp_sim_fork", "gp_sim_step_jerk", "gp_sim_get_actuators",
-           "gp_sim_set_light")
+           "gp_sim_set_light", "gp_sim_set_signal_colors", "gp_sim_num_signals")
 
 
 class GpError(RuntimeError):
@@ -45,7 +45,8 @@ class SceneDesc(C.Structure):
                 ("agent_state", C.c_void_p), ("agent_dims", C.c_void_p),
                 ("agent_color", C.c_void_p), ("road_xy", C.c_void_p), ("road_color", C.c_void_p),
                 ("n_static", C.c_int32), ("static_xyp", C.c_void_p), ("static_dims", C.c_void_p),
-                ("static_color", C.c_void_p)]
+                ("static_color", C.c_void_p), ("n_signals", C.c_int32), ("signal_xyzr", C.c_void_p),
+                ("signal_color", C.c_void_p)]
 
 
 class Launch(C.Structure):
@@ -97,8 +98,11 @@ def lib() -> C.CDLL:
         L.gp_sim_step_jerk.argtypes = [vp, vp, vp]
         L.gp_sim_get_actuators.argtypes = [vp, vp, vp]
         L.gp_sim_set_light.argtypes = [vp, vp]
+        L.gp_sim_set_signal_colors.argtypes = [vp, vp, vp]
+        L.gp_sim_num_signals.argtypes = [vp]
+        L.gp_sim_num_signals.restype = C.c_int64
         for name in ("gp_sim_check_infractions", "gp_sim_fork", "gp_sim_step_jerk", "gp_sim_get_actuators",
-                     "gp_sim_set_light", "gp_batch_step_render", "gp_sim_create", "gp_sim_set_launch", "gp_sim_get_launch", "gp_sim_step",
+                     "gp_sim_set_light", "gp_sim_set_signal_colors", "gp_batch_step_render", "gp_sim_create", "gp_sim_set_launch", "gp_sim_get_launch", "gp_sim_step",
                      "gp_sim_render", "gp_sim_step_render_graph", "gp_sim_get_state",
                      "gp_sim_set_state"):
             getattr(L, name).restype = C.c_int
@@ -160,6 +164,15 @@ def _scene_descs(scenes: Sequence):
             descs[i].n_static = sx.shape[0]
             descs[i].static_xyp, descs[i].static_dims, descs[i].static_color = (
                 sx.ctypes.data, sd.ctypes.data, sc.ctypes.data)
+        gx = getattr(s, "signal_xyzr", None)
+        if gx is not None and len(gx):
+            gx = np.ascontiguousarray(gx, dtype=np.float32)
+            gc = np.ascontiguousarray(s.signal_color, dtype=np.uint8)
+            if gx.shape != (gc.shape[0], 4):
+                raise ValueError("traffic lights need xyzr [g, 4] and colour [g]")
+            keep += [gx, gc]
+            descs[i].n_signals = gx.shape[0]
+            descs[i].signal_xyzr, descs[i].signal_color = gx.ctypes.data, gc.ctypes.data
     return descs, keep
 
 
@@ -244,6 +257,15 @@ class Sim:
         (3 * longitudinal + lateral; larger indices coast)."""
         self._check_tensor(actions, (self.n_agents,), "uint8")
         _check(lib().gp_sim_step_jerk(self._h, actions.data_ptr(), _stream_handle(stream)))
+
+    @property
+    def n_signals(self) -> int:
+        return int(lib().gp_sim_num_signals(self._h))
+
+    def set_signal_colors(self, colors, stream=None):
+        """colors: uint8 [n_signals] device tensor, the palette index of every light's state."""
+        self._check_tensor(colors, (self.n_signals,), "uint8")
+        _check(lib().gp_sim_set_signal_colors(self._h, colors.data_ptr(), _stream_handle(stream)))
 
     def set_light(self, light=None):
         """light = (lx, ly, lz, ambient): unit direction towards the light (world
