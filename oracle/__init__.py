@@ -71,6 +71,8 @@ def lib():
                                       C.c_float, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.POINTER(C.c_longlong)]
         L.gpo_render_view.restype = C.c_longlong
+        L.gpo_raycast_view.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.c_int, C.c_float,
+                                       C.c_float, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.gpo_cover_tri.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_void_p]
         _lib = L
     return _lib
@@ -188,11 +190,13 @@ class View:
 
 
 def render_view(state, dims, agent_color, road_xy, road_color, camera, palette,
-                ego: int, cam_dir=(1.0, 0.0), light=None, statics=None, signals=None) -> View:
+                ego: int, cam_dir=(1.0, 0.0), light=None, statics=None, signals=None,
+                backend: str = "raster") -> View:
     """Render one ego view.  `camera` has width, height, focal_px, cam_height, z_near, z_far.
     `light` = (lx, ly, lz, ambient) turns on directional shading (unit direction
     towards the light, world frame).  `statics` = (xyp [k, 3], dims [k, 3],
-    colour [k]) are static obstacles, `signals` = (xyzr [g, 4], colour [g]) traffic lights."""
+    colour [k]) are static obstacles, `signals` = (xyzr [g, 4], colour [g]) traffic lights.
+    backend "raycast" casts one primary ray per pixel instead of rasterising."""
     st = np.ascontiguousarray(state, dtype=np.float32)
     dm = np.ascontiguousarray(dims, dtype=np.float32)
     ac = np.ascontiguousarray(agent_color, dtype=np.uint8)
@@ -222,17 +226,23 @@ def render_view(state, dims, agent_color, road_xy, road_color, camera, palette,
     depth = np.empty((H, W), dtype=np.float32)
     prim = np.empty((H, W), dtype=np.int32)
     nf = C.c_longlong(0)
+    if backend == "raycast":
+        lib().gpo_raycast_view(C.byref(sc), C.byref(cm), int(ego), C.c_float(cam_dir[0]), C.c_float(cam_dir[1]),
+                               _ptr(key), _ptr(rgb), _ptr(depth), _ptr(prim))
+        return View(rgb, depth, prim, -1, -1)
+    if backend != "raster":
+        raise ValueError(backend)
     nt = lib().gpo_render_view(C.byref(sc), C.byref(cm), int(ego), C.c_float(cam_dir[0]),
                                C.c_float(cam_dir[1]), _ptr(key), _ptr(rgb), _ptr(depth),
                                _ptr(prim), C.byref(nf))
     return View(rgb, depth, prim, int(nt), int(nf.value))
 
 
-def render_scene_view(scene, camera, palette, ego: int, cam: int = 0, light=None) -> View:
+def render_scene_view(scene, camera, palette, ego: int, cam: int = 0, light=None, backend: str = "raster") -> View:
     """Render view (ego, cam) of a scenegen.Scene-like object."""
     return render_view(scene.agent_state, scene.agent_dims, scene.agent_color, scene.road_xy,
                        scene.road_color, camera, palette, ego, camera.cam_dirs[cam], light, _statics(scene),
-                       _signals(scene))
+                       _signals(scene), backend)
 
 
 def render_views(items, camera, palette, threads: int = 1):

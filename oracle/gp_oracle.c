@@ -575,6 +575,59 @@ static uint32_t shade_level(const gpo_camera *cam, float nx, float ny, int face)
     return (uint32_t)fmaf(s, 255.0f, 0.5f);
 }
 
+/* Keys -> colour (lit as the camera says), depth 1/invz (+inf for
+ * background) and primitive index (-1), for one W x H view. */
+static void resolve_keys(const gpo_scene *sc, const gpo_camera *cam, const uint64_t *key_scratch, uint8_t *rgb,
+                         float *depth, int32_t *primid)
+{
+    const int W = cam->width, H = cam->height;
+    const uint32_t n_a = (uint32_t)sc->n_agents;
+    const uint32_t n_box = n_a + (uint32_t)sc->n_static;
+    const uint32_t sig0 = 6 * n_box + (uint32_t)sc->n_roads;
+    for (int p = 0; p < W * H; ++p) {
+        uint64_t key = key_scratch[p];
+        int32_t prim = -1;
+        uint8_t color = 0;
+        float dep = INFINITY;
+        if (key != 0) {
+            uint32_t zb = (uint32_t)(key >> 32);
+            float invz;
+            memcpy(&invz, &zb, 4);
+            prim = (int32_t)(0x7FFFFFFFu - (uint32_t)(key & 0x7FFFFFFFu));
+            const int32_t b = prim / 6;
+            color = prim >= (int32_t)sig0       ? sc->signal_color[prim - (int32_t)sig0]
+                    : prim >= (int32_t)(6 * n_box) ? sc->road_color[prim - 6 * (int32_t)n_box]
+                    : b < (int32_t)n_a            ? sc->agent_color[b]
+                                                  : sc->static_color[b - (int32_t)n_a];
+            dep = 1.0f / invz;
+        }
+        if (rgb) {
+            uint32_t q = 255;
+            if (cam->shade && prim >= 0 && prim < (int32_t)sig0) {     /* lights are emissive */
+                if (prim < (int32_t)(6 * n_box)) {
+                    const int32_t b = prim / 6;
+                    const float psi = b < (int32_t)n_a ? sc->agent_state[4 * b + 2]
+                                                       : sc->static_xyp[3 * (b - (int32_t)n_a) + 2];
+                    float sj, cj;
+                    gpo_sincos(psi, &sj, &cj);
+                    const int f = prim % 6;
+                    const float nx[4] = { cj, -sj, -cj, sj }, ny[4] = { sj, cj, -sj, -cj };
+                    q = shade_level(cam, f < 4 ? nx[f] : 0.0f, f < 4 ? ny[f] : 0.0f, f);
+                } else {
+                    q = shade_level(cam, 0.0f, 0.0f, 4);
+                }
+            }
+            for (int ch = 0; ch < 3; ++ch) {
+                uint32_t c = cam->palette[3 * color + ch];
+                rgb[3 * p + ch] = (uint8_t)(cam->shade && prim >= 0 && prim < (int32_t)sig0 ? (c * q + 127u) / 255u
+                                                                                            : c);
+            }
+        }
+        if (depth) depth[p] = dep;
+        if (primid) primid[p] = prim;
+    }
+}
+
 /* Render the view of agent `ego` through the camera whose yaw offset is
  * (ck, sk) = (cos, sin).  Outputs (any may be NULL): rgb [H][W][3], depth
  * [H][W] (1/invz, +inf for background), primid [H][W] (-1 for background).
@@ -657,53 +710,146 @@ long long gpo_render_view(const gpo_scene *sc, const gpo_camera *cam, int ego, f
         raster_sphere(&t, to_cam(&vw, q[0] - vw.px, q[1] - vw.py, q[2]), q[3], sig0 + (uint32_t)g);
     }
 
-    /* resolve */
-    for (int p = 0; p < W * H; ++p) {
-        uint64_t key = key_scratch[p];
-        int32_t prim = -1;
-        uint8_t color = 0;
-        float dep = INFINITY;
-        if (key != 0) {
-            uint32_t zb = (uint32_t)(key >> 32);
-            float invz;
-            memcpy(&invz, &zb, 4);
-            prim = (int32_t)(0x7FFFFFFFu - (uint32_t)(key & 0x7FFFFFFFu));
-            const int32_t b = prim / 6;
-            color = prim >= (int32_t)sig0       ? sc->signal_color[prim - (int32_t)sig0]
-                    : prim >= (int32_t)(6 * n_box) ? sc->road_color[prim - 6 * (int32_t)n_box]
-                    : b < (int32_t)n_a            ? sc->agent_color[b]
-                                                  : sc->static_color[b - (int32_t)n_a];
-            dep = 1.0f / invz;
-        }
-        if (rgb) {
-            uint32_t q = 255;
-            if (cam->shade && prim >= 0 && prim < (int32_t)sig0) {     /* lights are emissive */
-                if (prim < (int32_t)(6 * n_box)) {
-                    const int32_t b = prim / 6;
-                    const float psi = b < (int32_t)n_a ? sc->agent_state[4 * b + 2]
-                                                       : sc->static_xyp[3 * (b - (int32_t)n_a) + 2];
-                    float sj, cj;
-                    gpo_sincos(psi, &sj, &cj);
-                    const int f = prim % 6;
-                    const float nx[4] = { cj, -sj, -cj, sj }, ny[4] = { sj, cj, -sj, -cj };
-                    q = shade_level(cam, f < 4 ? nx[f] : 0.0f, f < 4 ? ny[f] : 0.0f, f);
-                } else {
-                    q = shade_level(cam, 0.0f, 0.0f, 4);
-                }
-            }
-            for (int ch = 0; ch < 3; ++ch) {
-                uint32_t c = cam->palette[3 * color + ch];
-                rgb[3 * p + ch] = (uint8_t)(cam->shade && prim >= 0 && prim < (int32_t)sig0 ? (c * q + 127u) / 255u
-                                                                                            : c);
-            }
-        }
-        if (depth) depth[p] = dep;
-        if (primid) primid[p] = prim;
-    }
+    resolve_keys(sc, cam, key_scratch, rgb, depth, primid);
     if (frags_out) *frags_out = t.frags;
     return ntri;
 }
 
+
+/* ------------------------------------------------------------ ray casting
+ * The paper's other backend (App. A: rasterised or ray-traced; the ray tracer
+ * is its default).  One primary ray per pixel sample, the same scene and the
+ * same winner order as the raster (largest key: 1/z, then class, then the
+ * lower primitive index), the same resolve.  Reading, binary32 with fmaf:
+ *   - camera at (px, py, h) with forward (fx, fy, 0), right (fy, -fx, 0) and
+ *     up (0, 0, 1); the sample of pixel (i, j) has offsets a = i + 0.5 - cx,
+ *     b = cy - (j + 0.5) and world direction
+ *       d = (fmaf(a, fy, f fx), fmaf(a, -fx, f fy), b);
+ *     a hit at parameter s has planar depth z = s f, kept in [z_near, z_far];
+ *   - box b (heading cos/sin (c, s) from the project's sincos, half length hl,
+ *     half width hw, height H): the ray in the box frame
+ *       o = (fmaf(ox, c, oy s), fmaf(oy, c, -(ox s)), h),  ox = px - x_b, oy = py - y_b,
+ *       e = (fmaf(dx, c, dy s), fmaf(dy, c, -(dx s)), b)
+ *     against the slabs [-hl, hl] x [-hw, hw] x [0, H]: per axis with e != 0
+ *     the entry (lo - o) / e or (hi - o) / e on the side the ray comes from,
+ *     with e = 0 the slab is all (-inf, inf) when lo < o < hi and empty
+ *     otherwise; the entry is the largest axis entry (the first axis on a
+ *     tie), its face the side entered (front / back on the first axis, left /
+ *     right on the second, top / bottom on the third); a hit needs
+ *     entry <= exit and entry > 0 (only rays that enter from outside: boxes
+ *     are one-sided);
+ *   - road strips (two-sided, z = 0): a downward ray (b < 0) meets the plane
+ *     at s = -h / b, point (fmaf(s, dx, px), fmaf(s, dy, py)); the strips
+ *     that hold the point strictly inside (all four edge cross products
+ *     fmaf(ex, wy, -(ey wx)) of one sign) are candidates, the lowest road
+ *     index wins (all share the depth);
+ *   - traffic lights: the sphere test of the raster (same arithmetic).
+ */
+static void cast_boxes(const gpo_scene *sc, const view_t *vw, int ego, uint64_t *keys)
+{
+    const uint32_t n_a = (uint32_t)sc->n_agents, n_box = n_a + (uint32_t)sc->n_static;
+    const float f = vw->f;
+    for (uint32_t bi = 0; bi < n_box; ++bi) {
+        if ((int)bi == ego) continue;
+        const int is_static = bi >= n_a;
+        const float *st = is_static ? sc->static_xyp + 3 * (bi - n_a) : sc->agent_state + 4 * bi;
+        const float *dm = is_static ? sc->static_dims + 3 * (bi - n_a) : sc->agent_dims + 3 * bi;
+        float sn, cs;
+        gpo_sincos(st[2], &sn, &cs);
+        const float ox = vw->px - st[0], oy = vw->py - st[1];
+        const float o[3] = { fmaf(ox, cs, oy * sn), fmaf(oy, cs, -(ox * sn)), vw->h };
+        const float lo[3] = { -(0.5f * dm[0]), -(0.5f * dm[1]), 0.0f };
+        const float hi[3] = { 0.5f * dm[0], 0.5f * dm[1], dm[2] };
+        const int face_lo[3] = { 2, 3, 5 }, face_hi[3] = { 0, 1, 4 };
+        for (int j = 0; j < vw->H; ++j) {
+            for (int i = 0; i < vw->W; ++i) {
+                const float a = ((float)i + 0.5f) - vw->cx;
+                const float b = vw->cy - ((float)j + 0.5f);
+                const float dx = fmaf(a, vw->fy, f * vw->fx), dy = fmaf(a, -vw->fx, f * vw->fy);
+                const float e[3] = { fmaf(dx, cs, dy * sn), fmaf(dy, cs, -(dx * sn)), b };
+                float t_in = -INFINITY, t_out = INFINITY;
+                int face = -1;
+                for (int k = 0; k < 3; ++k) {
+                    float en, lv;
+                    int fk;
+                    if (e[k] > 0.0f) {
+                        en = (lo[k] - o[k]) / e[k]; lv = (hi[k] - o[k]) / e[k]; fk = face_lo[k];
+                    } else if (e[k] < 0.0f) {
+                        en = (hi[k] - o[k]) / e[k]; lv = (lo[k] - o[k]) / e[k]; fk = face_hi[k];
+                    } else {
+                        const int in = lo[k] < o[k] && o[k] < hi[k];
+                        en = in ? -INFINITY : INFINITY; lv = in ? INFINITY : -INFINITY; fk = -1;
+                    }
+                    if (en > t_in) { t_in = en; face = fk; }
+                    if (lv < t_out) t_out = lv;
+                }
+                if (!(t_in <= t_out && t_in > 0.0f && t_in < INFINITY)) continue;
+                const float z = t_in * f;
+                if (!(z >= vw->z_near && z <= vw->z_far)) continue;
+                const float invz = 1.0f / z;
+                const uint32_t prim = 6 * bi + (uint32_t)face;
+                const uint64_t key = ((uint64_t)f32_bits(invz) << 32) | ((uint64_t)1u << 31)
+                                   | (uint64_t)(0x7FFFFFFFu - prim);
+                if (key > keys[j * vw->W + i]) keys[j * vw->W + i] = key;
+            }
+        }
+    }
+}
+
+static void cast_roads(const gpo_scene *sc, const view_t *vw, uint64_t *keys)
+{
+    const uint32_t n_box = (uint32_t)(sc->n_agents + sc->n_static);
+    const float f = vw->f;
+    for (int j = 0; j < vw->H; ++j) {
+        for (int i = 0; i < vw->W; ++i) {
+            const float a = ((float)i + 0.5f) - vw->cx;
+            const float b = vw->cy - ((float)j + 0.5f);
+            if (!(b < 0.0f)) continue;
+            const float dx = fmaf(a, vw->fy, f * vw->fx), dy = fmaf(a, -vw->fx, f * vw->fy);
+            const float s = -vw->h / b;
+            const float z = s * f;
+            if (!(z >= vw->z_near && z <= vw->z_far)) continue;
+            const float x = fmaf(s, dx, vw->px), y = fmaf(s, dy, vw->py);
+            int best = -1;
+            for (int r = 0; r < sc->n_roads && best < 0; ++r) {
+                const float *q = sc->road_xy + 8 * r;
+                int pos = 0, neg = 0;
+                for (int k = 0; k < 4; ++k) {
+                    const int k1 = (k + 1) & 3;
+                    const float ex = q[2 * k1] - q[2 * k], ey = q[2 * k1 + 1] - q[2 * k + 1];
+                    const float wx = x - q[2 * k], wy = y - q[2 * k + 1];
+                    const float c = fmaf(ex, wy, -(ey * wx));
+                    pos += c > 0.0f;
+                    neg += c < 0.0f;
+                }
+                if (pos == 4 || neg == 4) best = r;
+            }
+            if (best < 0) continue;
+            const float invz = 1.0f / z;
+            const uint32_t prim = 6 * n_box + (uint32_t)best;
+            const uint64_t key = ((uint64_t)f32_bits(invz) << 32) | (uint64_t)(0x7FFFFFFFu - prim);
+            if (key > keys[j * vw->W + i]) keys[j * vw->W + i] = key;
+        }
+    }
+}
+
+/* Ray-cast view of agent `ego` (outputs as gpo_render_view). */
+void gpo_raycast_view(const gpo_scene *sc, const gpo_camera *cam, int ego, float ck, float sk,
+                      uint64_t *key_scratch, uint8_t *rgb, float *depth, int32_t *primid)
+{
+    view_t vw;
+    make_view(&vw, sc, cam, ego, ck, sk);
+    for (int p = 0; p < vw.W * vw.H; ++p) key_scratch[p] = 0;
+    target_t t = { key_scratch, &vw, 0 };
+    cast_boxes(sc, &vw, ego, key_scratch);
+    cast_roads(sc, &vw, key_scratch);
+    const uint32_t sig0 = 6 * (uint32_t)(sc->n_agents + sc->n_static) + (uint32_t)sc->n_roads;
+    for (int g = 0; g < sc->n_signals; ++g) {
+        const float *q = sc->signal_xyzr + 4 * g;
+        raster_sphere(&t, to_cam(&vw, q[0] - vw.px, q[1] - vw.py, q[2]), q[3], sig0 + (uint32_t)g);
+    }
+    resolve_keys(sc, cam, key_scratch, rgb, depth, primid);
+}
 
 /* ----------------------------------------------------------- infractions
  * App. A ("halted in place ... continues to receive observations"): an agent
