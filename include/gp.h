@@ -147,6 +147,18 @@ gp_status gp_sim_step(gp_sim *sim, const float *d_actions, void *stream);
  * to the scene. */
 gp_status gp_sim_render(gp_sim *sim, uint8_t *d_rgb, float *d_depth, int32_t *d_primid, void *stream);
 
+/* Render every view with the ray-cast backend (App. A: the renderer can
+ * rasterise or ray-trace the same scene): one primary ray per pixel sample
+ * through the sample's centre; boxes by slab tests in each box's frame
+ * (entering hits only), road strips by the ray's ground point (strictly
+ * inside a strip; the lowest road index wins), traffic lights by the same
+ * sphere test as gp_sim_render; the same winner order (nearest, boxes and
+ * lights above roads on ties, then the lower primitive index), colours,
+ * light and outputs as gp_sim_render.  The images agree with the raster's
+ * except at primitive edges, where exact rays and snapped triangles can
+ * differ.  Arguments as gp_sim_render (rgb need not be 4-byte aligned). */
+gp_status gp_sim_render_raycast(gp_sim *sim, uint8_t *d_rgb, float *d_depth, int32_t *d_primid, void *stream);
+
 /* Step then render (rgb only) as one hipGraph replay.  The graph is captured
  * on first use and re-captured when a pointer or the launch settings change.
  * Uses the persistent schedule whatever the current launch setting. */

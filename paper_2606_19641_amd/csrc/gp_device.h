@@ -114,6 +114,9 @@ hipError_t launch_render(const DevSim &s, const RenderOut &o, const LaunchCfg &c
                          int persistent, int view_begin, int grid, hipStream_t st);
 size_t render_lds_bytes(const DevSim &s, const LaunchCfg &c, int fast);
 size_t render_lds_bytes(int width, int height, const LaunchCfg &c, int fast);
+// ray-cast backend (gp_raycast.hip): one workgroup per view of [view_begin, view_begin + n_views)
+hipError_t launch_raycast(const DevSim &s, const RenderOut &o, int view_begin, int n_views, hipStream_t st);
+size_t raycast_lds_bytes();
 // batched (serving) launches over a device table of sims
 hipError_t launch_step_multi(const SimEntry *tab, int n_sims, int max_agents, hipStream_t st);
 hipError_t launch_render_multi(const SimEntry *tab, const int2 *items, int n_items, uint32_t *ctl,

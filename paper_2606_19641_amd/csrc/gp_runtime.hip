@@ -783,6 +783,15 @@ gp_status gp_sim_set_light(gp_sim *sim, const float *h_light)
     return GP_OK;
 }
 
+gp_status gp_sim_render_raycast(gp_sim *sim, uint8_t *d_rgb, float *d_depth, int32_t *d_primid, void *stream)
+{
+    if (!sim || !d_rgb) return fail(GP_EINVAL, "NULL argument");
+    if (gp::raycast_lds_bytes() > sim->max_lds) return fail(GP_EINVAL, "ray caster needs more LDS than the device has");
+    gp::RenderOut o{d_rgb, d_depth, d_primid};
+    hipError_t e = gp::launch_raycast(sim->dev, o, 0, (int)sim->lay.n_views, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? GP_OK : hip_fail(e, "ray-cast launch");
+}
+
 gp_status gp_sim_set_signal_colors(gp_sim *sim, const uint8_t *d_colors, void *stream)
 {
     if (!sim || !d_colors) return fail(GP_EINVAL, "NULL argument");

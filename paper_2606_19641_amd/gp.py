@@ -24,7 +24,8 @@ EXPORTS = ("gp_sim_required_bytes", "gp_sim_create", "gp_sim_set_launch", "gp_si
            "gp_sim_set_state", "gp_sim_num_views", "gp_sim_num_agents", "gp_sim_num_scenes",
            "gp_sim_destroy", "gp_last_error", "gp_batch_required_bytes", "gp_batch_step_render",
            "gp_sim_check_infractions", "gp_sim_fork", "gp_sim_step_jerk", "gp_sim_get_actuators",
-           "gp_sim_set_light", "gp_sim_set_signal_colors", "gp_sim_num_signals")
+           "gp_sim_set_light", "gp_sim_set_signal_colors", "gp_sim_num_signals",
+           "gp_sim_render_raycast")
 
 
 class GpError(RuntimeError):
@@ -99,11 +100,13 @@ def lib() -> C.CDLL:
         L.gp_sim_get_actuators.argtypes = [vp, vp, vp]
         L.gp_sim_set_light.argtypes = [vp, vp]
         L.gp_sim_set_signal_colors.argtypes = [vp, vp, vp]
+        L.gp_sim_render_raycast.argtypes = [vp, vp, vp, vp, vp]
         L.gp_sim_num_signals.argtypes = [vp]
         L.gp_sim_num_signals.restype = C.c_int64
         for name in ("gp_sim_check_infractions", "gp_sim_fork", "gp_sim_step_jerk", "gp_sim_get_actuators",
-                     "gp_sim_set_light", "gp_sim_set_signal_colors", "gp_batch_step_render", "gp_sim_create", "gp_sim_set_launch", "gp_sim_get_launch", "gp_sim_step",
-                     "gp_sim_render", "gp_sim_step_render_graph", "gp_sim_get_state",
+                     "gp_sim_set_light", "gp_sim_set_signal_colors", "gp_sim_render_raycast",
+                     "gp_batch_step_render", "gp_sim_create", "gp_sim_set_launch", "gp_sim_get_launch",
+                     "gp_sim_step", "gp_sim_render", "gp_sim_step_render_graph", "gp_sim_get_state",
                      "gp_sim_set_state"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -266,6 +269,18 @@ class Sim:
         """colors: uint8 [n_signals] device tensor, the palette index of every light's state."""
         self._check_tensor(colors, (self.n_signals,), "uint8")
         _check(lib().gp_sim_set_signal_colors(self._h, colors.data_ptr(), _stream_handle(stream)))
+
+    def render_raycast(self, rgb=None, depth=False, primid=False, stream=None):
+        """Render every view with the ray-cast backend; returns (rgb, depth or None, primid or None)."""
+        import torch
+        rgb = self.new_rgb() if rgb is None else rgb
+        self._check_tensor(rgb, (self.n_views, self.camera.height, self.camera.width, 3), "uint8")
+        shp = (self.n_views, self.camera.height, self.camera.width)
+        d = torch.empty(shp, dtype=torch.float32, device=self.device) if depth is True else (depth or None)
+        p = torch.empty(shp, dtype=torch.int32, device=self.device) if primid is True else (primid or None)
+        _check(lib().gp_sim_render_raycast(self._h, rgb.data_ptr(), d.data_ptr() if d is not None else None,
+                                           p.data_ptr() if p is not None else None, _stream_handle(stream)))
+        return rgb, d, p
 
     def set_light(self, light=None):
         """light = (lx, ly, lz, ambient): unit direction towards the light (world
