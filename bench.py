@@ -337,6 +337,21 @@ def main():
     infr_ms = float(np.mean([a.elapsed_time(b) for a, b in iev]))
     sim.set_state(state0)               # the check halted offenders: restore the state
 
+    # ---- the ray-cast backend on the same state (same images up to edge pixels),
+    # timed apart: the raster is the measured path
+    rc_rgb = sim.new_rgb()
+    sim.render_raycast(rgb=rc_rgb)
+    rev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
+    torch.cuda.synchronize()
+    torch.cuda._sleep(1_000_000)
+    for a, b in rev:
+        a.record(stream)
+        sim.render_raycast(rgb=rc_rgb)
+        b.record(stream)
+    torch.cuda.synchronize()
+    raycast_ms = float(np.mean([a.elapsed_time(b) for a, b in rev]))
+    del rc_rgb
+
     # ---- plain: per-scene launches of the same kernels, no graph
     plain = None
     if not args.no_plain:
@@ -391,6 +406,7 @@ def main():
         "p99_step_ms": float(np.percentile(lat_ms, 99)),
         "render_kernel_ms": render_ms,
         "infraction_check_ms": infr_ms,
+        "raycast_render_ms": raycast_ms,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": meas["traffic"] if meas else None,
                      "kernel": "k_render", "bytes_per_launch": rb,
