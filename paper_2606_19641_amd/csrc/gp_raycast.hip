@@ -39,7 +39,8 @@ namespace {
 
 constexpr int kRcThreads = 256;
 constexpr int kRcBandPixels = 4096;
-constexpr int kRcStageWords = 8;          // words per staged record
+constexpr int kRcRoadPixels = 512;        // pixels of a road sub-band
+constexpr int kRcStageWords = 10;         // words per staged record
 
 #define GP_RC_LDS __attribute__((address_space(3)))
 
@@ -127,6 +128,7 @@ __global__ __launch_bounds__(kRcThreads) void k_raycast(DevSim s, RenderOut o, i
                  ((uint32_t)s.palette[3 * p + 2] << 16);
     const int W = cam.W, H = cam.H;
     const int rows = max(1, kRcBandPixels / W);
+    const int rrows = max(1, kRcRoadPixels / W);      // rows of a road sub-band
     const int64_t img0 = (int64_t)view * W * H;
     const int sig0 = 6 * n_box + sc.n_roads;
     for (int j0 = 0; j0 < H; j0 += rows) {
@@ -145,11 +147,43 @@ __global__ __launch_bounds__(kRcThreads) void k_raycast(DevSim s, RenderOut o, i
                 const float4 dm = s.dims[g];
                 const float ox = st.x - cam.px, oy = st.y - cam.py;
                 const float z = fmaf(ox, cam.fx, oy * cam.fy), x = fmaf(ox, cam.fy, -(oy * cam.fx));
-                const float R = 0.5f * (dm.x + dm.y) + dm.z + 1e-3f;      // >= the box's reach from its centre
+                const float R = 0.5f * (dm.x + dm.y) + 1e-3f;      // bounds the footprint's reach from its centre
                 const bool keep = !(z + R < cam.zn) && !(z - R > cam.zf) && !(fabsf(x) - R > (z + R) * cam.tx);
                 if (keep) {
                     const int q = __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     const float2 cs = s.cs[g];
+                    // pixel rectangle that holds every sample whose ray can hit the
+                    // box: with every corner in front of the camera, the box's
+                    // image is the hull of its corners' images (a pixel of margin
+                    // for rounding); otherwise the whole image
+                    int i0 = 0, i1 = cam.W - 1, jr0 = 0, jr1 = cam.H - 1;
+                    {
+                        const float ax = 0.5f * dm.x * cs.x, ay = 0.5f * dm.x * cs.y;
+                        const float bx = -(0.5f * dm.y * cs.y), by = 0.5f * dm.y * cs.x;
+                        float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY, zmin = INFINITY;
+#pragma unroll
+                        for (int c4 = 0; c4 < 4; ++c4) {
+                            const float sa = (c4 & 1) ? -1.0f : 1.0f, sb = (c4 & 2) ? -1.0f : 1.0f;
+                            const float wx = ox + sa * ax + sb * bx, wy = oy + sa * ay + sb * by;
+                            const float zc = fmaf(wx, cam.fx, wy * cam.fy), xc = fmaf(wx, cam.fy, -(wy * cam.fx));
+                            zmin = fminf(zmin, zc);
+                            const float iz = 1.0f / zc;
+                            const float u = fmaf(cam.f * xc, iz, cam.cx);
+                            const float v0 = fmaf(-cam.f * (0.0f - cam.h), iz, cam.cy), v1 = fmaf(-cam.f * (dm.z - cam.h), iz, cam.cy);
+                            umin = fminf(umin, u);
+                            umax = fmaxf(umax, u);
+                            vmin = fminf(vmin, fminf(v0, v1));
+                            vmax = fmaxf(vmax, fmaxf(v0, v1));
+                        }
+                        if (zmin > 0.05f) {
+                            i0 = max(0, (int)fminf(fmaxf(floorf(umin - 0.5f) - 1.0f, -1.0f), (float)cam.W));
+                            i1 = min(cam.W - 1, (int)fminf(fmaxf(ceilf(umax - 0.5f) + 1.0f, -1.0f), (float)cam.W));
+                            jr0 = max(0, (int)fminf(fmaxf(floorf(vmin - 0.5f) - 1.0f, -1.0f), (float)cam.H));
+                            jr1 = min(cam.H - 1, (int)fminf(fmaxf(ceilf(vmax - 0.5f) + 1.0f, -1.0f), (float)cam.H));
+                        }
+                    }
+                    istg[8 * B + q] = i0 | (jr0 << 16);
+                    istg[9 * B + q] = i1 | (jr1 << 16);
                     stg[0 * B + q] = st.x;
                     stg[1 * B + q] = st.y;
                     stg[2 * B + q] = cs.x;
@@ -168,6 +202,8 @@ __global__ __launch_bounds__(kRcThreads) void k_raycast(DevSim s, RenderOut o, i
                 rc_sample(cam, i, j, a, b, dx, dy);
                 unsigned long long best = keys[p];
                 for (int r = 0; r < nb; ++r) {
+                    const int lo = istg[8 * B + r], hi = istg[9 * B + r];
+                    if (i < (lo & 0xFFFF) || j < (lo >> 16) || i > (hi & 0xFFFF) || j > (hi >> 16)) continue;
                     const float bxr = stg[r], byr = stg[B + r], cb = stg[2 * B + r], sb = stg[3 * B + r];
                     const float hl = stg[4 * B + r], hw = stg[5 * B + r], Hb = stg[6 * B + r];
                     const int tag = istg[7 * B + r];
@@ -215,79 +251,91 @@ __global__ __launch_bounds__(kRcThreads) void k_raycast(DevSim s, RenderOut o, i
             }
         }
 
-        // ---- road strips by culling bin: the ground point of each pixel
-        for (int u0 = 0; u0 < sc.n_bins; u0 += B) {
-            __syncthreads();
-            if (tid == 0) cnt[0] = 0;
-            __syncthreads();
-            const int u = u0 + tid;
-            if (u < sc.n_bins) {
-                const RoadBin bn = s.bins[sc.bin_base + u];
-                // ground points a sample can show lie at depth [zn, zf] inside the
-                // horizontal frustum; reject bins whose corners are all out on one side
-                const float xs[4] = {bn.xmin, bn.xmax, bn.xmax, bn.xmin}, ys[4] = {bn.ymin, bn.ymin, bn.ymax, bn.ymax};
-                bool nz = true, fz = true, lft = true, rgt = true;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const float ox = xs[q] - cam.px, oy = ys[q] - cam.py;
-                    const float z = fmaf(ox, cam.fx, oy * cam.fy), x = fmaf(ox, cam.fy, -(oy * cam.fx));
-                    const float m = 1e-3f * (fabsf(x) + fabsf(z)) + 1e-3f;
-                    nz = nz && (z < cam.zn - m);
-                    fz = fz && (z > cam.zf + m);
-                    rgt = rgt && (x - cam.tx * z > m);
-                    lft = lft && (-x - cam.tx * z > m);
-                }
-                if (!(nz || fz || lft || rgt)) {
-                    const int q = __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    stg[0 * B + q] = bn.xmin - 1e-2f;
-                    stg[1 * B + q] = bn.ymin - 1e-2f;
-                    stg[2 * B + q] = bn.xmax + 1e-2f;
-                    stg[3 * B + q] = bn.ymax + 1e-2f;
-                    istg[4 * B + q] = bn.start;
-                    istg[5 * B + q] = bn.count;
-                }
-            }
-            __syncthreads();
-            const int nb = cnt[0];
-            if (nb == 0) continue;
-            for (int p = tid; p < npix; p += B) {
-                const int j = j0 + p / W, i = p - (p / W) * W;
-                float a, b, dx, dy;
-                rc_sample(cam, i, j, a, b, dx, dy);
-                if (!(b < 0.0f)) continue;
-                const float sp = -cam.h / b;
-                const float z = sp * cam.f;
-                if (!(z >= cam.zn && z <= cam.zf)) continue;
-                const float x = fmaf(sp, dx, cam.px), y = fmaf(sp, dy, cam.py);
-                int best_r = INT32_MAX, best_slot = -1;
-                for (int r = 0; r < nb; ++r) {
-                    if (x < stg[r] || y < stg[B + r] || x > stg[2 * B + r] || y > stg[3 * B + r]) continue;
-                    const int st0 = istg[4 * B + r], n = istg[5 * B + r];
-                    for (int q = 0; q < n; ++q) {
-                        const int g = sc.road_base + st0 + q;
-                        const float4 q0 = s.roads[2 * g], q1 = s.roads[2 * g + 1];
-                        const float qx[4] = {q0.x, q0.z, q1.x, q1.z}, qy[4] = {q0.y, q0.w, q1.y, q1.w};
-                        int pos = 0, neg = 0;
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            const int e1 = (e + 1) & 3;
-                            const float ex = qx[e1] - qx[e], ey = qy[e1] - qy[e];
-                            const float wx = x - qx[e], wy = y - qy[e];
-                            const float c = fmaf(ex, wy, -(ey * wx));
-                            pos += c > 0.0f;
-                            neg += c < 0.0f;
-                        }
-                        const int ri = s.road_index[g];
-                        if ((pos == 4 || neg == 4) && ri < best_r) {
-                            best_r = ri;
-                            best_slot = g;
-                        }
+        // ---- road strips by culling bin: the ground point of each pixel, in
+        // sub-bands of rows.  A row's ground points share the depth -h f / b,
+        // so a sub-band sees the ground only between the depths of its lowest
+        // row and of its highest row below the horizon; bins outside that
+        // range are culled as well
+        for (int r0 = j0; r0 < j1; r0 += rrows) {
+            const int r1 = min(j1, r0 + rrows);
+            const float b_low = cam.cy - ((float)(r1 - 1) + 0.5f);
+            const int j_top = max(r0, (int)floorf(cam.cy - 0.5f) + 1);
+            const float b_top = cam.cy - ((float)j_top + 0.5f);
+            const float gz_lo = b_low < 0.0f ? fmaxf(cam.zn, -(cam.h * cam.f) / b_low) : cam.zf;
+            const float gz_hi = b_top < 0.0f ? fminf(cam.zf, -(cam.h * cam.f) / b_top) : cam.zf;
+            for (int u0 = 0; b_low < 0.0f && u0 < sc.n_bins; u0 += B) {
+                __syncthreads();
+                if (tid == 0) cnt[0] = 0;
+                __syncthreads();
+                const int u = u0 + tid;
+                if (u < sc.n_bins) {
+                    const RoadBin bn = s.bins[sc.bin_base + u];
+                    // ground points a sample can show lie at depth [zn, zf] inside the
+                    // horizontal frustum; reject bins whose corners are all out on one side
+                    const float xs[4] = {bn.xmin, bn.xmax, bn.xmax, bn.xmin}, ys[4] = {bn.ymin, bn.ymin, bn.ymax, bn.ymax};
+                    bool nz = true, fz = true, lft = true, rgt = true;
+    #pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const float ox = xs[q] - cam.px, oy = ys[q] - cam.py;
+                        const float z = fmaf(ox, cam.fx, oy * cam.fy), x = fmaf(ox, cam.fy, -(oy * cam.fx));
+                        const float m = 1e-3f * (fabsf(x) + fabsf(z)) + 1e-3f;
+                        nz = nz && (z < gz_lo - m);
+                        fz = fz && (z > gz_hi + m);
+                        rgt = rgt && (x - cam.tx * z > m);
+                        lft = lft && (-x - cam.tx * z > m);
+                    }
+                    if (!(nz || fz || lft || rgt)) {
+                        const int q = __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        stg[0 * B + q] = bn.xmin - 1e-2f;
+                        stg[1 * B + q] = bn.ymin - 1e-2f;
+                        stg[2 * B + q] = bn.xmax + 1e-2f;
+                        stg[3 * B + q] = bn.ymax + 1e-2f;
+                        istg[4 * B + q] = bn.start;
+                        istg[5 * B + q] = bn.count;
                     }
                 }
-                if (best_slot >= 0) {
-                    const unsigned long long key =
-                        make_key(1.0f / z, key_word(0u, 6 * n_box + best_r, s.road_color[best_slot]));
-                    if (key > keys[p]) keys[p] = key;
+                __syncthreads();
+                const int nb = cnt[0];
+                if (nb == 0) continue;
+                for (int p = (r0 - j0) * W + tid; p < (r1 - j0) * W; p += B) {
+                    const int j = j0 + p / W, i = p - (p / W) * W;
+                    float a, b, dx, dy;
+                    rc_sample(cam, i, j, a, b, dx, dy);
+                    if (!(b < 0.0f)) continue;
+                    const float sp = -cam.h / b;
+                    const float z = sp * cam.f;
+                    if (!(z >= cam.zn && z <= cam.zf)) continue;
+                    const float x = fmaf(sp, dx, cam.px), y = fmaf(sp, dy, cam.py);
+                    int best_r = INT32_MAX, best_slot = -1;
+                    for (int r = 0; r < nb; ++r) {
+                        if (x < stg[r] || y < stg[B + r] || x > stg[2 * B + r] || y > stg[3 * B + r]) continue;
+                        const int st0 = istg[4 * B + r], n = istg[5 * B + r];
+                        for (int q = 0; q < n; ++q) {
+                            const int g = sc.road_base + st0 + q;
+                            const float4 q0 = s.roads[2 * g], q1 = s.roads[2 * g + 1];
+                            const float qx[4] = {q0.x, q0.z, q1.x, q1.z}, qy[4] = {q0.y, q0.w, q1.y, q1.w};
+                            int pos = 0, neg = 0;
+    #pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                const int e1 = (e + 1) & 3;
+                                const float ex = qx[e1] - qx[e], ey = qy[e1] - qy[e];
+                                const float wx = x - qx[e], wy = y - qy[e];
+                                const float c = fmaf(ex, wy, -(ey * wx));
+                                pos += c > 0.0f;
+                                neg += c < 0.0f;
+                            }
+                            const int ri = s.road_index[g];
+                            if ((pos == 4 || neg == 4) && ri < best_r) {
+                                best_r = ri;
+                                best_slot = g;
+                            }
+                        }
+                    }
+                    if (best_slot >= 0) {
+                        const unsigned long long key =
+                            make_key(1.0f / z, key_word(0u, 6 * n_box + best_r, s.road_color[best_slot]));
+                        if (key > keys[p]) keys[p] = key;
+                    }
                 }
             }
         }
