@@ -44,3 +44,27 @@ def test_last_error_is_callable_without_gpu():
     # a NULL config is rejected on the host before any device call
     assert L.gp_sim_required_bytes(None, None, 1) == -1
     assert b"cfg" in L.gp_last_error()
+
+
+def test_bad_obstacles_and_lights_are_rejected_on_the_host():
+    """Input checks run before any device call (gp_sim_required_bytes)."""
+    import numpy as np
+    from paper_2606_19641_amd import gp, scenegen as g
+    if not os.path.exists(gp.LIB_PATH):
+        pytest.skip("library not built")
+    cam, pal = g.camera_for(32), g.default_palette()
+    sc = g.make_scene(0x5EED0002, 1, 6, 120, n_static=40, n_signals=30)
+    base = gp.required_bytes([sc], cam, pal)
+    plain = gp.required_bytes([g.make_scene(0x5EED0002, 1, 6, 120)], cam, pal)
+    assert base > plain                          # obstacles and lights take workspace
+    for field, idx, bad in (("static_xyp", (1, 0), np.inf), ("static_dims", (2, 1), np.nan),
+                            ("signal_xyzr", (0, 3), 0.0), ("signal_xyzr", (1, 3), -0.2),
+                            ("signal_xyzr", (2, 1), np.nan)):
+        b = g.make_scene(0x5EED0002, 1, 6, 120, n_static=4, n_signals=3)
+        getattr(b, field)[idx] = bad
+        with pytest.raises(gp.GpError):
+            gp.required_bytes([b], cam, pal)
+    b = g.make_scene(0x5EED0002, 1, 6, 120, n_static=4)
+    b.static_color = b.static_color[:2]          # shapes disagree: refused by the binding
+    with pytest.raises(ValueError):
+        gp.required_bytes([b], cam, pal)
