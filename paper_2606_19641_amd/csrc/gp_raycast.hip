@@ -23,11 +23,13 @@
 //   lights   the raster's sphere test in camera space
 //
 // Layout: one workgroup of 256 threads per view; the view is processed in
-// bands of about 4096 pixels whose keys live in LDS, each thread owning the
-// same pixels of a band throughout (no atomics).  Boxes, road bins and
+// bands of about 4096 pixels whose keys live in LDS; between two barriers
+// each key is updated by one thread only (no atomics).  Boxes, road bins and
 // lights are culled against the view frustum in chunks of up to 256 and the
 // survivors staged in LDS; every pixel of the band then tests the staged
-// records.  Colours come from the keys as in the raster's general kernel.
+// records (boxes only where their image rectangle holds the pixel, road bins
+// per sub-band of rows by the ground depths the rows see).  Colours come
+// from the keys as in the raster's general kernel.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
