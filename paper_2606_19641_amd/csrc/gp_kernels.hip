@@ -1376,13 +1376,6 @@ __device__ __forceinline__ void clear_band(Lds &L, int npix)
     for (int p = threadIdx.x; p < npix; p += blockDim.x) L.zb[p] = 0ull;
 }
 
-// rgb kernel: rows [r0, r1) from the road coverage bits and, with keys, the
-// box key band whose first row is zb0.
-//
-// Every road strip shares the depth plane (A, B, C) with A = +-0, so the road
-// 1/z of pixel (i, j) is fma(A, du, y) = y for y = fma(B, dv, C) != 0: one
-// value per row, positive exactly below the horizon.  A box fragment beats
-// the road where its 1/z is not smaller (agents rank above roads on ties).
 // ------------------------------------------------------------ shading
 //
 // App. A: one directional light per world, a colour per instance.  With the
@@ -1424,6 +1417,14 @@ __device__ __forceinline__ uint32_t lit_box(const DevSim &s, const SceneRec &sc,
     const float ny = f == 0 ? cs.y : f == 1 ? cs.x : f == 2 ? -cs.y : -cs.x;
     return shade_rgb(c, shade_level(s, nx, ny, f));
 }
+
+// rgb kernel: rows [r0, r1) from the road coverage bits and, with keys, the
+// box key band whose first row is zb0.
+//
+// Every road strip shares the depth plane (A, B, C) with A = +-0, so the road
+// 1/z of pixel (i, j) is fma(A, du, y) = y for y = fma(B, dv, C) != 0: one
+// value per row, positive exactly below the horizon.  A box fragment beats
+// the road where its 1/z is not smaller (agents rank above roads on ties).
 
 // colour of a pixel of the rgb kernel: a box fragment wins where its 1/z is
 // not below the road's (agents rank above roads on ties); else road or
