@@ -144,3 +144,29 @@ def test_bad_lights_are_refused():
     sim = gp.Sim([sc], g.camera_for(32), g.default_palette())
     with pytest.raises(ValueError):
         sim.set_signal_colors(torch.zeros(sc.n_signals + 1, dtype=torch.uint8, device="cuda"))
+
+
+def test_graph_replays_with_lights_and_state_changes():
+    """step + render captured once as a graph on a sim with lights (the
+    general kernel's lights instances): replays follow light-state changes and
+    equal the eager step + render."""
+    from paper_2606_19641_amd import gp
+    scenes = _scenes()
+    cam = g.camera_for(48)
+    pal = g.default_palette()
+    a, b = gp.Sim(scenes, cam, pal), gp.Sim(scenes, cam, pal)
+    ra, rb = a.new_rgb(), b.new_rgb()
+    act = torch.empty((a.n_agents, 2), dtype=torch.float32, device="cuda")
+    colors = np.concatenate([s.signal_color for s in scenes])
+    for k in range(4):
+        act.copy_(torch.from_numpy(g.batch_actions(0xB0B, k, scenes)))
+        colors = np.roll(colors, 3)
+        c = torch.from_numpy(colors).cuda()
+        a.set_signal_colors(c)
+        b.set_signal_colors(c)
+        a.step_render_graph(act, ra)
+        b.step(act)
+        b.render(rgb=rb)
+        torch.cuda.synchronize()
+        assert torch.equal(a.get_state(), b.get_state()), k
+        assert torch.equal(ra, rb), k
