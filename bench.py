@@ -379,6 +379,14 @@ def main():
 
     rb = render_bytes(w)
     achieved = rb / (render_ms * 1e-3) / 1e9
+    # the render kernel's work rates: pixel samples resolved, and primitives
+    # considered before culling (every view: the other boxes' 6 faces, the
+    # obstacles' faces, every road strip and light of its scene)
+    cams = len(w.camera.cam_dirs)
+    prims = sum(s.n_agents * cams * (6 * (s.n_agents - 1 + getattr(s, "n_static", 0)) + s.n_roads
+                                     + getattr(s, "n_signals", 0)) for s in w.scenes)
+    rates = {"pixels_per_s": V * w.camera.width * w.camera.height / (render_ms * 1e-3),
+             "primitives_per_s": prims / (render_ms * 1e-3), "primitives_per_step": prims}
     meas = measured_counters(args.workload if args.workload != "sweep" else f"sweep{args.res}", launch)
     cpu = None
     if not args.no_cpu_baseline:
@@ -407,6 +415,7 @@ def main():
         "render_kernel_ms": render_ms,
         "infraction_check_ms": infr_ms,
         "raycast_render_ms": raycast_ms,
+        "render_rates": rates,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": meas["traffic"] if meas else None,
                      "kernel": "k_render", "bytes_per_launch": rb,
