@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+VALU_PEAK = 256 * 64 * 2.4e9          # vector lane-ops/s: 256 CUs, 4 SIMDs x 16 lanes, 2.4 GHz
 METRIC = "agent-views/sec at 128×128 RGB (batched vs plain, same GPU); p99 step latency"
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 256 << 20
@@ -57,7 +58,8 @@ def measured_counters(workload_name: str, launch: dict):
             return None
         return {"traffic": float(kv["traffic_bytes_per_launch"]),
                 "valu_busy_pct": float(kv["valu_busy_pct"]),
-                "lds_bank_conflict_pct": float(kv["lds_bank_conflict_pct"])}
+                "lds_bank_conflict_pct": float(kv["lds_bank_conflict_pct"]),
+                "valu_insts": float(kv["valu_insts_per_launch"])}
     except (KeyError, ValueError):
         return None
 
@@ -238,11 +240,14 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
+    # the GPU needs about 0.1 s of steady work to reach its full clocks: 1,000
+    # warm-up steps (~0.1 s) before the timed ones
+    ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--workload", default="uniform",
                     choices=["small", "uniform", "uneven", "sweep", "serve", "student"])
     ap.add_argument("--res", type=int, default=128)
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--lat-steps", type=int, default=1000, help="graph replays sampled for the latency percentiles")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--tuned", default="", help="launch settings JSON (skips the autotuner)")
@@ -288,27 +293,41 @@ def main():
     launch["sched"] = gp.SCHED_PERSISTENT
     sim.set_launch(**launch)
     V = sim.n_views
-    acts = torch.from_numpy(np.stack([g.batch_actions(w.seed, k, w.scenes) for k in range(K + W)])).to(dev)
+    # warm-up steps reuse a pool of at most 32 action sets in turn; the timed
+    # steps get their own
+    PW = max(1, min(W, 32))
+    acts = torch.from_numpy(np.stack([g.batch_actions(w.seed, k, w.scenes) for k in range(PW + K)])).to(dev)
     act_buf = torch.empty_like(acts[0])
     rgb = sim.new_rgb()
     stream = torch.cuda.current_stream()
 
     # ---- batched: step + persistent render as one graph replay per step
     for k in range(W):
-        act_buf.copy_(acts[k])
+        act_buf.copy_(acts[k % PW])
         sim.step_render_graph(act_buf, rgb)
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
     t0 = time.perf_counter()
     for k in range(K):
         ev[k][0].record(stream)
-        act_buf.copy_(acts[W + k])
+        act_buf.copy_(acts[PW + k])
         sim.step_render_graph(act_buf, rgb)
         ev[k][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    lat_ms = np.array([a.elapsed_time(b) for a, b in ev])
     batched = V * K / wall
+
+    # ---- step latency: its own run of lat_steps graph replays (actions reused in
+    # turn), one event pair each, for the p50 / p99
+    n_lat = max(args.lat_steps, 1)
+    lev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_lat)]
+    for k in range(n_lat):
+        lev[k][0].record(stream)
+        act_buf.copy_(acts[k % (PW + K)])
+        sim.step_render_graph(act_buf, rgb)
+        lev[k][1].record(stream)
+    torch.cuda.synchronize()
+    lat_ms = np.array([a.elapsed_time(b) for a, b in lev])
 
     # ---- the render kernel alone (eager, persistent), events on its stream; a
     # short spin kernel first lets the launches queue up, so host launch gaps
@@ -356,13 +375,13 @@ def main():
     plain = None
     if not args.no_plain:
         sim.set_launch(sched=gp.SCHED_PLAIN)
-        for k in range(W):
-            sim.step(acts[k])
+        for k in range(min(W, 20)):         # the clocks are up by now
+            sim.step(acts[k % PW])
             sim.render(rgb=rgb)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for k in range(K):
-            sim.step(acts[W + k])
+            sim.step(acts[PW + k])
             sim.render(rgb=rgb)
         torch.cuda.synchronize()
         plain = V * K / (time.perf_counter() - t1)
@@ -412,6 +431,7 @@ def main():
         "batched_over_plain": (batched / plain) if plain else None,
         "p50_step_ms": float(np.percentile(lat_ms, 50)),
         "p99_step_ms": float(np.percentile(lat_ms, 99)),
+        "latency_samples": int(n_lat),
         "render_kernel_ms": render_ms,
         "infraction_check_ms": infr_ms,
         "raycast_render_ms": raycast_ms,
@@ -421,6 +441,11 @@ def main():
                      "kernel": "k_render", "bytes_per_launch": rb,
                      "valu_busy_pct": meas["valu_busy_pct"] if meas else None,
                      "lds_bank_conflict_pct": meas["lds_bank_conflict_pct"] if meas else None},
+        # the plain VALU roof beside the HBM one: wave instructions x 64 lanes
+        # over the kernel time, against 256 CUs x 64 lanes x 2.4 GHz
+        "valu_roof": ({"achieved": meas["valu_insts"] * 64 / (render_ms * 1e-3), "peak": VALU_PEAK,
+                       "unit": "lane-ops/s", "frac": meas["valu_insts"] * 64 / (render_ms * 1e-3) / VALU_PEAK}
+                      if meas else None),
         "cpu_baseline": cpu,
         "paper_context": "~50k agent steps/s from pixels on 1 NVIDIA A100L (workload not stated)",
     }
