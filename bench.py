@@ -306,13 +306,10 @@ def main():
         act_buf.copy_(acts[k % PW])
         sim.step_render_graph(act_buf, rgb)
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
     t0 = time.perf_counter()
     for k in range(K):
-        ev[k][0].record(stream)
         act_buf.copy_(acts[PW + k])
         sim.step_render_graph(act_buf, rgb)
-        ev[k][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     batched = V * K / wall
