@@ -377,6 +377,12 @@ def test_uneven_full_size_graph_sampled():
         si = int(rng.integers(256))
         picks.append((si, int(rng.integers(w.scenes[si].n_agents)), int(rng.integers(3))))
     _compare_views(hs, w.camera, pal, rgb.cpu().numpy(), None, None, picks)
+    # the launch the bench's tuner picks for this workload: the same bits
+    tuned = sim.new_rgb()
+    sim.set_launch(band_rows=16, batch_tris=512, block_threads=256, blocks_per_cu=3)
+    sim.render(rgb=tuned)
+    torch.cuda.synchronize()
+    assert torch.equal(tuned, rgb)
 
 
 def test_state_save_restore_reproduces_images():
