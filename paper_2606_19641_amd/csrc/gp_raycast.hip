@@ -51,7 +51,11 @@ struct RcCam {
     int W, H;
 };
 
-__device__ __forceinline__ float ufl(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+// a value that is the same in every lane, kept in a scalar register
+__device__ __forceinline__ float uniform_float(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
 
 __device__ __forceinline__ uint32_t key_word(uint32_t cls, int prim, uint32_t color)
 {
@@ -111,10 +115,10 @@ __global__ __launch_bounds__(kRcThreads) void k_raycast(DevSim s, RenderOut o, i
         const float4 st = s.state[ga];
         const float2 cs = s.cs[ga];
         const float ck = s.cam_dir[k][0], sk = s.cam_dir[k][1];
-        cam.px = ufl(st.x);
-        cam.py = ufl(st.y);
-        cam.fx = ufl(fmaf(cs.x, ck, -(cs.y * sk)));
-        cam.fy = ufl(fmaf(cs.y, ck, cs.x * sk));
+        cam.px = uniform_float(st.x);
+        cam.py = uniform_float(st.y);
+        cam.fx = uniform_float(fmaf(cs.x, ck, -(cs.y * sk)));
+        cam.fy = uniform_float(fmaf(cs.y, ck, cs.x * sk));
         cam.h = s.cam_height;
         cam.f = s.focal;
         cam.W = s.width;
