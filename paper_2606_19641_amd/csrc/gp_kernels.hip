@@ -1140,21 +1140,32 @@ __device__ __forceinline__ V3 shfl_v3(const V3 &v, int src)
     return r;
 }
 
-// Every lane of the wave calls this with the same candidate.
-__device__ __forceinline__ void clip_wave(const Cam &cam, const Poly &P, const Sink &K, Lds &L)
+// Each 16-lane segment of the wave clips its own candidate (lane k of a
+// segment holds vertex k; a clip never has more than kMaxVerts = 12
+// vertices), so a wave clips four candidates at a time.  Within a segment the
+// walk is the sequential one: per plane each lane emits its vertex if inside
+// and the crossing of its edge if the edge crosses, the outputs placed by a
+// prefix over the segment's part of the ballots, which keeps the sequential
+// walk's vertex order and arithmetic exactly.  A segment whose vertices are
+// all inside a plane keeps its polygon unchanged (the same outputs).  live:
+// the segment has a candidate; road: the pass emits road strips (uniform).
+constexpr int kClipSeg = 16;
+static_assert(kMaxVerts <= kClipSeg, "a clipped polygon fits a segment");
+
+__device__ __forceinline__ void clip_wave(const Cam &cam, const Poly &P, bool live, bool road, const Sink &K, Lds &L)
 {
-    const float d = plane_d(P.n, P.v[0]);
-    if (P.one_sided && !(d < 0.0f)) return;
     const int lane = (int)lane_id();
-    const int l4 = lane & 3;
+    const int sl = lane & (kClipSeg - 1), base = lane - sl;     // lane in the segment, segment's first lane
+    const float d = plane_d(P.n, P.v[0]);
+    int n = (live && !(P.one_sided && !(d < 0.0f))) ? 4 : 0;
+    const int l4 = sl & 3;
     V3 v = sel_v3(l4 == 0, P.v[0], sel_v3(l4 == 1, P.v[1], sel_v3(l4 == 2, P.v[2], P.v[3])));
-    int n = 4;
     for (int pl = 0; pl < 6; ++pl) {
-        const V3 b = shfl_v3(v, lane + 1 >= n ? 0 : lane + 1);
+        const V3 b = shfl_v3(v, base + (sl + 1 >= n ? 0 : sl + 1));
         const float da = plane_dist(pl, cam, v), db = plane_dist(pl, cam, b);
-        const bool act = lane < n;
+        const bool act = sl < n;
         const bool ia = da >= 0.0f, ib = db >= 0.0f;
-        // every vertex inside: the walk would emit the polygon unchanged
+        // every vertex of every segment inside: the walks emit the polygons unchanged
         if (__ballot(act && !ia) == 0ull) continue;
         const bool e0 = act && ia, e1 = act && (ia != ib);
         V3 r = v;
@@ -1168,32 +1179,31 @@ __device__ __forceinline__ void clip_wave(const Cam &cam, const Poly &P, const S
             if (pl == 0) r.z = cam.zn;
             if (pl == 1) r.z = cam.zf;
         }
-        const uint32_t m0 = (uint32_t)__ballot(e0), m1 = (uint32_t)__ballot(e1);   // lanes < n <= 12
+        const uint32_t m0 = (uint32_t)(__ballot(e0) >> base) & 0xFFFFu;
+        const uint32_t m1 = (uint32_t)(__ballot(e1) >> base) & 0xFFFFu;
         const int total = __popc(m0) + __popc(m1);
-        if (total == 0 || total > kMaxVerts) return;
         // bit 2k: vertex of lane k, bit 2k+1: crossing of lane k; output p is the
         // (p+1)-th set bit
         uint32_t M = spread_bits(m0) | (spread_bits(m1) << 1);
-        const int drop = min(lane, total - 1);
+        const int drop = min(sl, max(total - 1, 0));
         for (int k = 0; k < drop; ++k) M &= M - 1u;
-        const int bit = __ffs(M) - 1;
-        const int src = bit >> 1;
+        const int bit = M ? __ffs(M) - 1 : 0;
+        const int src = base + (bit >> 1);
         const V3 fv = shfl_v3(v, src), fr = shfl_v3(r, src);
         v = sel_v3(bit & 1, fr, fv);
-        n = total;
+        // nothing left, or more than kMaxVerts: the polygon is dropped
+        n = (total == 0 || total > kMaxVerts) ? 0 : total;
     }
-    if (n < 3) return;
     const Plane pln = face_plane(cam, P.n, d);
-    const bool road = K.fast && !P.one_sided;
     int32_t X, Y;
     snap(cam, v, X, Y);
-    const int32_t X0 = __shfl(X, 0), Y0 = __shfl(Y, 0);
-    const int nx = lane + 1 < n ? lane + 1 : 0;
-    const int32_t X2 = __shfl(X, nx), Y2 = __shfl(Y, nx);
-    // fan triangle (0, k, k+1) on lane k
+    const int32_t X0 = __shfl(X, base), Y0 = __shfl(Y, base);
+    const int nx = sl + 1 < n ? sl + 1 : 0;
+    const int32_t X2 = __shfl(X, base + nx), Y2 = __shfl(Y, base + nx);
+    // fan triangle (0, k, k+1) on lane k of the segment
     TriRec t;
     bool ok = false;
-    if (lane >= 1 && lane + 1 < n) {
+    if (n >= 3 && sl >= 1 && sl + 1 < n) {
         ok = make_tri(cam, P.one_sided, X0, Y0, X, Y, X2, Y2, K.r0, K.r1, t.g);
         t.A = pln.A; t.B = pln.B; t.C = pln.C; t.keylo = P.keylo;
     }
@@ -1352,14 +1362,16 @@ __device__ void setup_source(const DevSim &s, const SceneRec &sc, const Cam &cam
             const int tail = L.cnt[par ? C_CLIPQ1 : C_CLIPQ], nq = tail - head;
             // the clipper may emit up to kMaxTrisPerCand triangles per candidate
             const int chunk = can_flush ? max(1, fcap / kMaxTrisPerCand) : B;
-            // one wave per queued candidate
+            // one 16-lane segment per queued candidate, four per wave
             for (int q0 = 0; q0 < nq; q0 += chunk) {
                 const int qn = min(chunk, nq - q0);
                 if (can_flush) r_up = make_room(cam, L, K, qn * kMaxTrisPerCand, qn * kMaxTrisPerCand) + qn * kMaxTrisPerCand;
-                for (int q = q0 + (tid >> 6); q < q0 + qn; q += B >> 6) {
-                    Poly Q;
-                    build_code(s, sc, cam, L.clipq[par * B + (head + q) % B], Q);
-                    clip_wave(cam, Q, K, L);
+                for (int qb = q0; qb < q0 + qn; qb += B / kClipSeg) {
+                    const int q = qb + tid / kClipSeg;
+                    const bool live = q < q0 + qn;
+                    Poly Q = {};
+                    if (live) build_code(s, sc, cam, L.clipq[par * B + (head + q) % B], Q);
+                    clip_wave(cam, Q, live, road, K, L);
                 }
                 __syncthreads();
             }
