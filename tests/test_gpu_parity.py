@@ -385,6 +385,61 @@ def test_uneven_full_size_graph_sampled():
     assert torch.equal(tuned, rgb)
 
 
+def test_sweep_full_size_every_resolution_sampled():
+    """The resolution sweep at full size (64 scenes x 64 agents, 4,000 quads
+    each) at 64x64, 128x128, 256x256 and 512x512: step + render replayed as a
+    hipGraph for 2 steps; sampled views (rgb, depth, primitive ids) vs the
+    oracle, and the launches the bench's tuner picked on these shapes give the
+    same bits.  Sampled views are gathered on the device before the copy."""
+    tuned = {64: [dict(band_rows=64, batch_tris=256, blocks_per_cu=3)],
+             128: [dict(band_rows=32, batch_tris=256, blocks_per_cu=3)],
+             256: [dict(band_rows=16, batch_tris=256, blocks_per_cu=2), dict(band_rows=16, batch_tris=512, blocks_per_cu=2)],
+             512: [dict(band_rows=8, batch_tris=256, blocks_per_cu=3)]}
+    pal = g.default_palette()
+    rng = np.random.default_rng(64)
+    for res in (64, 128, 256, 512):
+        print(f"sweep {res}x{res}", flush=True)
+        w = g.workload("sweep", resolution=res)
+        sim = _sim(w.scenes, w.camera, pal)
+        rgb = sim.new_rgb()
+        act_d = torch.empty((sim.n_agents, 2), dtype=torch.float32, device="cuda")
+        st = np.concatenate([s.agent_state for s in w.scenes])
+        dims = np.concatenate([s.agent_dims for s in w.scenes])
+        for step in range(2):
+            act = g.batch_actions(w.seed, step, w.scenes)
+            act_d.copy_(torch.from_numpy(act))
+            sim.step_render_graph(act_d, rgb)
+            st, _ = oracle.step(st, dims, act, 0.1)
+        torch.cuda.synchronize()
+        assert np.array_equal(sim.get_state().cpu().numpy().view(np.uint32), st.view(np.uint32))
+        rgb2, d, p = sim.render(depth=True, primid=True)
+        torch.cuda.synchronize()
+        assert torch.equal(rgb, rgb2), res
+        hs = _host_scene_state(w.scenes, st)
+        n = 6 if res == 512 else 10
+        picks = [(int(rng.integers(64)), int(rng.integers(64)), 0) for _ in range(n)] + [(63, 63, 0), (0, 0, 0)]
+        idx = torch.tensor([si * 64 + a for si, a, _ in picks], device="cuda")
+        got_rgb, got_d, got_p = rgb.index_select(0, idx).cpu().numpy(), d.index_select(0, idx).cpu().numpy(), \
+            p.index_select(0, idx).cpu().numpy()
+        for k, (si, a, c) in enumerate(picks):
+            ref = oracle.render_scene_view(hs[si], w.camera, pal, a, c)
+            assert np.array_equal(got_rgb[k], ref.rgb), (res, si, a)
+            assert np.array_equal(got_p[k], ref.primid), (res, si, a)
+            fin = np.isfinite(ref.depth)
+            assert np.array_equal(np.isfinite(got_d[k]), fin), (res, si, a)
+            rel = np.abs(got_d[k][fin].astype(np.float64) - ref.depth[fin]) / np.abs(ref.depth[fin])
+            assert rel.size == 0 or rel.max() <= 1e-5, (res, si, a, rel.max())
+        del rgb2, d, p
+        for lv in tuned[res]:
+            sim.set_launch(block_threads=256, **lv)
+            other = sim.new_rgb()
+            sim.render(rgb=other)
+            torch.cuda.synchronize()
+            assert torch.equal(other, rgb), (res, lv)
+        del sim, rgb, other
+        torch.cuda.empty_cache()
+
+
 def test_state_save_restore_reproduces_images():
     w = g.workload("uniform", n_scenes=3)
     pal = g.default_palette()
