@@ -29,6 +29,8 @@ VALU_PEAK = 256 * 64 * 2.4e9          # vector lane-ops/s: 256 CUs, 4 SIMDs x 16
 METRIC = "agent-views/sec at 128×128 RGB (batched vs plain, same GPU); p99 step latency"
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 256 << 20
+# the workloads' episodes: 100 steps of random actions from the initial placement
+EPISODE_STEPS = 100
 COUNTERS = os.path.join(ROOT, "profiles", "k_render_rgb_uniform128_counters.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2606_19641_amd", "csrc", "gp_kernels.hip")
 
@@ -258,7 +260,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-resident", type=int, default=64)
     ap.add_argument("--serve-pool", type=int, default=256)
-    ap.add_argument("--serve-life", type=int, default=1000)
+    ap.add_argument("--serve-life", type=int, default=EPISODE_STEPS, help="requests per rollout (one episode)")
     ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--serve-budget-gib", type=int, default=16)
     args = ap.parse_args()
@@ -284,13 +286,26 @@ def main():
     K, W = args.steps, args.warmup
     sim = gp.Sim(w.scenes, w.camera, pal, device="cuda:0")
     V = sim.n_views
-    # the inputs first (host work, the GPU idle): warm-up steps reuse a pool of
-    # at most 32 action sets in turn, the timed steps get their own
-    PW = max(1, min(W, 32))
-    acts = torch.from_numpy(np.stack([g.batch_actions(w.seed, k, w.scenes) for k in range(PW + K)])).to(dev)
+    # Every step this benchmark runs belongs to an episode of E steps of random
+    # actions from the workload's initial placement: with random actions the
+    # agents leave the road network within a few hundred steps and the views
+    # empty out, so a longer run would time a different (cheaper) workload.
+    # Episode step e takes action set e; the state returns to the initial one
+    # at every episode start.  The inputs are built first (host work, GPU idle).
+    E = EPISODE_STEPS
+    state0 = sim.get_state()
+    acts = torch.from_numpy(np.stack([g.batch_actions(w.seed, k, w.scenes) for k in range(E)])).to(dev)
     act_buf = torch.empty_like(acts[0])
     rgb = sim.new_rgb()
     stream = torch.cuda.current_stream()
+
+    def replay(k):
+        """Step k of the run (episode step k mod E) as one graph replay."""
+        if k % E == 0:
+            sim.set_state(state0)
+        act_buf.copy_(acts[k % E])
+        sim.step_render_graph(act_buf, rgb)
+
     if args.tuned:
         sim.set_launch(**json.loads(args.tuned))
     elif not args.no_tune:
@@ -306,20 +321,24 @@ def main():
     # has run, since the clocks rise only under sustained load
     t_w = time.perf_counter()
     for k in range(W):
-        act_buf.copy_(acts[k % PW])
-        sim.step_render_graph(act_buf, rgb)
+        replay(k)
     torch.cuda.synchronize()
     k = W
     while time.perf_counter() - t_w < 0.1:
         for _ in range(16):
-            act_buf.copy_(acts[k % PW])
-            sim.step_render_graph(act_buf, rgb)
+            replay(k)
             k += 1
         torch.cuda.synchronize()
     settle_steps = k - W
+    # the timed steps: one episode from its start (more than E steps run
+    # further episodes, each from the initial state again)
+    sim.set_state(state0)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(K):
-        act_buf.copy_(acts[PW + k])
+        if k and k % E == 0:
+            sim.set_state(state0)
+        act_buf.copy_(acts[k % E])
         sim.step_render_graph(act_buf, rgb)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -330,30 +349,37 @@ def main():
     n_lat = max(args.lat_steps, 1)
     lev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_lat)]
     for k in range(n_lat):
+        if k % E == 0:
+            sim.set_state(state0)
         lev[k][0].record(stream)
-        act_buf.copy_(acts[k % (PW + K)])
+        act_buf.copy_(acts[k % E])
         sim.step_render_graph(act_buf, rgb)
         lev[k][1].record(stream)
     torch.cuda.synchronize()
     lat_ms = np.array([a.elapsed_time(b) for a, b in lev])
 
-    # ---- the render kernel alone (eager, persistent), events on its stream; a
-    # short spin kernel first lets the launches queue up, so host launch gaps
-    # do not enter the event times of short kernels
-    rk = max(10, min(K, 50))
+    # ---- the render kernel alone (eager, persistent), events on its stream,
+    # over the states of one episode: after each untimed step, RR renders
+    # back to back between one event pair (which spreads the dispatch latency
+    # an event pair adds over RR launches); a short spin kernel first lets the
+    # launches queue up, so host launch gaps do not enter the event times
+    rk, RR = max(10, min(K, E)), 3
     rev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(rk)]
+    sim.set_state(state0)
     torch.cuda._sleep(1_000_000)
     for k in range(rk):
+        sim.step(acts[k % E])
         rev[k][0].record(stream)
-        sim.render(rgb=rgb)
+        for _ in range(RR):
+            sim.render(rgb=rgb)
         rev[k][1].record(stream)
     torch.cuda.synchronize()
-    render_ms = float(np.mean([a.elapsed_time(b) for a, b in rev]))
+    render_ms = float(np.mean([a.elapsed_time(b) for a, b in rev])) / RR
 
     # ---- the infraction check (collision / off-road, halting) on the same state,
     # timed apart: it is not part of the step + render graph
     flags = torch.empty(sim.n_agents, dtype=torch.uint8, device=dev)
-    state0 = sim.get_state()
+    state_c = sim.get_state()
     iev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
     torch.cuda._sleep(1_000_000)
     for a, b in iev:
@@ -362,19 +388,24 @@ def main():
         b.record(stream)
     torch.cuda.synchronize()
     infr_ms = float(np.mean([a.elapsed_time(b) for a, b in iev]))
-    sim.set_state(state0)               # the check halted offenders: restore the state
+    sim.set_state(state_c)              # the check halted offenders: restore the state
 
-    # ---- the ray-cast backend on the same state (same images up to edge pixels),
-    # timed apart: the raster is the measured path
+    # ---- the ray-cast backend over the states of one episode (every fifth
+    # step; same images up to edge pixels), timed apart: the raster is the
+    # measured path
     rc_rgb = sim.new_rgb()
     sim.render_raycast(rgb=rc_rgb)
-    rev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
+    rev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(E // 5)]
+    sim.set_state(state0)
     torch.cuda.synchronize()
     torch.cuda._sleep(1_000_000)
-    for a, b in rev:
-        a.record(stream)
-        sim.render_raycast(rgb=rc_rgb)
-        b.record(stream)
+    for k in range(E):
+        sim.step(acts[k])
+        if k % 5 == 4:
+            a, b = rev[k // 5]
+            a.record(stream)
+            sim.render_raycast(rgb=rc_rgb)
+            b.record(stream)
     torch.cuda.synchronize()
     raycast_ms = float(np.mean([a.elapsed_time(b) for a, b in rev]))
     del rc_rgb
@@ -383,13 +414,17 @@ def main():
     plain = None
     if not args.no_plain:
         sim.set_launch(sched=gp.SCHED_PLAIN)
+        sim.set_state(state0)
         for k in range(min(W, 20)):         # the clocks are up by now
-            sim.step(acts[k % PW])
+            sim.step(acts[k % E])
             sim.render(rgb=rgb)
+        sim.set_state(state0)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for k in range(K):
-            sim.step(acts[PW + k])
+            if k and k % E == 0:
+                sim.set_state(state0)
+            sim.step(acts[k % E])
             sim.render(rgb=rgb)
         torch.cuda.synchronize()
         plain = V * K / (time.perf_counter() - t1)

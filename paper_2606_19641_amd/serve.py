@@ -313,6 +313,12 @@ class GpuExecutor:
                 "event": None, "token": None,
             })
         self.max_batch_agents = max_batch_agents
+        # Creating a sim uploads its scene and waits for that upload.  On a
+        # stream of its own (non-blocking, like every torch stream) the wait
+        # covers the upload only, not the batches queued on the slots' streams
+        # (the legacy default stream would wait for all of them).  A rollout's
+        # arena block is reused only after its last batch completed.
+        self.upload_stream = torch.cuda.Stream(device=self.device)
 
     def footprint(self, scene) -> int:
         ws = self.gp.required_bytes([scene], self.camera, self.palette)
@@ -324,7 +330,7 @@ class GpuExecutor:
         ws_end = offset + (ws_bytes + ALIGN - 1) // ALIGN * ALIGN
         n_views = scene.agent_state.shape[0] * self.n_cams
         sim = self.gp.Sim([scene], self.camera, self.palette, device=str(self.device),
-                          workspace=self.arena[offset:offset + ws_bytes])
+                          workspace=self.arena[offset:offset + ws_bytes], stream=self.upload_stream)
         if self.launch_cfg:
             sim.set_launch(**self.launch_cfg)
         rgb = self.arena[ws_end:ws_end + n_views * self.img_bytes].view(
