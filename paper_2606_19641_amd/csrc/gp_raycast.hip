@@ -28,7 +28,8 @@
 // lights are culled against the view frustum in chunks of up to 256 and the
 // survivors staged in LDS; every pixel of the band then tests the staged
 // records (boxes only where their image rectangle holds the pixel, road bins
-// per sub-band of rows by the ground depths the rows see).  Colours come
+// per sub-band of rows by the ground depths the rows see, their strips staged
+// in LDS sixteen bins at a time).  Colours come
 // from the keys as in the raster's general kernel.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -43,6 +44,9 @@ constexpr int kRcThreads = 256;
 constexpr int kRcBandPixels = 4096;
 constexpr int kRcRoadPixels = 512;        // pixels of a road sub-band
 constexpr int kRcStageWords = 10;         // words per staged record
+constexpr int kRcStripWords = 9;          // words per staged road strip: 8 corner coordinates, index and colour
+constexpr int kRcGroupBins = kRcThreads / kBinQuads;   // bins whose strips are staged together
+static_assert(kRcGroupBins * kBinQuads == kRcThreads, "one staged strip per thread");
 
 #define GP_RC_LDS __attribute__((address_space(3)))
 
@@ -101,6 +105,8 @@ __global__ __launch_bounds__(kRcThreads) void k_raycast(DevSim s, RenderOut o, i
     GP_RC_LDS float *stg = (GP_RC_LDS float *)(smem + 8 * kRcBandPixels);       // [kRcStageWords][256]
     GP_RC_LDS int32_t *cnt = (GP_RC_LDS int32_t *)(smem + 8 * kRcBandPixels + 4 * kRcStageWords * kRcThreads);
     GP_RC_LDS uint32_t *pal = (GP_RC_LDS uint32_t *)(cnt + 4);
+    GP_RC_LDS float *sst = (GP_RC_LDS float *)(pal + 256);                         // [kRcStripWords][256]
+    GP_RC_LDS int32_t *isst = (GP_RC_LDS int32_t *)sst;
     GP_RC_LDS int32_t *istg = (GP_RC_LDS int32_t *)stg;
     const int tid = threadIdx.x, B = kRcThreads;
     const int view = view_begin + blockIdx.x;
@@ -303,45 +309,67 @@ __global__ __launch_bounds__(kRcThreads) void k_raycast(DevSim s, RenderOut o, i
                 __syncthreads();
                 const int nb = cnt[0];
                 if (nb == 0) continue;
-                for (int p = (r0 - j0) * W + tid; p < (r1 - j0) * W; p += B) {
-                    const int j = j0 + p / W, i = p - (p / W) * W;
-                    float a, b, dx, dy;
-                    rc_sample(cam, i, j, a, b, dx, dy);
-                    if (!(b < 0.0f)) continue;
-                    const float sp = -cam.h / b;
-                    const float z = sp * cam.f;
-                    if (!(z >= cam.zn && z <= cam.zf)) continue;
-                    const float x = fmaf(sp, dx, cam.px), y = fmaf(sp, dy, cam.py);
-                    int best_r = INT32_MAX, best_slot = -1;
-                    for (int r = 0; r < nb; ++r) {
-                        if (x < stg[r] || y < stg[B + r] || x > stg[2 * B + r] || y > stg[3 * B + r]) continue;
-                        const int st0 = istg[4 * B + r], n = istg[5 * B + r];
-                        for (int q = 0; q < n; ++q) {
-                            const int g = sc.road_base + st0 + q;
+                // the staged bins in groups of kRcGroupBins: a group's strips go
+                // to LDS (thread k holds strip k mod kBinQuads of bin k / kBinQuads),
+                // then every pixel tests them and folds its best road into its
+                // key; the largest key over the groups is the lowest road index
+                for (int g0 = 0; g0 < nb; g0 += kRcGroupBins) {
+                    const int g1 = min(nb, g0 + kRcGroupBins);
+                    {
+                        const int r = g0 + tid / kBinQuads, q = tid % kBinQuads;
+                        if (r < g1 && q < istg[5 * B + r]) {
+                            const int g = sc.road_base + istg[4 * B + r] + q;
                             const float4 q0 = s.roads[2 * g], q1 = s.roads[2 * g + 1];
-                            const float qx[4] = {q0.x, q0.z, q1.x, q1.z}, qy[4] = {q0.y, q0.w, q1.y, q1.w};
-                            int pos = 0, neg = 0;
-    #pragma unroll
-                            for (int e = 0; e < 4; ++e) {
-                                const int e1 = (e + 1) & 3;
-                                const float ex = qx[e1] - qx[e], ey = qy[e1] - qy[e];
-                                const float wx = x - qx[e], wy = y - qy[e];
-                                const float c = fmaf(ex, wy, -(ey * wx));
-                                pos += c > 0.0f;
-                                neg += c < 0.0f;
-                            }
-                            const int ri = s.road_index[g];
-                            if ((pos == 4 || neg == 4) && ri < best_r) {
-                                best_r = ri;
-                                best_slot = g;
-                            }
+                            sst[0 * B + tid] = q0.x;
+                            sst[1 * B + tid] = q0.y;
+                            sst[2 * B + tid] = q0.z;
+                            sst[3 * B + tid] = q0.w;
+                            sst[4 * B + tid] = q1.x;
+                            sst[5 * B + tid] = q1.y;
+                            sst[6 * B + tid] = q1.z;
+                            sst[7 * B + tid] = q1.w;
+                            isst[8 * B + tid] = (s.road_index[g] << 8) | (int)s.road_color[g];
                         }
                     }
-                    if (best_slot >= 0) {
-                        const unsigned long long key =
-                            make_key(1.0f / z, key_word(0u, 6 * n_box + best_r, s.road_color[best_slot]));
-                        if (key > keys[p]) keys[p] = key;
+                    __syncthreads();
+                    for (int p = (r0 - j0) * W + tid; p < (r1 - j0) * W; p += B) {
+                        const int j = j0 + p / W, i = p - (p / W) * W;
+                        float a, b, dx, dy;
+                        rc_sample(cam, i, j, a, b, dx, dy);
+                        if (!(b < 0.0f)) continue;
+                        const float sp = -cam.h / b;
+                        const float z = sp * cam.f;
+                        if (!(z >= cam.zn && z <= cam.zf)) continue;
+                        const float x = fmaf(sp, dx, cam.px), y = fmaf(sp, dy, cam.py);
+                        int best = INT32_MAX;          // (road index << 8) | colour of the best strip
+                        for (int r = g0; r < g1; ++r) {
+                            if (x < stg[r] || y < stg[B + r] || x > stg[2 * B + r] || y > stg[3 * B + r]) continue;
+                            const int n = istg[5 * B + r], base = (r - g0) * kBinQuads;
+                            for (int q = 0; q < n; ++q) {
+                                const int k = base + q;
+                                const float qx[4] = {sst[k], sst[2 * B + k], sst[4 * B + k], sst[6 * B + k]};
+                                const float qy[4] = {sst[B + k], sst[3 * B + k], sst[5 * B + k], sst[7 * B + k]};
+                                int pos = 0, neg = 0;
+    #pragma unroll
+                                for (int e = 0; e < 4; ++e) {
+                                    const int e1 = (e + 1) & 3;
+                                    const float ex = qx[e1] - qx[e], ey = qy[e1] - qy[e];
+                                    const float wx = x - qx[e], wy = y - qy[e];
+                                    const float c = fmaf(ex, wy, -(ey * wx));
+                                    pos += c > 0.0f;
+                                    neg += c < 0.0f;
+                                }
+                                const int rc = isst[8 * B + k];
+                                if ((pos == 4 || neg == 4) && rc < best) best = rc;
+                            }
+                        }
+                        if (best != INT32_MAX) {
+                            const unsigned long long key =
+                                make_key(1.0f / z, key_word(0u, 6 * n_box + (best >> 8), (uint32_t)best & 0xFFu));
+                            if (key > keys[p]) keys[p] = key;
+                        }
                     }
+                    __syncthreads();                   // the next group overwrites the strips
                 }
             }
         }
@@ -426,7 +454,10 @@ __global__ __launch_bounds__(kRcThreads) void k_raycast(DevSim s, RenderOut o, i
 
 }  // namespace
 
-size_t raycast_lds_bytes() { return 8 * kRcBandPixels + 4 * kRcStageWords * kRcThreads + 16 + 1024; }
+size_t raycast_lds_bytes()
+{
+    return 8 * kRcBandPixels + 4 * kRcStageWords * kRcThreads + 16 + 1024 + 4 * kRcStripWords * kRcThreads;
+}
 
 hipError_t launch_raycast(const DevSim &s, const RenderOut &o, int view_begin, int n_views, hipStream_t st)
 {
