@@ -109,6 +109,8 @@ typedef enum {
     GP_SCHED_PLAIN = 0,       /* one launch per scene                                  */
     GP_SCHED_PERSISTENT = 1   /* one launch; workgroups pull views from a work queue   */
 } gp_sched;
+/* With GP_SCHED_PERSISTENT and no more views than blocks_per_cu * CUs, the one
+ * launch gives every view a workgroup of its own and uses no queue. */
 
 typedef struct {
     int32_t sched;            /* gp_sched                                             */

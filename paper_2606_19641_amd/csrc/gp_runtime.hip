@@ -306,8 +306,15 @@ gp_status render_impl(gp_sim *sim, const gp::RenderOut &o, const gp_launch &l, h
         }
         return GP_OK;
     }
-    const int64_t grid = std::min<int64_t>(sim->lay.n_views, (int64_t)l.blocks_per_cu * sim->n_cu);
-    e = gp::launch_render(sim->dev, o, c, kind, 1, 0, (int)grid, st);
+    const int64_t resident = (int64_t)l.blocks_per_cu * sim->n_cu;
+    if (sim->lay.n_views <= resident) {
+        // every view gets a workgroup of its own: one launch over all views,
+        // without the queue (whose empty segments would cost each workgroup a
+        // chain of device-scope atomics before it finds its view)
+        e = gp::launch_render(sim->dev, o, c, kind, 0, 0, (int)sim->lay.n_views, st);
+    } else {
+        e = gp::launch_render(sim->dev, o, c, kind, 1, 0, (int)resident, st);
+    }
     if (e != hipSuccess) return hip_fail(e, "render launch");
     return GP_OK;
 }
