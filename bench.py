@@ -469,7 +469,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic (seeded scenes standing in for nuPlan)",
         "config": {"workload": _describe(w), "views_per_step": V, "seed": w.seed,
-                   "schedule": "persistent work queue + hipGraph (step + render)",
+                   "schedule": "persistent work queue (one workgroup per view when the views fit the resident grid) + hipGraph (step + render)",
                    "launch": launch},
         "plain_value": plain,
         "batched_over_plain": (batched / plain) if plain else None,
