@@ -326,6 +326,34 @@ def test_every_launch_variant_gives_identical_bits():
                 assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), lv
 
 
+def test_direct_and_queued_persistent_launch_at_the_resident_boundary():
+    """With the persistent schedule, a render of no more views than resident
+    workgroups gives each view a workgroup of its own (no queue); one view
+    more takes the queue.  Both equal the per-scene launches bit for bit, and
+    sampled views of the direct form equal the oracle."""
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    cam = g.camera_for(32)
+    pal = g.default_palette()
+    for n_views in (n_cu, n_cu + 1):
+        print(f"resident boundary: {n_views} views on {n_cu} CUs", flush=True)
+        sizes = [32] * (n_views // 32) + ([n_views % 32] if n_views % 32 else [])
+        scenes = [g.make_scene(0x5EED0B0, i, n, 300) for i, n in enumerate(sizes)]
+        sim = _sim(scenes, cam, pal)
+        assert sim.n_views == n_views
+        out = {}
+        for sched in (0, 1):
+            sim.set_launch(sched=sched, blocks_per_cu=1)
+            rgb, d, p = sim.render(depth=True, primid=True)
+            fast, _, _ = sim.render()
+            torch.cuda.synchronize()
+            out[sched] = [x.cpu().numpy() for x in (rgb, d, p, fast)]
+        for a, b in zip(out[0], out[1]):
+            assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), n_views
+        assert np.array_equal(out[1][0], out[1][3])
+        picks = [(0, 0, 0), (len(scenes) - 1, sizes[-1] - 1, 0)]
+        _compare_views(scenes, cam, pal, *out[1][:3], picks, label=f"{n_views} views")
+
+
 def test_uniform_full_size_bench_launch_sampled():
     """64 scenes x 32 agents, 2,000 quads, 128x128, in the launch the bench
     times (persistent, rgb only) for 3 steps; sampled views vs the oracle."""
