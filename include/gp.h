@@ -112,12 +112,26 @@ typedef enum {
 /* With GP_SCHED_PERSISTENT and no more views than blocks_per_cu * CUs, the one
  * launch gives every view a workgroup of its own and uses no queue. */
 
+/* Rasteriser of rgb-only renders (no depth / primitive id) of sims whose road
+ * strips share one colour, without traffic lights or shading.  Other renders
+ * always take the banded rasteriser. */
+typedef enum {
+    GP_RASTER_BANDED = 0,     /* one workgroup of block_threads per view; LDS key bands of
+                                 band_rows rows; triangle lists of batch_tris             */
+    GP_RASTER_SPLIT = 1       /* view_waves wavefronts per view sharing the view's work
+                                 through an LDS work counter; about 19 KB of LDS per view
+                                 at 128 x 128; needs width % 16 == 0 and a 16-byte aligned
+                                 image (else the banded rasteriser runs)                  */
+} gp_raster;
+
 typedef struct {
     int32_t sched;            /* gp_sched                                             */
-    int32_t band_rows;        /* image rows per LDS depth-buffer band: 8, 16, 32 or 64 */
-    int32_t batch_tris;       /* triangles per LDS batch: 256, 512, 1024 or 2048       */
-    int32_t block_threads;    /* threads per workgroup: 256, 512 or 1024               */
+    int32_t band_rows;        /* banded: image rows per LDS depth-buffer band: 8, 16, 32 or 64 */
+    int32_t batch_tris;       /* banded: triangles per LDS batch: 256, 512, 1024 or 2048 */
+    int32_t block_threads;    /* banded: threads per workgroup: 256, 512 or 1024       */
     int32_t blocks_per_cu;    /* persistent grid = blocks_per_cu * CUs (1..16)         */
+    int32_t raster;           /* gp_raster                                            */
+    int32_t view_waves;       /* split: wavefronts per view: 1, 2 or 4                 */
 } gp_launch;
 
 /* Workspace bytes needed for these scenes (>= 0), or -1 on bad arguments. */

@@ -58,6 +58,8 @@ struct DevSim {
     const RoadBin *bins;
     const uint8_t *palette;   // [256*3]
     const int32_t *queue;     // [V] view order for the persistent schedule, kQueues segments
+    const int32_t *order;     // [V] view of workgroup b when every view has a workgroup: consecutive
+                              // workgroups (which go to the XCDs in turn) take the segments in turn
     uint32_t *counter;        // [kQueues + 2] segment heads, finished workgroups, exhausted
                               // segment mask (all zero between launches)
     int32_t qseg[kQueues + 1];// segment q of the queue is [qseg[q], qseg[q + 1])
@@ -98,7 +100,14 @@ struct LaunchCfg {
     int block_threads;
 };
 
-// Host-side launch helpers (defined in gp_kernels.hip).
+// Settings of the wave-split rgb raster (gp_raster.hip).
+struct RgbCfg {
+    int waves;        // wavefronts per view: 1, 2 or 4
+    int bcap;         // box triangles one view's list holds
+    int bins_cap;     // culling bins of the largest scene (surviving bins are listed in LDS)
+};
+
+// Host-side launch helpers (defined in gp_kernels.hip and gp_raster.hip).
 hipError_t launch_step(const DevSim &s, const float *actions, int agent_begin, int agent_count,
                        hipStream_t st);
 // clear_halted = 1 also clears the halted flags and the jerk actuators
@@ -117,6 +126,13 @@ size_t render_lds_bytes(int width, int height, const LaunchCfg &c, int fast);
 // ray-cast backend (gp_raycast.hip): one workgroup per view of [view_begin, view_begin + n_views)
 hipError_t launch_raycast(const DevSim &s, const RenderOut &o, int view_begin, int n_views, hipStream_t st);
 size_t raycast_lds_bytes();
+// wave-split rgb raster (gp_raster.hip) for uniform road colours, no depth /
+// primitive id, width a multiple of 16 and a 16-byte aligned image.
+// mode 0: workgroup b renders view view_begin + b; 1: view order[b]; 2: the
+// persistent work queue
+hipError_t launch_render_rgb(const DevSim &s, const RenderOut &o, const RgbCfg &c, int mode, int view_begin,
+                             int grid, hipStream_t st);
+size_t rgb_lds_bytes(int width, int height, const RgbCfg &c);
 // batched (serving) launches over a device table of sims
 hipError_t launch_step_multi(const SimEntry *tab, int n_sims, int max_agents, hipStream_t st);
 hipError_t launch_render_multi(const SimEntry *tab, const int2 *items, int n_items, uint32_t *ctl,

@@ -344,10 +344,12 @@ __device__ __forceinline__ int64_t floor_div64(int64_t a, int64_t b)   // b > 0
 // P_k = dX_k (Sy - Y_k) + dY_k (X_k - 128); a sample is inside iff every
 // E_k >= t_k, t_k = 0 on top (dY == 0, dX > 0) and left (dY < 0) edges, else 1.
 // The same span in exact int64 arithmetic, for triangles with a coordinate
-// of 2^25 subpixels or more (guard-band geometry).
-__device__ __forceinline__ bool row_span_int64(const TriGeo &t, int j, int W, int &xl_out, int &xr_out)
+// of 2^25 subpixels or more (guard-band geometry).  Rare: kept out of line
+// (its 64-bit divisions are long), with scalar arguments.  Returns (xl, xr).
+__device__ __noinline__ int2 row_span_int64(int32_t X0, int32_t Y0, int32_t X1, int32_t Y1, int32_t X2, int32_t Y2,
+                                            int j, int W)
 {
-    const int32_t X[3] = {t.X0, t.X1, t.X2}, Y[3] = {t.Y0, t.Y1, t.Y2};
+    const int32_t X[3] = {X0, X1, X2}, Y[3] = {Y0, Y1, Y2};
     int xl = 0, xr = W - 1;
     const int64_t Sy = 256 * (int64_t)j + 128;
     for (int k = 0; k < 3; ++k) {
@@ -356,7 +358,7 @@ __device__ __forceinline__ bool row_span_int64(const TriGeo &t, int j, int W, in
         const int64_t tk = (dY < 0 || (dY == 0 && dX > 0)) ? 0 : 1;
         const int64_t P = dX * (Sy - Y[k]) + dY * ((int64_t)X[k] - 128);
         if (dY == 0) {
-            if (P < tk) return false;
+            if (P < tk) return make_int2(0, -1);
             continue;
         }
         if (dY > 0) {
@@ -368,9 +370,7 @@ __device__ __forceinline__ bool row_span_int64(const TriGeo &t, int j, int W, in
             xl = (int)max((int64_t)xl, min(ic, (int64_t)W));
         }
     }
-    xl_out = xl;
-    xr_out = xr;
-    return xl <= xr;
+    return make_int2(xl, xr);
 }
 
 __device__ __forceinline__ bool row_span(const TriGeo &t, int j, int W, int &xl_out, int &xr_out)
@@ -378,39 +378,42 @@ __device__ __forceinline__ bool row_span(const TriGeo &t, int j, int W, int &xl_
     const int32_t X[3] = {t.X0, t.X1, t.X2}, Y[3] = {t.Y0, t.Y1, t.Y2};
     int xl = 0, xr = W - 1;
     if (!t.huge) {
-        // every term is an integer below 2^53: fp64 is exact here
+        // every term is an integer below 2^53: fp64 is exact here.  With
+        // N = P - t_k and D = 256 |dY|, edge k holds sample i iff
+        // N - D i >= 0 (dY > 0: i <= floor(N / D)), N + D i >= 0 (dY < 0:
+        // i >= -floor(N / D)) or N >= 0 (dY = 0); the same instructions serve
+        // every orientation (no branch on the sign)
         const double Sy = 256.0 * (double)j + 128.0;
+        const double Wd = (double)W;
+        double lo = 0.0, hi = Wd - 1.0;
+        bool empty = false;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const int k1 = (k == 2) ? 0 : k + 1;
             const int32_t dX = X[k1] - X[k], dY = Y[k1] - Y[k];
             const double tk = (dY < 0 || (dY == 0 && dX > 0)) ? 0.0 : 1.0;
             const double P = fma((double)dX, Sy - (double)Y[k], (double)dY * ((double)X[k] - 128.0));
-            if (dY == 0) {
-                if (P < tk) return false;
-                continue;
-            }
-            const double D = 256.0 * (double)dY;
-            // estimate of (P - tk) / D from a binary32 reciprocal: relative
-            // error below 2^-21, so within 1 of the quotient wherever the
-            // quotient lies in [-2, W + 1]; outside that range the clamp
-            // below decides, and the exact test that follows moves the
-            // estimate by at most one to the exact boundary
-            const double q = (double)((float)(P - tk) * __builtin_amdgcn_rcpf((float)D));
-            if (dY > 0) {            // E decreases with i: i <= q
-                double ic = fmin(fmax(floor(q), -1.0), (double)W);
-                if (P - D * ic < tk) ic -= 1.0;
-                else if (P - D * (ic + 1.0) >= tk) ic += 1.0;
-                xr = min(xr, (int)ic);
-            } else {                 // E increases with i: i >= q
-                double ic = fmin(fmax(ceil(q), -1.0), (double)W);
-                if (P - D * ic < tk) ic += 1.0;
-                else if (P - D * (ic - 1.0) >= tk) ic -= 1.0;
-                xl = max(xl, (int)ic);
-            }
+            const double N = P - tk;
+            empty = empty || (dY == 0 && N < 0.0);
+            const double D = 256.0 * (double)abs(dY);
+            // floor(N / D) from a binary32 reciprocal estimate (relative
+            // error below 2^-21, so within 1 of the quotient wherever it lies
+            // within W + 2 of zero; farther out the clamp decides, and only
+            // the clamped side of the range is used), moved by at most one to
+            // the exact value by the exact remainder N - D f
+            const double q = (double)((float)N * __builtin_amdgcn_rcpf((float)D));
+            double f = fmin(fmax(floor(q), -Wd - 1.0), Wd + 1.0);
+            const double r = fma(-D, f, N);
+            f = r < 0.0 ? f - 1.0 : (r >= D ? f + 1.0 : f);
+            hi = dY > 0 ? fmin(hi, f) : hi;
+            lo = dY < 0 ? fmax(lo, -f) : lo;
         }
+        xl = (int)lo;
+        xr = empty ? -1 : (int)hi;
     } else {
-        return row_span_int64(t, j, W, xl_out, xr_out);
+        const int2 r = row_span_int64(t.X0, t.Y0, t.X1, t.Y1, t.X2, t.Y2, j, W);
+        xl = r.x;
+        xr = r.y;
     }
     xl_out = xl;
     xr_out = xr;
@@ -446,6 +449,34 @@ __device__ __forceinline__ void lds_or64(lptr<unsigned long long> p, unsigned lo
 }
 
 __device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
+
+// Whole-record LDS copies as 16-byte vectors (the records' implicit copy
+// operators only bind to generic addresses).
+typedef int gp_v4i __attribute__((ext_vector_type(4)));
+
+template <class T>
+__device__ __forceinline__ T lds_load(lptr<T> p)
+{
+    constexpr int N = sizeof(T) / 16;
+    static_assert(sizeof(T) == 16 * N, "record size");
+    union { T t; gp_v4i v[N]; } u;
+    lptr<gp_v4i> q = (lptr<gp_v4i>)p;
+#pragma unroll
+    for (int k = 0; k < N; ++k) u.v[k] = q[k];
+    return u.t;
+}
+
+template <class T>
+__device__ __forceinline__ void lds_store(lptr<T> p, const T &t)
+{
+    constexpr int N = sizeof(T) / 16;
+    union { T t; gp_v4i v[N]; } u;
+    u.t = t;
+    lptr<gp_v4i> q = (lptr<gp_v4i>)p;
+#pragma unroll
+    for (int k = 0; k < N; ++k) q[k] = u.v[k];
+}
+
 
 static_assert(kBinQuads < 128, "bin count packs into 7 bits");
 constexpr int kMaxVerts = 12;
@@ -485,6 +516,116 @@ __device__ __forceinline__ V3 shfl_v3(const V3 &v, int src)
 constexpr int kClipSeg = 16;
 static_assert(kMaxVerts <= kClipSeg, "a clipped polygon fits a segment");
 
+// Fast path for one live candidate polygon: cull, project and orient its two
+// triangles (kept if their bounding box holds a sample within rows [r0, r1))
+// unless it needs the clipper (then `clip` is set).  PLANE: the triangles
+// need their depth plane and key (not for road strips of the rgb kernels).
+template <bool PLANE>
+__device__ __forceinline__ void fast_poly(const Cam &cam, const Poly &P, int r0, int r1, TriRec &t0, bool &v0,
+                                          TriRec &t1, bool &v1, bool &clip)
+{
+    if (outside(cam, P.v)) return;
+    if (!P.one_sided && road_beyond(cam, P.v)) return;
+    const float d = plane_d(P.n, P.v[0]);
+    if (P.one_sided && !(d < 0.0f)) return;
+    clip = needs_clip(cam, P.v);
+    if (clip) return;
+    int32_t X[4], Y[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) snap(cam, P.v[k], X[k], Y[k]);
+    v0 = make_tri(cam, P.one_sided, X[0], Y[0], X[1], Y[1], X[2], Y[2], r0, r1, t0.g);
+    v1 = make_tri(cam, P.one_sided, X[0], Y[0], X[2], Y[2], X[3], Y[3], r0, r1, t1.g);
+    if (PLANE && (v0 || v1)) {
+        const Plane pl = face_plane(cam, P.n, d);
+        t0.A = pl.A; t0.B = pl.B; t0.C = pl.C; t0.keylo = P.keylo;
+        t1.A = pl.A; t1.B = pl.B; t1.C = pl.C; t1.keylo = P.keylo;
+    }
+}
+
+// Sutherland-Hodgman clipping of one candidate by a whole wave, in registers.
+// Lane k holds vertex k of the current polygon.  Against each plane, in the
+// order near, far, guard band left / right / top / bottom, the edge from
+// vertex k to vertex k+1 (cyclically) contributes vertex k when it is inside
+// and then the crossing point when the edge crosses the plane; the crossing
+// is computed from the inside end towards the outside end.  The outputs are
+// ordered by k, vertex before crossing, exactly as a sequential walk emits
+// them; output p is fetched by lane p from the lane that produced it.  A
+// polygon that would need more than kMaxVerts vertices (only a
+// self-intersecting input quad can) is dropped.
+// Each 16-lane segment of the wave clips its own candidate (lane k of a
+// segment holds vertex k; a clip never has more than kMaxVerts = 12
+// vertices), so a wave clips four candidates at a time.  Within a segment the
+// walk is the sequential one: per plane each lane emits its vertex if inside
+// and the crossing of its edge if the edge crosses, the outputs placed by a
+// prefix over the segment's part of the ballots, which keeps the sequential
+// walk's vertex order and arithmetic exactly.  A segment whose vertices are
+// all inside a plane keeps its polygon unchanged (the same outputs).  live:
+// the segment has a candidate.  Returns true on the lanes that hold a fan
+// triangle (lane k of a segment: triangle (0, k, k+1)) with a sample in its
+// bounding box within rows [r0, r1), written to t (its depth plane and key
+// word too when PLANE).
+
+template <bool PLANE>
+__device__ __forceinline__ bool clip_seg(const Cam &cam, const Poly &P, bool live, int r0, int r1, TriRec &t)
+{
+    const int lane = (int)lane_id();
+    const int sl = lane & (kClipSeg - 1), base = lane - sl;     // lane in the segment, segment's first lane
+    const float d = plane_d(P.n, P.v[0]);
+    int n = (live && !(P.one_sided && !(d < 0.0f))) ? 4 : 0;
+    const int l4 = sl & 3;
+    V3 v = sel_v3(l4 == 0, P.v[0], sel_v3(l4 == 1, P.v[1], sel_v3(l4 == 2, P.v[2], P.v[3])));
+    for (int pl = 0; pl < 6; ++pl) {
+        const V3 b = shfl_v3(v, base + (sl + 1 >= n ? 0 : sl + 1));
+        const float da = plane_dist(pl, cam, v), db = plane_dist(pl, cam, b);
+        const bool act = sl < n;
+        const bool ia = da >= 0.0f, ib = db >= 0.0f;
+        // every vertex of every segment inside: the walks emit the polygons unchanged
+        if (__ballot(act && !ia) == 0ull) continue;
+        const bool e0 = act && ia, e1 = act && (ia != ib);
+        V3 r = v;
+        if (e1) {
+            const V3 pin = sel_v3(ia, v, b), pout = sel_v3(ia, b, v);
+            const float din = ia ? da : db, dout = ia ? db : da;
+            const float t = din / (din - dout);
+            r.x = fmaf(t, pout.x - pin.x, pin.x);
+            r.y = fmaf(t, pout.y - pin.y, pin.y);
+            r.z = fmaf(t, pout.z - pin.z, pin.z);
+            if (pl == 0) r.z = cam.zn;
+            if (pl == 1) r.z = cam.zf;
+        }
+        const uint32_t m0 = (uint32_t)(__ballot(e0) >> base) & 0xFFFFu;
+        const uint32_t m1 = (uint32_t)(__ballot(e1) >> base) & 0xFFFFu;
+        const int total = __popc(m0) + __popc(m1);
+        // bit 2k: vertex of lane k, bit 2k+1: crossing of lane k; output p is the
+        // (p+1)-th set bit
+        uint32_t M = spread_bits(m0) | (spread_bits(m1) << 1);
+        const int drop = min(sl, max(total - 1, 0));
+        for (int k = 0; k < drop; ++k) M &= M - 1u;
+        const int bit = M ? __ffs(M) - 1 : 0;
+        const int src = base + (bit >> 1);
+        const V3 fv = shfl_v3(v, src), fr = shfl_v3(r, src);
+        v = sel_v3(bit & 1, fr, fv);
+        // nothing left, or more than kMaxVerts: the polygon is dropped
+        n = (total == 0 || total > kMaxVerts) ? 0 : total;
+    }
+    int32_t X, Y;
+    snap(cam, v, X, Y);
+    const int32_t X0 = __shfl(X, base), Y0 = __shfl(Y, base);
+    const int nx = sl + 1 < n ? sl + 1 : 0;
+    const int32_t X2 = __shfl(X, base + nx), Y2 = __shfl(Y, base + nx);
+    // fan triangle (0, k, k+1) on lane k of the segment
+    bool ok = false;
+    if (n >= 3 && sl >= 1 && sl + 1 < n) {
+        ok = make_tri(cam, P.one_sided, X0, Y0, X, Y, X2, Y2, r0, r1, t.g);
+        if (PLANE) {
+            const Plane pln = face_plane(cam, P.n, d);
+            t.A = pln.A; t.B = pln.B; t.C = pln.C; t.keylo = P.keylo;
+        }
+    }
+    return ok;
+}
+
+
 __device__ __forceinline__ SceneRec uniform_scene(const SceneRec &r)
 {
     SceneRec u;
@@ -500,6 +641,43 @@ __device__ __forceinline__ SceneRec uniform_scene(const SceneRec &r)
     u.signal_base = __builtin_amdgcn_readfirstlane(r.signal_base);
     u.n_signals = __builtin_amdgcn_readfirstlane(r.n_signals);
     return u;
+}
+
+
+// ------------------------------------------------------------ work queue
+
+// Take the next view of the persistent work queue: kQueues segments of the
+// view order, one per XCD, each holding whole scenes (a scene's geometry is
+// then read through one L2).  Workgroups are dispatched to the XCDs in turn,
+// so workgroup b starts on segment b mod kQueues (`cur`); an exhausted
+// segment is marked in the shared mask, which the same atomic returns, and
+// the caller moves on to the next segment not yet marked.  counter[q] is the
+// head of segment q, counter[kQueues] counts the workgroups that have left,
+// counter[kQueues + 1] is the exhausted mask.  Returns a queue position, or
+// n_views when every segment is exhausted.  Called by one thread.
+__device__ __forceinline__ int queue_take(const DevSim &s, int &cur)
+{
+    for (;;) {
+        const int pos = (int)atomicAdd(&s.counter[cur], 1u);
+        if (pos < s.qseg[cur + 1] - s.qseg[cur]) return s.qseg[cur] + pos;
+        const uint32_t mask = atomicOr(&s.counter[kQueues + 1], 1u << cur) | (1u << cur);
+        if (mask == (1u << kQueues) - 1u) return s.n_views;
+        do cur = (cur + 1) % kQueues; while ((mask >> cur) & 1u);
+    }
+}
+
+// A workgroup leaves the persistent loop; the last one zeroes the counters,
+// so the next launch on the stream starts from full queues without a
+// separate reset (and a captured graph holds no memset node).  Called by one
+// thread.
+__device__ __forceinline__ void queue_leave(const DevSim &s)
+{
+    __threadfence();
+    const uint32_t done = atomicAdd(&s.counter[kQueues], 1u);
+    if (done == gridDim.x - 1) {
+        for (int q = 0; q < kQueues + 2; ++q) atomicExch(&s.counter[q], 0u);
+        __threadfence();
+    }
 }
 
 }  // namespace gp

@@ -376,33 +376,6 @@ struct Lds {
     __device__ int cap_of(int which) const { return which == C_RTRIS ? rcap : tcap; }
 };
 
-// Whole-record LDS copies as 16-byte vectors (the records' implicit copy
-// operators only bind to generic addresses).
-typedef int gp_v4i __attribute__((ext_vector_type(4)));
-
-template <class T>
-__device__ __forceinline__ T lds_load(lptr<T> p)
-{
-    constexpr int N = sizeof(T) / 16;
-    static_assert(sizeof(T) == 16 * N, "record size");
-    union { T t; gp_v4i v[N]; } u;
-    lptr<gp_v4i> q = (lptr<gp_v4i>)p;
-#pragma unroll
-    for (int k = 0; k < N; ++k) u.v[k] = q[k];
-    return u.t;
-}
-
-template <class T>
-__device__ __forceinline__ void lds_store(lptr<T> p, const T &t)
-{
-    constexpr int N = sizeof(T) / 16;
-    union { T t; gp_v4i v[N]; } u;
-    u.t = t;
-    lptr<gp_v4i> q = (lptr<gp_v4i>)p;
-#pragma unroll
-    for (int k = 0; k < N; ++k) q[k] = u.v[k];
-}
-
 // Block-wide exclusive scan of L.scan[0..n) in place; L.scan[n] = total.
 // Every thread must call it.
 __device__ int block_scan(Lds &L, int n)
@@ -635,106 +608,12 @@ __device__ __forceinline__ void append_one(Lds &L, int which, const TriRec &t)
     }
 }
 
-// Fast path for one live candidate polygon: cull, project and orient its two
-// triangles unless it needs the clipper (then `clip` is set).  PLANE: the
-// triangles need their depth plane and key (not for the rgb kernel's roads).
-template <bool PLANE>
-__device__ __forceinline__ void fast_poly(const Cam &cam, const Poly &P, const Sink &K, TriRec &t0, bool &v0,
-                                          TriRec &t1, bool &v1, bool &clip)
-{
-    if (outside(cam, P.v)) return;
-    if (!P.one_sided && road_beyond(cam, P.v)) return;
-    const float d = plane_d(P.n, P.v[0]);
-    if (P.one_sided && !(d < 0.0f)) return;
-    clip = needs_clip(cam, P.v);
-    if (clip) return;
-    int32_t X[4], Y[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) snap(cam, P.v[k], X[k], Y[k]);
-    v0 = make_tri(cam, P.one_sided, X[0], Y[0], X[1], Y[1], X[2], Y[2], K.r0, K.r1, t0.g);
-    v1 = make_tri(cam, P.one_sided, X[0], Y[0], X[2], Y[2], X[3], Y[3], K.r0, K.r1, t1.g);
-    if (PLANE && (v0 || v1)) {
-        const Plane pl = face_plane(cam, P.n, d);
-        t0.A = pl.A; t0.B = pl.B; t0.C = pl.C; t0.keylo = P.keylo;
-        t1.A = pl.A; t1.B = pl.B; t1.C = pl.C; t1.keylo = P.keylo;
-    }
-}
-
-// Sutherland-Hodgman clipping of one candidate by a whole wave, in registers.
-// Lane k holds vertex k of the current polygon.  Against each plane, in the
-// order near, far, guard band left / right / top / bottom, the edge from
-// vertex k to vertex k+1 (cyclically) contributes vertex k when it is inside
-// and then the crossing point when the edge crosses the plane; the crossing
-// is computed from the inside end towards the outside end.  The outputs are
-// ordered by k, vertex before crossing, exactly as a sequential walk emits
-// them; output p is fetched by lane p from the lane that produced it.  A
-// polygon that would need more than kMaxVerts vertices (only a
-// self-intersecting input quad can) is dropped.
-// Each 16-lane segment of the wave clips its own candidate (lane k of a
-// segment holds vertex k; a clip never has more than kMaxVerts = 12
-// vertices), so a wave clips four candidates at a time.  Within a segment the
-// walk is the sequential one: per plane each lane emits its vertex if inside
-// and the crossing of its edge if the edge crosses, the outputs placed by a
-// prefix over the segment's part of the ballots, which keeps the sequential
-// walk's vertex order and arithmetic exactly.  A segment whose vertices are
-// all inside a plane keeps its polygon unchanged (the same outputs).  live:
-// the segment has a candidate; road: the pass emits road strips (uniform).
-
+// Clip one candidate per 16-lane segment (clip_seg) and append the fan
+// triangles to the lists.
 __device__ __forceinline__ void clip_wave(const Cam &cam, const Poly &P, bool live, bool road, const Sink &K, Lds &L)
 {
-    const int lane = (int)lane_id();
-    const int sl = lane & (kClipSeg - 1), base = lane - sl;     // lane in the segment, segment's first lane
-    const float d = plane_d(P.n, P.v[0]);
-    int n = (live && !(P.one_sided && !(d < 0.0f))) ? 4 : 0;
-    const int l4 = sl & 3;
-    V3 v = sel_v3(l4 == 0, P.v[0], sel_v3(l4 == 1, P.v[1], sel_v3(l4 == 2, P.v[2], P.v[3])));
-    for (int pl = 0; pl < 6; ++pl) {
-        const V3 b = shfl_v3(v, base + (sl + 1 >= n ? 0 : sl + 1));
-        const float da = plane_dist(pl, cam, v), db = plane_dist(pl, cam, b);
-        const bool act = sl < n;
-        const bool ia = da >= 0.0f, ib = db >= 0.0f;
-        // every vertex of every segment inside: the walks emit the polygons unchanged
-        if (__ballot(act && !ia) == 0ull) continue;
-        const bool e0 = act && ia, e1 = act && (ia != ib);
-        V3 r = v;
-        if (e1) {
-            const V3 pin = sel_v3(ia, v, b), pout = sel_v3(ia, b, v);
-            const float din = ia ? da : db, dout = ia ? db : da;
-            const float t = din / (din - dout);
-            r.x = fmaf(t, pout.x - pin.x, pin.x);
-            r.y = fmaf(t, pout.y - pin.y, pin.y);
-            r.z = fmaf(t, pout.z - pin.z, pin.z);
-            if (pl == 0) r.z = cam.zn;
-            if (pl == 1) r.z = cam.zf;
-        }
-        const uint32_t m0 = (uint32_t)(__ballot(e0) >> base) & 0xFFFFu;
-        const uint32_t m1 = (uint32_t)(__ballot(e1) >> base) & 0xFFFFu;
-        const int total = __popc(m0) + __popc(m1);
-        // bit 2k: vertex of lane k, bit 2k+1: crossing of lane k; output p is the
-        // (p+1)-th set bit
-        uint32_t M = spread_bits(m0) | (spread_bits(m1) << 1);
-        const int drop = min(sl, max(total - 1, 0));
-        for (int k = 0; k < drop; ++k) M &= M - 1u;
-        const int bit = M ? __ffs(M) - 1 : 0;
-        const int src = base + (bit >> 1);
-        const V3 fv = shfl_v3(v, src), fr = shfl_v3(r, src);
-        v = sel_v3(bit & 1, fr, fv);
-        // nothing left, or more than kMaxVerts: the polygon is dropped
-        n = (total == 0 || total > kMaxVerts) ? 0 : total;
-    }
-    const Plane pln = face_plane(cam, P.n, d);
-    int32_t X, Y;
-    snap(cam, v, X, Y);
-    const int32_t X0 = __shfl(X, base), Y0 = __shfl(Y, base);
-    const int nx = sl + 1 < n ? sl + 1 : 0;
-    const int32_t X2 = __shfl(X, base + nx), Y2 = __shfl(Y, base + nx);
-    // fan triangle (0, k, k+1) on lane k of the segment
     TriRec t;
-    bool ok = false;
-    if (n >= 3 && sl >= 1 && sl + 1 < n) {
-        ok = make_tri(cam, P.one_sided, X0, Y0, X, Y, X2, Y2, K.r0, K.r1, t.g);
-        t.A = pln.A; t.B = pln.B; t.C = pln.C; t.keylo = P.keylo;
-    }
+    const bool ok = clip_seg<true>(cam, P, live, K.r0, K.r1, t);
     append_wave(L, road ? C_RTRIS : C_TRIS, ok, t, false, t);
     if (K.fast && !road && ok) {
         lds_min(L.cnt + C_BMIN, (int)t.g.j0);
@@ -852,7 +731,7 @@ __device__ void setup_source(const DevSim &s, const SceneRec &sc, const Cam &cam
             }
             TriRec t0, t1;
             bool v0 = false, v1 = false, clip = false;
-            if (live) fast_poly<!road>(cam, P, K, t0, v0, t1, v1, clip);
+            if (live) fast_poly<!road>(cam, P, K.r0, K.r1, t0, v0, t1, v1, clip);
             if (clip) {
                 const int q = lds_add(L.cnt + (par ? C_CLIPQ1 : C_CLIPQ), 1);
                 L.clipq[par * B + q % B] = code;
@@ -1372,43 +1251,16 @@ __global__ __launch_bounds__(BLOCK) void k_render(DevSim s, RenderOut o, LaunchC
         render_view<KIND>(s, o, lc, L, view_begin + blockIdx.x);
         return;
     }
-    // Work queue: kQueues segments of the view order, one per XCD; a segment
-    // holds whole scenes, so a scene's geometry is read through one XCD's L2.
-    // Workgroups are dispatched to the XCDs in turn, so workgroup b starts on
-    // segment b mod kQueues; when its segment is exhausted it marks it in the
-    // shared exhausted mask, which the same atomic returns, and moves on to
-    // the next segment not yet marked.  counter[q] is the head of segment q,
-    // counter[kQueues] counts the workgroups that have left the loop and
-    // counter[kQueues + 1] is the exhausted mask.  The last workgroup to leave
-    // zeroes them all, so the next launch on the stream starts from full
-    // queues without a separate reset (and a captured graph holds no memset
-    // node).
     int cur = (int)(blockIdx.x % kQueues);       // thread 0's current segment
-    auto take = [&]() -> int {
-        for (;;) {
-            const int pos = (int)atomicAdd(&s.counter[cur], 1u);
-            if (pos < s.qseg[cur + 1] - s.qseg[cur]) return s.qseg[cur] + pos;
-            const uint32_t mask = atomicOr(&s.counter[kQueues + 1], 1u << cur) | (1u << cur);
-            if (mask == (1u << kQueues) - 1u) return s.n_views;
-            do cur = (cur + 1) % kQueues; while ((mask >> cur) & 1u);
-        }
-    };
     for (;;) {
         __syncthreads();
-        if (threadIdx.x == 0) s_item = take();
+        if (threadIdx.x == 0) s_item = queue_take(s, cur);
         __syncthreads();
         const int it = __builtin_amdgcn_readfirstlane(s_item);
         if (it >= s.n_views) break;
         render_view<KIND>(s, o, lc, L, s.queue[it]);
     }
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t done = atomicAdd(&s.counter[kQueues], 1u);
-        if (done == gridDim.x - 1) {
-            for (int q = 0; q < kQueues + 2; ++q) atomicExch(&s.counter[q], 0u);
-            __threadfence();
-        }
-    }
+    if (threadIdx.x == 0) queue_leave(s);
 }
 
 

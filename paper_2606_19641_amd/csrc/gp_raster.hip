@@ -1,0 +1,1014 @@
+// Wave-split rgb raster of the Gigapixel hot path for gfx950 (MI355X).
+//
+// The rgb-only ego-centric render (Sec. 3.1 O_pixel; App. A "High-Throughput
+// Batched Rendering": one world per ego agent, all views in one batched
+// launch) for sims whose road strips share one colour and renders that need
+// neither depth nor primitive ids.  Its results are bit-identical to the
+// banded kernel (k_render) and to the plain definition: the same clip, snap,
+// fill rule and winner order, only organised for throughput.
+//
+// One workgroup of K wavefronts (K = 1, 2 or 4) renders one view, with about
+// 19 KB of LDS at 128 x 128, so that a CU keeps eight views in flight:
+//   A  bins    the scene's road culling bins are tested against the view
+//              (frustum, road depth limit and the row-gap test below); the
+//              surviving bins are listed in LDS.
+//   B  units   the waves deal out work units through an LDS counter.  Unit 0
+//              is the boxes: cull, face setup and clipping into the view's
+//              box triangle list.  Every further unit is four surviving bins
+//              (64 strip slots).  A strip first meets a cheap test that can
+//              only reject strips covering no sample: the frustum, the road
+//              depth limit, and the row-gap test (every vertex a strip's clip
+//              can produce lies at camera height -h, so its snapped row
+//              coordinate is a non-increasing function of its depth; a strip
+//              whose depth range maps between two sample rows covers none).
+//              Survivors' camera-space corners go to the wave's ring; full
+//              setup (clip test, snap, the two fan triangles) runs 64 at a
+//              time, and each batch of triangles is rasterised at once: per
+//              (triangle, row) the exact span of covered samples is OR-ed
+//              into the view's road coverage bitmask.  Strips that need
+//              clipping are queued and clipped four per wavefront.
+//   C  resolve rows no box triangle touches are written from the table of the
+//              sixteen four-pixel road/background patterns, 16 pixels (48
+//              bytes) per lane; box rows go band by band through a band of
+//              64-bit keys that reuses the waves' staging memory: box
+//              fragments are dealt to lanes (span lengths prefix-summed over
+//              the wavefront) and folded in with LDS atomic max, and the band
+//              is resolved against the road coverage.
+//
+// Every float operation is written out (fmaf for fused operations) and the
+// file is compiled with -ffp-contract=off, correctly rounded division and
+// IEEE denormals.
+
+#include "gp_device.h"
+#include "gp_geom.h"
+
+namespace gp {
+
+namespace {
+
+constexpr int kRing = 128;      // strips passed by the cheap test (road slot indices)
+constexpr int kWTris = 128;     // triangles staged for one span pass
+constexpr int kWClip = 68;      // road strips waiting for the clipper: a setup batch on top of < 4
+constexpr int kWaveBytes = kRing * 4 + kWTris * 32 + kWClip * 4;
+static_assert(kWaveBytes % 16 == 0, "wave regions stay 16-byte aligned");
+static_assert(sizeof(TriGeo) == 32, "staged triangle size");
+
+// LDS counters
+enum { R_NSB = 0, R_NEXT, R_NBT, R_BOVF, R_BMIN, R_BMAX, R_NCNT = 8 };
+constexpr int kBoxClip = 64;     // box faces waiting for the clipper (one setup pass)
+constexpr int kSurvCap = kWTris * 8;  // boxes listed after culling (ints in the triangle staging's memory)
+
+struct RgbLds {
+    lptr<int32_t> cnt;               // [R_NCNT]
+    lptr<uint32_t> pal;              // [256] RGB of each palette entry
+    lptr<uint32_t> lut;              // [16][4] four-pixel road/background patterns, 3 packed dwords
+    lptr<unsigned long long> bits;   // [H][nw] road coverage, bit i of word w: column 64 w + i
+    lptr<TriRec> btris;              // [bcap] the view's box triangles
+    lptr<int32_t> sbins;             // [bins_cap] surviving bins: start * 128 + count
+    lptr<int32_t> cq;                // [kBoxClip] box faces to clip (box * 8 + face)
+    lptr<unsigned char> waves;       // K regions of kWaveBytes
+    int nw, bcap, krows;
+    int region;                      // bytes from sbins to the end (free after the units)
+};
+
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+// byte offsets of the LDS sections (shared by the carve and the size query)
+struct RgbLayout {
+    size_t cnt, pal, lut, bits, btris, sbins, cq, waves, total;
+};
+
+__host__ __device__ inline RgbLayout rgb_layout(int W, int H, const RgbCfg &c)
+{
+    RgbLayout l;
+    const size_t nw = (size_t)(W + 63) / 64;
+    size_t o = 0;
+    l.cnt = o; o = align16(o + 4 * R_NCNT);
+    l.pal = o; o = align16(o + 4 * 256);
+    l.lut = o; o = align16(o + 4 * 64);
+    l.bits = o; o = align16(o + 8 * nw * (size_t)H);
+    l.btris = o; o = align16(o + sizeof(TriRec) * (size_t)c.bcap);
+    l.cq = o; o = align16(o + 4 * (size_t)kBoxClip);
+    l.sbins = o; o = align16(o + 4 * (size_t)c.bins_cap);
+    l.waves = o; o = align16(o + (size_t)kWaveBytes * (size_t)c.waves);
+    l.total = o;
+    return l;
+}
+
+// ------------------------------------------------------------ wave helpers
+
+// inclusive prefix sum over the wavefront: Hillis-Steele within each row of
+// 16 lanes (DPP row shifts), then the row totals carried across rows (DPP row
+// broadcasts of lanes 15 and 31)
+__device__ __forceinline__ int wave_incl_scan(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);   // row_bcast:15 into rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);   // row_bcast:31 into rows 2, 3
+    return v;
+}
+
+// number of lanes whose inclusive prefix is <= g: the lane that owns item g
+__device__ __forceinline__ int owner_of(int incl, int g)
+{
+    int t = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1)
+        if (__shfl(incl, t + step - 1) <= g) t += step;
+    return min(t, 63);
+}
+
+__device__ __forceinline__ int wave_min(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ int lanes_below(unsigned long long m)
+{
+    return __popcll(m & ((1ull << lane_id()) - 1ull));
+}
+
+// keep the compiler from moving LDS accesses across this point (the
+// wavefront's own LDS operations execute in order)
+__device__ __forceinline__ void wave_lds_order() { __asm__ __volatile__("" ::: "memory"); }
+
+// ------------------------------------------------------------ road tests
+
+// Road points lie at camera height -h, so a road vertex at depth z snaps to
+// the row coordinate Y(z) = rint(fmaf(h / z, F256, CY256)), a non-increasing
+// function of z (correctly rounded division, fmaf and rint are monotone).
+// Every vertex a strip's clip can produce has a depth within
+// [max(zmin, z_near), min(zmax, z_far)] up to a rounding of the guard-band
+// crossings, so its triangles' sample rows lie among the rows whose sample
+// 256 j + 128 falls within [Y(zhi), Y(zlo)].  The estimate below uses the
+// hardware reciprocal; its error (below 2^-20 relative on the quotient term)
+// and the rounding of rint are covered by the margins.  True if no image row
+// has its sample in the widened range: then the set covers no sample.
+__device__ __forceinline__ bool road_rows_empty(const Cam &c, float zmin, float zmax)
+{
+    const float zlo = fmaxf(zmin, c.zn) * (1.0f - 0x1p-20f);
+    const float zhi = fminf(zmax, c.zf) * (1.0f + 0x1p-20f);
+    const float hF = c.h * c.F256;
+    const float ylo = fmaf(hF, __builtin_amdgcn_rcpf(zhi), c.CY256);
+    const float yhi = fmaf(hF, __builtin_amdgcn_rcpf(zlo), c.CY256);
+    const float a = fmaf(-fabsf(ylo), 0x1p-18f, ylo) - 4.0f;
+    const float b = fmaf(fabsf(yhi), 0x1p-18f, yhi) + 4.0f;
+    const float j0 = fmaxf(ceilf((a - 128.0f) * (1.0f / 256.0f)), 0.0f);
+    const float j1 = fminf(floorf((b - 128.0f) * (1.0f / 256.0f)), (float)(c.H - 1));
+    return !(j0 <= j1);
+}
+
+// Cheap rejection of a road strip (BIN false) or of a culling bin's bounding
+// box (BIN true) with camera-space corners (x[k], -h, z[k]): true only if it
+// certainly covers no sample.  The tests are the near, far and side tests of
+// outside() (same predicates and margins), the road depth limit of
+// road_beyond(), and the row-gap test.  A strip's corners are computed here
+// exactly as the setup computes them, so its near and far predicates are the
+// clipper's own; a bin's strips have corners inside its box, whose computed
+// depths can differ from the box corners' by rounding (below 2^-22 of
+// |x| + |z|), so a bin's depth tests carry that margin.
+template <bool BIN>
+__device__ __forceinline__ bool road_culled(const Cam &c, const float *x, const float *z)
+{
+    bool n = true, fa = true, l = true, r = true;
+    float zmin = INFINITY, zmax = -INFINITY;
+    const float zlim = fminf(c.road_zmax, c.zf);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float ax = fabsf(x[k]), az = fabsf(z[k]);
+        const float dz = BIN ? fmaf(ax + az, 0x1p-20f, 1e-6f) : 0.0f;
+        n = n && (z[k] - c.zn < -dz);
+        fa = fa && (z[k] - zlim > dz);
+        const float mx = 1e-3f * (ax + az) + 1e-6f;
+        r = r && (fmaf(-c.t_right, z[k], x[k]) > mx);
+        l = l && (fmaf(-c.t_left, z[k], -x[k]) > mx);
+        zmin = fminf(zmin, z[k] - dz);
+        zmax = fmaxf(zmax, z[k] + dz);
+    }
+    if (n || fa || l || r) return true;
+    return road_rows_empty(c, zmin, zmax);
+}
+
+// camera-space x and z of a ground point (world x, y)
+__device__ __forceinline__ void ground_xz(const Cam &c, float wx, float wy, float &x, float &z)
+{
+    const float dx = wx - c.px, dy = wy - c.py;
+    z = fmaf(dx, c.fx, dy * c.fy);
+    x = fmaf(dx, c.fy, -(dy * c.fx));
+}
+
+// camera-space corners of road slot g (global), as the setup computes them
+__device__ __forceinline__ void road_corners(const DevSim &s, const Cam &cam, int g, V3 *v)
+{
+    const float4 q0 = s.roads[2 * g], q1 = s.roads[2 * g + 1];
+    const float y = 0.0f - cam.h;
+    ground_xz(cam, q0.x, q0.y, v[0].x, v[0].z);
+    ground_xz(cam, q0.z, q0.w, v[1].x, v[1].z);
+    ground_xz(cam, q1.x, q1.y, v[2].x, v[2].z);
+    ground_xz(cam, q1.z, q1.w, v[3].x, v[3].z);
+    v[0].y = y; v[1].y = y; v[2].y = y; v[3].y = y;
+}
+
+// ------------------------------------------------------------ per-wave state
+
+struct WaveSt {
+    lptr<int32_t> ring;      // [kRing] road slots (global) that passed the cheap test
+    lptr<TriGeo> tris;       // [kWTris]
+    lptr<int32_t> clipq;     // [kWClip] road slots (global) that need the clipper
+    int head, tail;          // ring positions (wave-uniform, only grow)
+    int nclip;               // queued strips
+};
+
+// OR the samples [xl, xr] of one row into its coverage words
+__device__ __forceinline__ void or_span(lptr<unsigned long long> row, int xl, int xr)
+{
+    const int w0 = xl >> 6, w1 = xr >> 6;
+    for (int w = w0; w <= w1; ++w) {
+        const int lo = (w == w0) ? (xl & 63) : 0;
+        const int hi = (w == w1) ? (xr & 63) : 63;
+        const unsigned long long m = (hi == 63 ? ~0ull : ((1ull << (hi + 1)) - 1ull)) & (~0ull << lo);
+        lds_or64(row + w, m);
+    }
+}
+
+// Rasterise the n staged road triangles into the coverage bitmask.  Lane t
+// first takes the first row of triangle t; the further rows of triangles
+// that span several rows are then dealt to the lanes by a prefix over their
+// counts.  Per (triangle, row) the exact span of covered samples is OR-ed
+// into the row's coverage words.
+__device__ __forceinline__ void road_spans(const RgbLds &L, const Cam &cam, const WaveSt &ws, int n)
+{
+    const int ln = (int)lane_id();
+    wave_lds_order();
+    for (int t0 = 0; t0 < n; t0 += 64) {
+        const int t = t0 + ln;
+        int c = 0;
+        if (t < n) {
+            const int32_t jj = ((lptr<const int32_t>)(ws.tris + t))[6];     // j0 | j1 << 16
+            c = (jj >> 16) - (int)(int16_t)(jj & 0xFFFF);
+        }
+        const int incl = wave_incl_scan(c);
+        const int total = __builtin_amdgcn_readlane(incl, 63);
+        const int excl = incl - c;
+        for (int g0 = -64; g0 < total; g0 += 64) {
+            // g0 < 0: lane t's own first row; then the dealt further rows
+            const int gi = g0 + ln;
+            int o = ln, extra = 0;
+            bool act = t < n;
+            if (g0 >= 0) {
+                o = owner_of(incl, gi);
+                extra = 1 + gi - __shfl(excl, o);
+                act = gi < total;
+            }
+            if (act) {
+                const TriGeo tg = lds_load((lptr<TriGeo>)(ws.tris + t0 + o));
+                const int j = tg.j0 + extra;
+                int xl, xr;
+                if (row_span(tg, j, cam.W, xl, xr)) or_span(L.bits + (size_t)j * L.nw, xl, xr);
+            }
+        }
+    }
+    wave_lds_order();
+}
+
+// Stage the triangles held by the lanes (v0: t0, v1: t1); returns how many.
+__device__ __forceinline__ int stage_tris(const WaveSt &ws, bool v0, const TriGeo &t0, bool v1, const TriGeo &t1)
+{
+    const unsigned long long b0 = __ballot(v0), b1 = __ballot(v1);
+    const int n0 = __popcll(b0);
+    if (v0) lds_store((lptr<TriGeo>)(ws.tris + lanes_below(b0)), t0);
+    if (v1) lds_store((lptr<TriGeo>)(ws.tris + n0 + lanes_below(b1)), t1);
+    return n0 + __popcll(b1);
+}
+
+// Clip up to four queued strips (the last ones of the queue), one per 16-lane
+// segment; stages their fan triangles and returns how many.
+__device__ __forceinline__ int road_clip(const DevSim &s, const Cam &cam, WaveSt &ws)
+{
+    const int m = min(ws.nclip, 4);
+    const int seg = (int)lane_id() >> 4;
+    const bool live = seg < m;
+    Poly P = {};
+    if (live) {
+        const int g = ws.clipq[ws.nclip - m + seg];
+        road_corners(s, cam, g, P.v);
+    }
+    P.n = dir_to_cam(cam, 0.0f, 0.0f, 1.0f);
+    P.one_sided = false;
+    P.keylo = 0u;
+    ws.nclip -= m;
+    TriRec t;
+    const bool ok = clip_seg<false>(cam, P, live, 0, cam.H, t);
+    TriGeo none = {};
+    return stage_tris(ws, ok, t.g, false, none);
+}
+
+// Full setup of n (<= 64) strips from the ring: clip test, snap and the two
+// fan triangles of the strips that need no clipping (staged; returns how
+// many); the others join the clip queue (which has room: fewer than four
+// wait whenever a setup runs).
+__device__ __forceinline__ int road_setup(const DevSim &s, const Cam &cam, WaveSt &ws, int n)
+{
+    const int ln = (int)lane_id();
+    wave_lds_order();
+    const bool live = ln < n;
+    int g = 0;
+    V3 v[4] = {};
+    if (live) {
+        g = ws.ring[(ws.head + ln) & (kRing - 1)];
+        road_corners(s, cam, g, v);
+    }
+    ws.head += n;
+    const bool clip = live && needs_clip(cam, v);
+    const unsigned long long cb = __ballot(clip);
+    if (clip) ws.clipq[ws.nclip + lanes_below(cb)] = g;
+    ws.nclip += __popcll(cb);
+    TriGeo t0, t1;
+    bool v0 = false, v1 = false;
+    if (live && !clip) {
+        int32_t X[4], Y[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) snap(cam, v[k], X[k], Y[k]);
+        v0 = make_tri(cam, false, X[0], Y[0], X[1], Y[1], X[2], Y[2], 0, cam.H, t0);
+        v1 = make_tri(cam, false, X[0], Y[0], X[2], Y[2], X[3], Y[3], 0, cam.H, t1);
+    }
+    return stage_tris(ws, v0, t0, v1, t1);
+}
+
+// The cheap test of one unit's strips (loaded by load_unit into q0, q1); the
+// survivors' camera-space corners go to the ring.
+__device__ __forceinline__ void road_unit(const Cam &cam, WaveSt &ws, bool live, int g, const float4 &q0,
+                                          const float4 &q1)
+{
+    float x[4], z[4];
+    ground_xz(cam, q0.x, q0.y, x[0], z[0]);
+    ground_xz(cam, q0.z, q0.w, x[1], z[1]);
+    ground_xz(cam, q1.x, q1.y, x[2], z[2]);
+    ground_xz(cam, q1.z, q1.w, x[3], z[3]);
+    const bool pass = live && !road_culled<false>(cam, x, z);
+    const unsigned long long bm = __ballot(pass);
+    if (pass) ws.ring[(ws.tail + lanes_below(bm)) & (kRing - 1)] = g;
+    ws.tail += __popcll(bm);
+}
+
+// strip data of unit u (lane l: strip l % 16 of surviving bin 4 u + l / 16)
+__device__ __forceinline__ bool load_unit(const DevSim &s, const SceneRec &sc, const RgbLds &L, int nsb, int u,
+                                          int &g, float4 &q0, float4 &q1)
+{
+    const int ln = (int)lane_id();
+    const int bi = 4 * u + (ln >> 4), k = ln & 15;
+    bool live = false;
+    if (u >= 0 && bi < nsb) {
+        const int pk = L.sbins[bi];
+        live = k < (pk & 127);
+        if (live) {
+            g = sc.road_base + (pk >> 7) + k;
+            q0 = s.roads[2 * g];
+            q1 = s.roads[2 * g + 1];
+        }
+    }
+    return live;
+}
+
+// ------------------------------------------------------------ boxes
+
+// One setup pass over box face candidates [c0, c0 + P) (P <= 64): candidate c
+// is face c % 6 of box surv[c / 6] (use_surv), or of box c / 6 culled here.
+// Fast triangles and clipped faces are appended to the box list at *nbt;
+// returns false (appending nothing) if the worst case would not fit.
+__device__ __forceinline__ bool box_pass(const DevSim &s, const SceneRec &sc, const Cam &cam, int ego, const RgbLds &L,
+                         lptr<const int32_t> surv, bool use_surv, int ncand, int c0, int P, int &nbt, int &bmin,
+                         int &bmax)
+{
+    const int ln = (int)lane_id();
+    const int c = c0 + ln;
+    bool live = ln < P && c < ncand;
+    int j = 0, f = 0;
+    if (live) {
+        j = use_surv ? surv[c / 6] : c / 6;
+        f = c - 6 * (c / 6);
+        if (!use_surv) live = j != ego && !box_outside(s, sc, cam, j);
+    }
+    Poly Pf;
+    TriRec t0, t1;
+    bool v0 = false, v1 = false, clip = false;
+    if (live) {
+        build_face(s, sc, cam, j, f, Pf);
+        fast_poly<true>(cam, Pf, 0, cam.H, t0, v0, t1, v1, clip);
+    }
+    const unsigned long long b0 = __ballot(v0), b1 = __ballot(v1), bc = __ballot(clip);
+    const int n0 = __popcll(b0), nf = n0 + __popcll(b1), ncl = __popcll(bc);
+    if (nbt + nf + kMaxTrisPerCand * ncl > L.bcap) return false;
+    if (v0) lds_store(L.btris + nbt + lanes_below(b0), t0);
+    if (v1) lds_store(L.btris + nbt + n0 + lanes_below(b1), t1);
+    if (v0) { bmin = min(bmin, (int)t0.g.j0); bmax = max(bmax, (int)t0.g.j1); }
+    if (v1) { bmin = min(bmin, (int)t1.g.j0); bmax = max(bmax, (int)t1.g.j1); }
+    nbt += nf;
+    if (clip) L.cq[lanes_below(bc)] = j * 8 + f;
+    wave_lds_order();
+    // the clipped faces, four per wavefront
+    for (int q0 = 0; q0 < ncl; q0 += 4) {
+        const int q = q0 + (ln >> 4);
+        const bool lv = q < ncl;
+        Poly Q = {};
+        if (lv) {
+            const int code = L.cq[q];
+            build_face(s, sc, cam, code >> 3, code & 7, Q);
+        }
+        TriRec t;
+        const bool ok = clip_seg<true>(cam, Q, lv, 0, cam.H, t);
+        const unsigned long long bo = __ballot(ok);
+        if (ok) {
+            lds_store(L.btris + nbt + lanes_below(bo), t);
+            bmin = min(bmin, (int)t.g.j0);
+            bmax = max(bmax, (int)t.g.j1);
+        }
+        nbt += __popcll(bo);
+    }
+    return true;
+}
+
+// The box unit: cull every box of the scene, list the survivors, set up their
+// faces into the view's box triangle list.  Publishes the list length, its
+// row range and whether it overflowed.
+__device__ __forceinline__ void do_boxes(const DevSim &s, const SceneRec &sc, const Cam &cam, int ego, const RgbLds &L,
+                         lptr<int32_t> surv)
+{
+    const int ln = (int)lane_id();
+    const int nbox = sc.n_agents + sc.n_static;
+    int ns = 0;
+    bool ovf = false;
+    for (int b0 = 0; b0 < nbox && !ovf; b0 += 64) {
+        const int j = b0 + ln;
+        const bool keep = j < nbox && j != ego && !box_outside(s, sc, cam, j);
+        const unsigned long long bm = __ballot(keep);
+        if (ns + __popcll(bm) > kSurvCap) {
+            ovf = true;          // more visible boxes than the list holds
+            break;
+        }
+        if (keep) surv[ns + lanes_below(bm)] = j;
+        ns += __popcll(bm);
+    }
+    wave_lds_order();
+    int nbt = 0, bmin = 0x7FFFFFFF, bmax = -1;
+    for (int c0 = 0; c0 < 6 * ns && !ovf; c0 += 64) {
+        if (!box_pass(s, sc, cam, ego, L, surv, true, 6 * ns, c0, 64, nbt, bmin, bmax)) {
+            ovf = true;
+            break;
+        }
+    }
+    bmin = wave_min(bmin);
+    bmax = wave_max(bmax);
+    if (ln == 0) {
+        L.cnt[R_NBT] = nbt;
+        L.cnt[R_BOVF] = ovf ? 1 : 0;
+        L.cnt[R_BMIN] = bmin;
+        L.cnt[R_BMAX] = bmax;
+    }
+}
+
+// Box fragments of the list's n triangles in rows [b0, b1) folded into the
+// key band.  The (triangle, row) items are dealt to the lanes by a prefix
+// over row counts, item passes shared out over the view's wavefronts (wave w
+// of nw takes passes w, w + nw, ...); each lane computes its item's exact
+// span; the spans are cut into pieces of up to 16 samples, which are dealt to
+// the lanes by a prefix over piece counts, and each lane folds its piece's
+// samples into the band with LDS atomic max.
+__device__ __forceinline__ void box_band(const RgbLds &L, const Cam &cam, lptr<unsigned long long> keys, int n,
+                                         int wv, int nwv, int b0, int b1)
+{
+    const int ln = (int)lane_id();
+    const int W = cam.W;
+    int pass = 0;
+    for (int t0 = 0; t0 < n; t0 += 64) {
+        const int t = t0 + ln;
+        int c = 0;
+        if (t < n) {
+            const int32_t jj = ((lptr<const int32_t>)(L.btris + t))[6];
+            const int j0 = max((int)(int16_t)(jj & 0xFFFF), b0), j1 = min(jj >> 16, b1 - 1);
+            c = max(0, j1 - j0 + 1);
+        }
+        const int incl = wave_incl_scan(c);
+        const int total = __builtin_amdgcn_readlane(incl, 63);
+        const int excl = incl - c;
+        for (int g0 = 0; g0 < total; g0 += 64, ++pass) {
+            if (pass % nwv != wv) continue;
+            const int gi = g0 + ln;
+            const int o = owner_of(incl, gi);
+            const int ex = __shfl(excl, o);
+            int xl = 0, xr = -1, j = 0;
+            float A = 0.0f, B = 0.0f, Cc = 0.0f;
+            uint32_t key = 0u;
+            if (gi < total) {
+                const TriRec tr = lds_load(L.btris + t0 + o);
+                j = max((int)tr.g.j0, b0) + (gi - ex);
+                if (!row_span(tr.g, j, W, xl, xr)) { xl = 0; xr = -1; }
+                A = tr.A; B = tr.B; Cc = tr.C; key = tr.keylo;
+            }
+            const int np = (xr - xl + 16) >> 4;            // pieces of up to 16 samples (0 if empty)
+            const int inc2 = wave_incl_scan(np);
+            const int npt = __builtin_amdgcn_readlane(inc2, 63);
+            const int ex2 = inc2 - np;
+            const float dv = ((float)j + 0.5f) - cam.cy;
+            for (int p0 = 0; p0 < npt; p0 += 64) {
+                const int pi = p0 + ln;
+                const int o2 = owner_of(inc2, pi);
+                const int k = pi - __shfl(ex2, o2);
+                const int sxl = __shfl(xl, o2), sxr = __shfl(xr, o2), sj = __shfl(j, o2);
+                const float sA = __shfl(A, o2), sB = __shfl(B, o2), sC = __shfl(Cc, o2), sdv = __shfl(dv, o2);
+                const uint32_t skey = (uint32_t)__shfl((int)key, o2);
+                const int i0 = sxl + 16 * k, i1 = pi < npt ? min(i0 + 15, sxr) : i0 - 1;
+                lptr<unsigned long long> row = keys + (size_t)(sj - b0) * W;
+                for (int i = i0; i <= i1; ++i) {
+                    const float du = ((float)i + 0.5f) - cam.cx;
+                    const float invz = fmaf(sA, du, fmaf(sB, sdv, sC));
+                    if (invz > 0.0f) lds_max64(row + i, ((unsigned long long)__float_as_uint(invz) << 32) | skey);
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ box rows by group masks
+//
+// The box rows [c0, c1) without a key band: the exact span of every (box
+// triangle, row) item is computed once and stored, and every group of 16
+// samples of a row gets a mask of the triangles whose span meets it.  The
+// resolve then walks, for its 16 samples, the triangles of its group's mask
+// and keeps the largest key of each sample in registers.  Memory (the free
+// region): the masks M[c1 - c0][W / 16][2], then the spans S[t][c1 - c0].
+constexpr int kMaskTris = 128;     // triangles a mask holds (two 64-bit words)
+
+__host__ __device__ inline int mask_rows_fit(int region, int n, int W)
+{
+    // rows per chunk so that the masks and a span of every triangle in every row fit
+    return region / (16 * (W / 16) + 4 * n);
+}
+
+__device__ __forceinline__ void box_spans(const RgbLds &L, const Cam &cam, int n, int c0, int c1, int wv, int nwv)
+{
+    const int ln = (int)lane_id();
+    const int R = c1 - c0, G = cam.W >> 4;
+    lptr<unsigned long long> M = (lptr<unsigned long long>)L.sbins;
+    lptr<int32_t> S = (lptr<int32_t>)(M + 2 * G * R);
+    int pass = 0;
+    for (int t0 = 0; t0 < n; t0 += 64) {
+        const int t = t0 + ln;
+        int c = 0;
+        if (t < n) {
+            const int32_t jj = ((lptr<const int32_t>)(L.btris + t))[6];
+            const int j0c = max((int)(int16_t)(jj & 0xFFFF), c0);
+            c = max(0, min(jj >> 16, c1 - 1) - j0c + 1);
+        }
+        const int incl = wave_incl_scan(c);
+        const int total = __builtin_amdgcn_readlane(incl, 63);
+        const int excl = incl - c;
+        for (int g0 = 0; g0 < total; g0 += 64, ++pass) {
+            if (pass % nwv != wv) continue;
+            const int gi = g0 + ln;
+            const int o = owner_of(incl, gi);
+            const int ex = __shfl(excl, o);
+            if (gi < total) {
+                const int tt = t0 + o;
+                const TriGeo tg = lds_load((lptr<TriGeo>)(L.btris + tt));
+                const int j = max((int)tg.j0, c0) + (gi - ex);
+                int xl, xr;
+                if (row_span(tg, j, cam.W, xl, xr)) {
+                    S[tt * R + (j - c0)] = xl | (xr << 16);
+                    lptr<unsigned long long> mrow = M + 2 * G * (j - c0) + (tt >> 6);
+                    const unsigned long long bit = 1ull << (tt & 63);
+                    for (int g = xl >> 4; g <= (xr >> 4); ++g) lds_or64(mrow + 2 * g, bit);
+                }
+            }
+        }
+    }
+}
+
+// 16 pixels' RGB (byte 0 red) packed into the 48 bytes of their samples
+__device__ __forceinline__ void store16(uint8_t *dst, const uint32_t *c)
+{
+    typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+    uint32_t w[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        // bytes 4k .. 4k + 3 belong to pixels p = 4k / 3 and p + 1
+        const int p = (4 * k) / 3;
+        uint32_t sel = 0;
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) {
+            const int b = 4 * k + bb, px = b / 3, ch = b - 3 * px;
+            sel |= (uint32_t)(px == p ? ch : 4 + ch) << (8 * bb);
+        }
+        w[k] = __builtin_amdgcn_perm(c[p + 1 < 16 ? p + 1 : 15], c[p], sel);
+    }
+    u4v *out = reinterpret_cast<u4v *>(dst);
+    out[0] = u4v{w[0], w[1], w[2], w[3]};
+    out[1] = u4v{w[4], w[5], w[6], w[7]};
+    out[2] = u4v{w[8], w[9], w[10], w[11]};
+}
+
+// rows [c0, c1) from the group masks and spans: 16 samples (48 bytes) per
+// task; tasks alternate over the view's wavefronts in blocks of 32 lanes so
+// that a few box rows still keep every wavefront busy
+__device__ __forceinline__ void resolve_masks(const RgbLds &L, const Cam &cam, uint8_t *img, uint32_t road_rgb,
+                                              uint32_t bg_rgb, int c0, int c1, int wv, int nwv)
+{
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    const int R = c1 - c0, G = cam.W >> 4;
+    lptr<const unsigned long long> M = (lptr<const unsigned long long>)L.sbins;
+    lptr<const int32_t> S = (lptr<const int32_t>)(M + 2 * G * R);
+    const int W = cam.W;
+    const int n = R * G;
+    const int ln = (int)lane_id();
+    const int half = ln >> 5, sub = ln & 31;
+    for (int blk = 2 * wv + half; 32 * blk < n; blk += 2 * nwv) {
+        const int task = 32 * blk + sub;
+        if (task >= n) continue;
+        const int r = task / G, g = task - r * G, i = g << 4, j = c0 + r;
+        const float dv = ((float)j + 0.5f) - cam.cy;
+        const float rz = fmaf(cam.road.B, dv, cam.road.C);
+        const uint32_t bits = rz > 0.0f ? (uint32_t)(L.bits[(size_t)j * L.nw + (i >> 6)] >> (i & 63)) & 0xFFFFu : 0u;
+        const uint32_t rzb = __float_as_uint(rz);
+        // sample offsets ((float)(i + m) + 0.5f) - cx are small exact values: du0 + m
+        const float du0 = ((float)i + 0.5f) - cam.cx;
+        unsigned long long best[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) best[m] = 0ull;
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            unsigned long long mk = M[2 * (G * r + g) + w];
+            while (mk != 0ull) {
+                const int t = 64 * w + (__ffsll((long long)mk) - 1);
+                mk &= mk - 1ull;
+                // span and plane read together (both depend on t only)
+                const int sp = S[t * R + r];
+                const f4v pk = *(lptr<const f4v>)((lptr<const unsigned char>)(L.btris + t) + 32);   // A B C keylo
+                // the span's samples within this group as a bit mask
+                const int lo = max((sp & 0xFFFF) - i, 0), hi = min((sp >> 16) - i, 15);
+                const uint32_t in = ((2u << hi) - 1u) & ~((1u << lo) - 1u);
+                const float bdv = fmaf(pk.y, dv, pk.z);
+                const uint32_t keylo = __float_as_uint(pk.w);
+#pragma unroll
+                for (int m = 0; m < 16; ++m) {
+                    const float invz = fmaf(pk.x, du0 + (float)m, bdv);
+                    const unsigned long long key = ((unsigned long long)__float_as_uint(invz) << 32) | keylo;
+                    best[m] = (((in >> m) & 1u) && invz > 0.0f && key > best[m]) ? key : best[m];
+                }
+            }
+        }
+        uint32_t c[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const unsigned long long kb = best[m];
+            const bool road = (bits >> m) & 1u;
+            const bool box = kb != 0ull && (!road || (uint32_t)(kb >> 32) >= rzb);
+            c[m] = road ? road_rgb : bg_rgb;
+            if (box) c[m] = L.pal[(uint32_t)kb & 0xFFu];
+        }
+        store16(img + 3 * ((int64_t)j * W + i), c);
+    }
+}
+
+// ------------------------------------------------------------ resolve
+
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+
+// rows [r0, r1) that no box fragment touches: 16 pixels (48 bytes) per lane
+// from the pattern table (road where the coverage bit is set and the row is
+// below the horizon, background elsewhere); two tasks per iteration so that
+// their LDS reads overlap
+__device__ __forceinline__ void resolve_lut(const RgbLds &L, const Cam &cam, uint8_t *img, int r0, int r1)
+{
+    const int W = cam.W, gpr = W >> 4;
+    const int n = (r1 - r0) * gpr;
+    const lptr<u4> lut = (lptr<u4>)L.lut;
+    const int B = (int)blockDim.x;
+    for (int task = (int)threadIdx.x; task < n; task += 2 * B) {
+        uint32_t bits[2];
+        u4 *out[2];
+        bool act[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int tk = task + h * B;
+            act[h] = tk < n;
+            const int tc = act[h] ? tk : task;
+            const int r = tc / gpr, i = (tc - r * gpr) << 4, j = r0 + r;
+            const float dv = ((float)j + 0.5f) - cam.cy;
+            const float rz = fmaf(cam.road.B, dv, cam.road.C);
+            bits[h] = rz > 0.0f ? (uint32_t)(L.bits[(size_t)j * L.nw + (i >> 6)] >> (i & 63)) & 0xFFFFu : 0u;
+            out[h] = reinterpret_cast<u4 *>(img + 3 * ((int64_t)j * W + i));
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t b = bits[h];
+            const u4 a = lut[b & 15u], bb = lut[(b >> 4) & 15u], c = lut[(b >> 8) & 15u], d = lut[b >> 12];
+            if (act[h]) {
+                out[h][0] = u4{a.x, a.y, a.z, bb.x};
+                out[h][1] = u4{bb.y, bb.z, c.x, c.y};
+                out[h][2] = u4{c.z, d.x, d.y, d.z};
+            }
+        }
+    }
+}
+
+// rows [b0, b1) of the key band: a box fragment wins where its 1/z is not
+// below the road's (agents rank above roads on equal depth); otherwise road
+// or background by the coverage bit
+__device__ __forceinline__ void resolve_band(const RgbLds &L, const Cam &cam, lptr<unsigned long long> keys, uint8_t *img,
+                             uint32_t road_rgb, uint32_t bg_rgb, int b0, int b1)
+{
+    const int W = cam.W, gpr = W >> 4;
+    const int n = (b1 - b0) * gpr;
+    for (int task = (int)threadIdx.x; task < n; task += (int)blockDim.x) {
+        const int r = task / gpr, i = (task - r * gpr) << 4, j = b0 + r;
+        const float dv = ((float)j + 0.5f) - cam.cy;
+        const float rz = fmaf(cam.road.B, dv, cam.road.C);
+        const bool rowok = rz > 0.0f;
+        const uint32_t bits = rowok ? (uint32_t)(L.bits[(size_t)j * L.nw + (i >> 6)] >> (i & 63)) & 0xFFFFu : 0u;
+        const uint32_t rzb = __float_as_uint(rz);
+        lptr<unsigned long long> kp = keys + (size_t)r * W + i;
+        uint32_t c[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const unsigned long long kb = kp[m];
+            const bool road = (bits >> m) & 1u;
+            const bool box = kb != 0ull && (!road || (uint32_t)(kb >> 32) >= rzb);
+            c[m] = box ? L.pal[(uint32_t)kb & 0xFFu] : (road ? road_rgb : bg_rgb);
+        }
+        u4 *out = reinterpret_cast<u4 *>(img + 3 * ((int64_t)j * W + i));
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            // 16 pixels = 48 bytes = 12 dwords; dword k holds bytes 4k .. 4k + 3
+            uint32_t w[4];
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const int k = 4 * q + d;     // dword index
+                uint32_t v = 0;
+#pragma unroll
+                for (int bb = 0; bb < 4; ++bb) {
+                    const int byte = 4 * k + bb, px = byte / 3, ch = byte - 3 * px;
+                    v |= ((c[px] >> (8 * ch)) & 0xFFu) << (8 * bb);
+                }
+                w[d] = v;
+            }
+            out[q] = u4{w[0], w[1], w[2], w[3]};
+        }
+    }
+}
+
+// ------------------------------------------------------------ per view
+
+template <int K>
+__device__ __forceinline__ void render_view_rgb(const DevSim &s, const RenderOut &o, const RgbLds &L, int view)
+{
+    constexpr int B = 64 * K;
+    const int tid = (int)threadIdx.x, ln = (int)lane_id(), wv = tid >> 6;
+    const int scene = __builtin_amdgcn_readfirstlane(s.views[view].scene);
+    const int ego_cam = __builtin_amdgcn_readfirstlane(s.views[view].ego_cam);
+    const SceneRec sc = uniform_scene(s.scenes[scene]);
+    const int ego = ego_cam >> 2;
+    const Cam cam = make_cam(s, sc, ego, ego_cam & 3);
+    const int W = cam.W, H = cam.H;
+
+    for (int p = tid; p < H * L.nw; p += B) L.bits[p] = 0ull;
+    if (tid < R_NCNT) L.cnt[tid] = 0;
+    __syncthreads();
+
+    // ---- A: road culling bins
+    for (int b0 = 64 * wv; b0 < sc.n_bins; b0 += B) {
+        const int b = b0 + ln;
+        bool keep = false;
+        int rec = 0;
+        if (b < sc.n_bins) {
+            const RoadBin bn = s.bins[sc.bin_base + b];
+            float x[4], z[4];
+            ground_xz(cam, bn.xmin, bn.ymin, x[0], z[0]);
+            ground_xz(cam, bn.xmax, bn.ymin, x[1], z[1]);
+            ground_xz(cam, bn.xmax, bn.ymax, x[2], z[2]);
+            ground_xz(cam, bn.xmin, bn.ymax, x[3], z[3]);
+            keep = !road_culled<true>(cam, x, z);
+            rec = bn.start * 128 + bn.count;
+        }
+        const unsigned long long bm = __ballot(keep);
+        const int nk = __popcll(bm);
+        int base = 0;
+        if (nk > 0) {
+            const int leader = __ffsll((long long)bm) - 1;
+            if (ln == leader) base = lds_add(L.cnt + R_NSB, nk);
+            base = __shfl(base, leader);
+        }
+        if (keep) L.sbins[base + lanes_below(bm)] = rec;
+    }
+    __syncthreads();
+
+    // ---- B: work units (0: boxes, u >= 1: surviving bins 4 (u - 1) .. 4 (u - 1) + 3)
+    const int nsb = L.cnt[R_NSB];
+    const int n_units = 1 + (nsb + 3) / 4;
+    lptr<unsigned char> wbase = L.waves + (size_t)wv * kWaveBytes;
+    WaveSt ws;
+    ws.tris = (lptr<TriGeo>)wbase;
+    ws.ring = (lptr<int32_t>)(wbase + kWTris * 32);
+    ws.clipq = (lptr<int32_t>)(wbase + kWTris * 32 + kRing * 4);
+    ws.head = ws.tail = ws.nclip = 0;
+    auto take = [&]() -> int {
+        int u = 0;
+        if (ln == 0) u = lds_add(L.cnt + R_NEXT, 1);
+        return __builtin_amdgcn_readfirstlane(__shfl(u, 0));
+    };
+    // One action per iteration, every part of the pipeline at one place in
+    // the code: clip when four strips wait, set up when a batch of 64 waits,
+    // else take the next unit (the box unit or four bins) and prefetch the
+    // strips of the one after it; at the end, drain the ring and the queue.
+    int u = take();
+    float4 q0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), q1 = q0;
+    int gq = 0;
+    bool live = load_unit(s, sc, L, nsb, u - 1, gq, q0, q1);
+    bool final = false;
+    for (;;) {
+        int ntri = 0;
+        if (ws.nclip >= 4 || (final && ws.nclip > 0)) {
+            ntri = road_clip(s, cam, ws);
+        } else if (ws.tail - ws.head >= 64 || (final && ws.tail > ws.head)) {
+            ntri = road_setup(s, cam, ws, min(64, ws.tail - ws.head));
+        } else if (!final) {
+            if (u >= n_units) {
+                final = true;
+                continue;
+            }
+            const int un = take();
+            float4 n0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), n1 = n0;
+            int gn = 0;
+            const bool nlive = load_unit(s, sc, L, nsb, un - 1, gn, n0, n1);
+            if (u == 0) {
+                // the box unit is the first one dealt: this wave's staging is still empty
+                do_boxes(s, sc, cam, ego, L, (lptr<int32_t>)ws.tris);
+            } else {
+                road_unit(cam, ws, live, gq, q0, q1);
+            }
+            u = un;
+            q0 = n0;
+            q1 = n1;
+            gq = gn;
+            live = nlive;
+            continue;
+        } else {
+            break;
+        }
+        if (ntri > 0) road_spans(L, cam, ws, ntri);
+    }
+    __syncthreads();
+
+    // ---- C: resolve
+    uint8_t *img = o.rgb + 3 * ((int64_t)view * W * H);
+    const int nbt = L.cnt[R_NBT];
+    const bool ovf = L.cnt[R_BOVF] != 0;
+    int kr0 = H, kr1 = H;          // rows that need the key band
+    if (ovf) {
+        kr0 = 0;
+    } else if (nbt > 0) {
+        kr0 = L.cnt[R_BMIN];
+        kr1 = L.cnt[R_BMAX] + 1;
+    }
+    resolve_lut(L, cam, img, 0, kr0);
+    resolve_lut(L, cam, img, kr1, H);
+    const uint32_t road_rgb = L.pal[s.road_color0], bg_rgb = L.pal[0];
+    const int mrows = mask_rows_fit(L.region, nbt, W);
+    if (!ovf && nbt <= kMaskTris && mrows >= 1) {
+        // box rows through row masks, in chunks of rows whose items fit
+        for (int c0 = kr0; c0 < kr1; c0 += mrows) {
+            const int c1 = min(c0 + mrows, kr1);
+            __syncthreads();
+            lptr<unsigned long long> M = (lptr<unsigned long long>)L.sbins;
+            for (int p = tid; p < 2 * (W >> 4) * (c1 - c0); p += B) M[p] = 0ull;
+            __syncthreads();
+            box_spans(L, cam, nbt, c0, c1, wv, K);
+            __syncthreads();
+            resolve_masks(L, cam, img, road_rgb, bg_rgb, c0, c1, wv, K);
+        }
+        return;
+    }
+    // the key band path: lists that overflowed (streamed through the list)
+    lptr<unsigned long long> keys = (lptr<unsigned long long>)L.sbins;   // free after the units
+    for (int b0 = kr0; b0 < kr1; b0 += L.krows) {
+        const int b1 = min(b0 + L.krows, kr1);
+        __syncthreads();
+        for (int p = tid; p < (b1 - b0) * W; p += B) keys[p] = 0ull;
+        __syncthreads();
+        if (!ovf) {
+            box_band(L, cam, keys, nbt, wv, K, b0, b1);
+        } else if (wv == 0) {
+            // the list could not hold every box triangle: stream the box
+            // faces through it eight candidates at a time (at most 96
+            // triangles per pass), culling the boxes again
+            const int ncand = 6 * (sc.n_agents + sc.n_static);
+            for (int c0 = 0; c0 < ncand; c0 += 8) {
+                int n = 0, bmn = 0, bmx = 0;
+                (void)box_pass(s, sc, cam, ego, L, (lptr<const int32_t>)L.sbins, false, ncand, c0, 8, n, bmn, bmx);
+                wave_lds_order();
+                box_band(L, cam, keys, n, 0, 1, b0, b1);
+                wave_lds_order();
+            }
+        }
+        __syncthreads();
+        resolve_band(L, cam, keys, img, road_rgb, bg_rgb, b0, b1);
+    }
+}
+
+__device__ __forceinline__ void carve_rgb(unsigned char *smem, RgbLds &L, int W, int H, const RgbCfg &c)
+{
+    const RgbLayout l = rgb_layout(W, H, c);
+    L.cnt = (lptr<int32_t>)(smem + l.cnt);
+    L.pal = (lptr<uint32_t>)(smem + l.pal);
+    L.lut = (lptr<uint32_t>)(smem + l.lut);
+    L.bits = (lptr<unsigned long long>)(smem + l.bits);
+    L.btris = (lptr<TriRec>)(smem + l.btris);
+    L.sbins = (lptr<int32_t>)(smem + l.sbins);
+    L.cq = (lptr<int32_t>)(smem + l.cq);
+    L.waves = (lptr<unsigned char>)(smem + l.waves);
+    L.nw = (W + 63) >> 6;
+    L.bcap = c.bcap;
+    // the key band takes the surviving-bin list, the box clip queue and the
+    // waves' staging, all idle by then
+    L.region = (int)(l.total - l.sbins);
+    L.krows = max(1, L.region / (8 * W));
+}
+
+__device__ __forceinline__ void load_palette_rgb(const DevSim &s, const RgbLds &L)
+{
+    auto rgb_of = [&](int idx) -> uint32_t {
+        return (uint32_t)s.palette[3 * idx] | ((uint32_t)s.palette[3 * idx + 1] << 8) |
+               ((uint32_t)s.palette[3 * idx + 2] << 16);
+    };
+    for (int p = threadIdx.x; p < 256; p += blockDim.x) L.pal[p] = rgb_of(p);
+    if (threadIdx.x < 16) {
+        // pattern b: pixel k is road where bit k of b is set, background elsewhere
+        const uint32_t road = rgb_of(s.road_color0), bg = rgb_of(0);
+        const int b = threadIdx.x;
+        const uint32_t c0 = (b & 1) ? road : bg, c1 = (b & 2) ? road : bg;
+        const uint32_t c2 = (b & 4) ? road : bg, c3 = (b & 8) ? road : bg;
+        L.lut[4 * b + 0] = c0 | (c1 << 24);
+        L.lut[4 * b + 1] = (c1 >> 8) | (c2 << 16);
+        L.lut[4 * b + 2] = (c2 >> 16) | (c3 << 8);
+        L.lut[4 * b + 3] = 0u;
+    }
+}
+
+// mode 0: view view_begin + blockIdx.x; 1: view order[blockIdx.x]; 2: the
+// persistent work queue
+template <int K>
+__global__ __launch_bounds__(64 * K) __attribute__((amdgpu_waves_per_eu(4))) void k_render_rgb(DevSim s, RenderOut o, RgbCfg c, int mode, int view_begin)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    RgbLds L;
+    carve_rgb(smem, L, s.width, s.height, c);
+    load_palette_rgb(s, L);
+    __shared__ int s_item;
+    if (mode != 2) {
+        __syncthreads();
+        const int view = mode == 0 ? view_begin + (int)blockIdx.x : s.order[blockIdx.x];
+        render_view_rgb<K>(s, o, L, view);
+        return;
+    }
+    int cur = (int)(blockIdx.x % kQueues);
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = queue_take(s, cur);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
+        if (it >= s.n_views) break;
+        render_view_rgb<K>(s, o, L, s.queue[it]);
+    }
+    if (threadIdx.x == 0) queue_leave(s);
+}
+
+}  // namespace
+
+size_t rgb_lds_bytes(int width, int height, const RgbCfg &c) { return rgb_layout(width, height, c).total; }
+
+hipError_t launch_render_rgb(const DevSim &s, const RenderOut &o, const RgbCfg &c, int mode, int view_begin,
+                             int grid, hipStream_t st)
+{
+    if (grid <= 0) return hipSuccess;
+    const size_t lds = rgb_lds_bytes(s.width, s.height, c);
+    switch (c.waves) {
+    case 1: hipLaunchKernelGGL(k_render_rgb<1>, dim3(grid), dim3(64), lds, st, s, o, c, mode, view_begin); break;
+    case 2: hipLaunchKernelGGL(k_render_rgb<2>, dim3(grid), dim3(128), lds, st, s, o, c, mode, view_begin); break;
+    case 4: hipLaunchKernelGGL(k_render_rgb<4>, dim3(grid), dim3(256), lds, st, s, o, c, mode, view_begin); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gp

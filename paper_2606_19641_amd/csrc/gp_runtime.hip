@@ -49,7 +49,7 @@ constexpr float kBinExtent = 32.0f;   // metres
 struct Layout {
     int64_t halted, infr, actu, signals, signal_color;
     int64_t scenes, views, state, cs, dims, agent_color, roads, road_index, road_color, bins, palette,
-        queue, counter;
+        queue, order, counter;
     int64_t total;
     int64_t n_agents, n_roads, n_views, n_bins, n_static, n_signals;
 };
@@ -148,6 +148,7 @@ Layout make_layout(const gp_config *cfg, const gp_scene_desc *sc, int32_t n)
     L.signals = take(16 * L.n_signals);
     L.signal_color = take(L.n_signals);
     L.queue = take(4 * L.n_views);
+    L.order = take(4 * L.n_views);
     L.counter = take(4 * (gp::kQueues + 2));
     L.total = o;
     return L;
@@ -159,7 +160,9 @@ bool valid_launch(const gp_launch &l)
     const bool bt = l.batch_tris == 256 || l.batch_tris == 512 || l.batch_tris == 1024 || l.batch_tris == 2048;
     const bool th = l.block_threads == 256 || l.block_threads == 512 || l.block_threads == 1024;
     const bool sc = l.sched == GP_SCHED_PLAIN || l.sched == GP_SCHED_PERSISTENT;
-    return br && bt && th && sc && l.blocks_per_cu >= 1 && l.blocks_per_cu <= 16;
+    const bool ra = l.raster == GP_RASTER_BANDED || l.raster == GP_RASTER_SPLIT;
+    const bool vw = l.view_waves == 1 || l.view_waves == 2 || l.view_waves == 4;
+    return br && bt && th && sc && ra && vw && l.blocks_per_cu >= 1 && l.blocks_per_cu <= 16;
 }
 
 // 2-D Morton code of 16-bit coordinates
@@ -268,6 +271,7 @@ struct gp_sim {
     uint8_t *g_rgb = nullptr;
     gp_launch g_launch{};
     int32_t road_uniform = 0;   // every road strip of every scene has one colour
+    int32_t bins_cap = 1;       // culling bins of the largest scene
 };
 
 namespace {
@@ -290,18 +294,43 @@ gp_status check_lds(const gp_sim *sim, const gp_launch &l)
     return GP_OK;
 }
 
+// box triangles one view's list holds in the split rasteriser (at least the
+// 96 that its streaming pass can need)
+constexpr int kSplitBoxTris = 96;
+
+gp::RgbCfg rgb_cfg(const gp_sim *sim, const gp_launch &l)
+{
+    gp::RgbCfg c;
+    c.waves = l.view_waves;
+    c.bcap = kSplitBoxTris;
+    c.bins_cap = sim->bins_cap;
+    return c;
+}
+
+// can this render take the split rasteriser?
+bool split_ok(const gp_sim *sim, const gp::RenderOut &o, const gp_launch &l, int kind)
+{
+    return l.raster == GP_RASTER_SPLIT && kind == 1 && sim->cfg.width % 16 == 0 &&
+           reinterpret_cast<uintptr_t>(o.rgb) % 16 == 0 && sim->cfg.cam_height > 0.0f &&
+           gp::rgb_lds_bytes(sim->cfg.width, sim->cfg.height, rgb_cfg(sim, l)) <= sim->max_lds;
+}
+
 gp_status render_impl(gp_sim *sim, const gp::RenderOut &o, const gp_launch &l, hipStream_t st)
 {
     const gp::LaunchCfg c = launch_cfg(l);
-    // the rgb-only kernel serves renders without depth / primitive id when
+    // the rgb-only kernels serve renders without depth / primitive id when
     // every road strip has the same colour; everything else takes the general one
     // (scenes with traffic lights take the general kernel's instances with lights)
     const int kind = sim->lay.n_signals > 0 ? 2 : (!o.depth && !o.primid && sim->dev.road_color_uniform) ? 1 : 0;
+    const bool split = split_ok(sim, o, l, kind);
+    const gp::RgbCfg rc = rgb_cfg(sim, l);
     hipError_t e;
     if (l.sched == GP_SCHED_PLAIN) {
         for (int s = 0; s < sim->n_scenes; ++s) {
             const gp::SceneRec &r = sim->scenes[s];
-            e = gp::launch_render(sim->dev, o, c, kind, 0, r.view_base, r.n_agents * sim->cfg.n_cams, st);
+            const int nv = r.n_agents * sim->cfg.n_cams;
+            e = split ? gp::launch_render_rgb(sim->dev, o, rc, 0, r.view_base, nv, st)
+                      : gp::launch_render(sim->dev, o, c, kind, 0, r.view_base, nv, st);
             if (e != hipSuccess) return hip_fail(e, "render launch");
         }
         return GP_OK;
@@ -311,9 +340,11 @@ gp_status render_impl(gp_sim *sim, const gp::RenderOut &o, const gp_launch &l, h
         // every view gets a workgroup of its own: one launch over all views,
         // without the queue (whose empty segments would cost each workgroup a
         // chain of device-scope atomics before it finds its view)
-        e = gp::launch_render(sim->dev, o, c, kind, 0, 0, (int)sim->lay.n_views, st);
+        e = split ? gp::launch_render_rgb(sim->dev, o, rc, 1, 0, (int)sim->lay.n_views, st)
+                  : gp::launch_render(sim->dev, o, c, kind, 0, 0, (int)sim->lay.n_views, st);
     } else {
-        e = gp::launch_render(sim->dev, o, c, kind, 1, 0, (int)resident, st);
+        e = split ? gp::launch_render_rgb(sim->dev, o, rc, 2, 0, (int)resident, st)
+                  : gp::launch_render(sim->dev, o, c, kind, 1, 0, (int)resident, st);
     }
     if (e != hipSuccess) return hip_fail(e, "render launch");
     return GP_OK;
@@ -346,7 +377,8 @@ void drop_graph(gp_sim *sim)
 bool same_launch(const gp_launch &a, const gp_launch &b)
 {
     return a.sched == b.sched && a.band_rows == b.band_rows && a.batch_tris == b.batch_tris &&
-           a.block_threads == b.block_threads && a.blocks_per_cu == b.blocks_per_cu;
+           a.block_threads == b.block_threads && a.blocks_per_cu == b.blocks_per_cu && a.raster == b.raster &&
+           a.view_waves == b.view_waves;
 }
 
 }  // namespace
@@ -459,6 +491,7 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
         abase += d.n_agents;
         rbase += d.n_roads;
         bbase += (int32_t)sb.size();
+        sim->bins_cap = std::max<int32_t>(sim->bins_cap, (int32_t)sb.size());
     }
     std::memcpy(at(L.scenes), sim->scenes.data(), sizeof(gp::SceneRec) * n_scenes);
     std::memcpy(at(L.palette), cfg->palette, 768);
@@ -492,6 +525,22 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
         }
     }
     sim->dev.qseg[gp::kQueues] = (int32_t)qi;
+    // direct order: workgroup b (dispatched to XCD b mod kQueues) renders the
+    // next view of segment b mod kQueues; once that segment is used up, the
+    // next view of the segment with the most views left
+    {
+        auto *ord = reinterpret_cast<int32_t *>(at(L.order));
+        std::vector<int64_t> next(gp::kQueues);
+        for (int q = 0; q < gp::kQueues; ++q) next[q] = sim->dev.qseg[q];
+        auto left = [&](int q) { return (int64_t)sim->dev.qseg[q + 1] - next[q]; };
+        for (int64_t b = 0; b < L.n_views; ++b) {
+            int q = (int)(b % gp::kQueues);
+            if (left(q) == 0)
+                for (int r = 0; r < gp::kQueues; ++r)
+                    if (left(r) > left(q)) q = r;
+            ord[b] = queue[next[q]++];
+        }
+    }
 
     unsigned char *base = static_cast<unsigned char *>(d_workspace);
     hipStream_t hs = static_cast<hipStream_t>(stream);
@@ -517,6 +566,7 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
     D.signals = reinterpret_cast<const float4 *>(base + L.signals);
     D.signal_color = base + L.signal_color;
     D.queue = reinterpret_cast<const int32_t *>(base + L.queue);
+    D.order = reinterpret_cast<const int32_t *>(base + L.order);
     D.counter = reinterpret_cast<uint32_t *>(base + L.counter);
     D.n_scenes = n_scenes;
     D.n_agents = (int32_t)L.n_agents;
@@ -566,6 +616,19 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
     l.batch_tris = 256;
     l.block_threads = 256;
     l.blocks_per_cu = 3;
+    // rgb renders take the split rasteriser (two wavefronts per view, eight
+    // views per CU) where it can run
+    l.raster = GP_RASTER_BANDED;
+    l.view_waves = 2;
+    {
+        gp_launch t = l;
+        t.raster = GP_RASTER_SPLIT;
+        if (cfg->width % 16 == 0 && cfg->cam_height > 0.0f &&
+            gp::rgb_lds_bytes(cfg->width, cfg->height, rgb_cfg(sim, t)) * 8 <= 160u * 1024u) {
+            l.raster = GP_RASTER_SPLIT;
+            l.blocks_per_cu = 8;
+        }
+    }
     sim->launch = l;
     if (check_lds(sim, l) != GP_OK) { delete sim; return GP_EINVAL; }
     e = hipStreamCreateWithFlags(&sim->capture_stream, hipStreamNonBlocking);

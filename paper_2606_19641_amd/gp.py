@@ -52,7 +52,8 @@ class SceneDesc(C.Structure):
 
 class Launch(C.Structure):
     _fields_ = [("sched", C.c_int32), ("band_rows", C.c_int32), ("batch_tris", C.c_int32),
-                ("block_threads", C.c_int32), ("blocks_per_cu", C.c_int32)]
+                ("block_threads", C.c_int32), ("blocks_per_cu", C.c_int32), ("raster", C.c_int32),
+                ("view_waves", C.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

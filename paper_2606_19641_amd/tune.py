@@ -103,7 +103,12 @@ def tune(sim, scenes, space: Dict[str, Iterable[int]] = DEFAULT_SPACE, reps: int
     warm_up(sim, rgb_ref)
     # two interleaved passes over every setting, each keeping its faster time,
     # so that a drift of the clocks during the search favours none of them
-    settings = [dict(base)] + [c for c in candidates(space) if c != base]
+    settings = [dict(base)]
+    for c in candidates(space):
+        full = dict(base)
+        full.update(c)
+        if full not in settings:
+            settings.append(full)
     times = [float("inf")] * len(settings)
     ok = [True] * len(settings)
     report = []
