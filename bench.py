@@ -295,7 +295,6 @@ def main():
     E = EPISODE_STEPS
     state0 = sim.get_state()
     acts = torch.from_numpy(np.stack([g.batch_actions(w.seed, k, w.scenes) for k in range(E)])).to(dev)
-    act_buf = torch.empty_like(acts[0])
     rgb = sim.new_rgb()
     stream = torch.cuda.current_stream()
 
@@ -303,8 +302,7 @@ def main():
         """Step k of the run (episode step k mod E) as one graph replay."""
         if k % E == 0:
             sim.set_state(state0)
-        act_buf.copy_(acts[k % E])
-        sim.step_render_graph(act_buf, rgb)
+        sim.step_render_graph(acts[k % E], rgb)
 
     if args.tuned:
         sim.set_launch(**json.loads(args.tuned))
@@ -338,8 +336,7 @@ def main():
     for k in range(K):
         if k and k % E == 0:
             sim.set_state(state0)
-        act_buf.copy_(acts[k % E])
-        sim.step_render_graph(act_buf, rgb)
+        sim.step_render_graph(acts[k % E], rgb)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     batched = V * K / wall
@@ -352,8 +349,7 @@ def main():
         if k % E == 0:
             sim.set_state(state0)
         lev[k][0].record(stream)
-        act_buf.copy_(acts[k % E])
-        sim.step_render_graph(act_buf, rgb)
+        sim.step_render_graph(acts[k % E], rgb)
         lev[k][1].record(stream)
     torch.cuda.synchronize()
     lat_ms = np.array([a.elapsed_time(b) for a, b in lev])

@@ -118,10 +118,16 @@ typedef enum {
 typedef enum {
     GP_RASTER_BANDED = 0,     /* one workgroup of block_threads per view; LDS key bands of
                                  band_rows rows; triangle lists of batch_tris             */
-    GP_RASTER_SPLIT = 1       /* view_waves wavefronts per view sharing the view's work
+    GP_RASTER_SPLIT = 1,      /* view_waves wavefronts per view sharing the view's work
                                  through an LDS work counter; about 19 KB of LDS per view
                                  at 128 x 128; needs width % 16 == 0 and a 16-byte aligned
                                  image (else the banded rasteriser runs)                  */
+    GP_RASTER_CHIP = 2        /* three chip-wide passes: per-view setup (bin culling, box
+                                 triangle lists), road items over the whole chip (coverage
+                                 bitmasks in the workspace), resolve items of whole rows;
+                                 road_wgs_per_cu workgroups per CU for the road pass;
+                                 needs width % 16 == 0, 64 <= width <= 1024 and a 16-byte
+                                 aligned image (else the banded rasteriser runs)          */
 } gp_raster;
 
 typedef struct {
@@ -132,6 +138,7 @@ typedef struct {
     int32_t blocks_per_cu;    /* persistent grid = blocks_per_cu * CUs (1..16)         */
     int32_t raster;           /* gp_raster                                            */
     int32_t view_waves;       /* split: wavefronts per view: 1, 2 or 4                 */
+    int32_t road_wgs_per_cu;  /* chip: road-pass workgroups (4 wavefronts) per CU, 1..16 */
 } gp_launch;
 
 /* Workspace bytes needed for these scenes (>= 0), or -1 on bad arguments. */
@@ -158,9 +165,11 @@ gp_status gp_sim_step(gp_sim *sim, const float *d_actions, void *stream);
  * [num_views][height][width][3] (required).  d_depth: optional device float
  * [num_views][height][width], planar depth in m, +inf for background.
  * d_primid: optional device int32 [num_views][height][width], -1 for
- * background, else 6*agent + face (0 front, 1 left, 2 back, 3 right, 4 top,
- * 5 bottom) for boxes and 6*n_agents + road for road strips, indices local
- * to the scene. */
+ * background, else 6*box + face (0 front, 1 left, 2 back, 3 right, 4 top,
+ * 5 bottom) for boxes (box = agent, or n_agents + k for static obstacle k),
+ * 6*(n_agents + n_static) + road for road strips and, after the roads,
+ * 6*(n_agents + n_static) + n_roads + light for traffic lights; indices
+ * local to the scene. */
 gp_status gp_sim_render(gp_sim *sim, uint8_t *d_rgb, float *d_depth, int32_t *d_primid, void *stream);
 
 /* Render every view with the ray-cast backend (App. A: the renderer can
@@ -175,9 +184,11 @@ gp_status gp_sim_render(gp_sim *sim, uint8_t *d_rgb, float *d_depth, int32_t *d_
  * differ.  Arguments as gp_sim_render (rgb need not be 4-byte aligned). */
 gp_status gp_sim_render_raycast(gp_sim *sim, uint8_t *d_rgb, float *d_depth, int32_t *d_primid, void *stream);
 
-/* Step then render (rgb only) as one hipGraph replay.  The graph is captured
- * on first use and re-captured when a pointer or the launch settings change.
- * Uses the persistent schedule whatever the current launch setting. */
+/* Step then render (rgb only) as one hipGraph replay.  The graph is built on
+ * first use and rebuilt when the image pointer or the launch settings change;
+ * a new d_actions pointer only updates the step node's arguments, so callers
+ * may pass each step's own action buffer without a copy.  Uses the persistent
+ * schedule whatever the current launch setting. */
 gp_status gp_sim_step_render_graph(gp_sim *sim, const float *d_actions, uint8_t *d_rgb, void *stream);
 
 /* Traffic-light states: d_colors, device uint8 [num_signals], the palette

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgigapix.so")
-SOURCES = ["gp_kernels.hip", "gp_raster.hip", "gp_raycast.hip", "gp_runtime.hip"]
+SOURCES = ["gp_kernels.hip", "gp_raster.hip", "gp_chip.hip", "gp_raycast.hip", "gp_runtime.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-fno-gpu-rdc",

@@ -12,6 +12,10 @@ constexpr int kMaxCams = 4;
 constexpr int kBinQuads = 16;            // road strips per culling bin
 constexpr int kMaxPrims = 1 << 23;       // primitives per scene (key packs 23 bits)
 constexpr int kQueues = 8;               // work-queue segments, one per XCD of the MI355X
+// Spacing of the queue's counters in 32-bit words: one counter per 256 bytes.
+// Device-scope atomics on one cache line serialise (about 12 ns each on the
+// MI355X), on distinct lines they proceed in parallel.
+constexpr int kCtrStride = 64;
 
 // Per-scene record.
 struct SceneRec {
@@ -60,8 +64,9 @@ struct DevSim {
     const int32_t *queue;     // [V] view order for the persistent schedule, kQueues segments
     const int32_t *order;     // [V] view of workgroup b when every view has a workgroup: consecutive
                               // workgroups (which go to the XCDs in turn) take the segments in turn
-    uint32_t *counter;        // [kQueues + 2] segment heads, finished workgroups, exhausted
-                              // segment mask (all zero between launches)
+    uint32_t *counter;        // [(kQueues + 2) * kCtrStride] segment heads, finished workgroups,
+                              // exhausted segment mask, kCtrStride words apart (all zero
+                              // between launches)
     int32_t qseg[kQueues + 1];// segment q of the queue is [qseg[q], qseg[q + 1])
     int32_t n_scenes, n_agents, n_views;
     int32_t n_boxes;          // A + S
@@ -107,9 +112,30 @@ struct RgbCfg {
     int bins_cap;     // culling bins of the largest scene (surviving bins are listed in LDS)
 };
 
+// Buffers of the chip-wide rgb raster (gp_chip.hip), all inside the
+// workspace.  The coverage words and the counters are zero between renders.
+enum { CHIP_NITEMS = 0, CHIP_NCTL = 8 };
+struct ChipBufs {
+    unsigned long long *cov;  // [V][H][nw] road coverage: bit i of word w of a row is sample 64 w + i
+    int32_t *sbins;           // [V][bins_stride] surviving culling bins: start * 128 + count
+    int4 *vinfo;              // [V] surviving bins, box triangles (-1: the list overflowed), box rows min, max
+    void *btri;               // [V][btri_cap] the view's box triangles (TriRec)
+    int4 *rinfo;              // [V] road triangles appended (may pass rtri_cap), coverage words used, 0, 0
+    void *rtri;               // [V][rtri_cap] the view's road triangles (TriGeo)
+    int32_t *rrows;           // [V][rtri_cap] their sample rows j0 | j1 << 16
+    uint2 *items;             // road work items (view, unit of four surviving bins)
+    uint32_t *ctl;            // [CHIP_NCTL] road item count (the others unused)
+    int32_t bins_stride, btri_cap, rtri_cap, nw, rows_per_item, items_per_view;
+};
+
 // Host-side launch helpers (defined in gp_kernels.hip and gp_raster.hip).
 hipError_t launch_step(const DevSim &s, const float *actions, int agent_begin, int agent_count,
                        hipStream_t st);
+// The direct step of every agent as a graph kernel node: added to g when exec
+// is null (the node returned in *node), else the arguments of *node in the
+// instantiated graph exec replaced (a new action buffer, no re-capture).
+hipError_t step_graph_node(hipGraph_t g, hipGraphExec_t exec, hipGraphNode_t *node, const DevSim &s,
+                           const float *actions);
 // clear_halted = 1 also clears the halted flags and the jerk actuators
 hipError_t launch_cs(const DevSim &s, int clear_halted, hipStream_t st);
 // jerk-actuated step of every agent; actions [A] uint8 indices 0..11
@@ -133,6 +159,13 @@ size_t raycast_lds_bytes();
 hipError_t launch_render_rgb(const DevSim &s, const RenderOut &o, const RgbCfg &c, int mode, int view_begin,
                              int grid, hipStream_t st);
 size_t rgb_lds_bytes(int width, int height, const RgbCfg &c);
+// chip-wide rgb raster (gp_chip.hip), same conditions as the wave-split one
+// plus 64 <= width <= 1024: the setup pass over views [view_begin,
+// view_begin + n_views) (mode 0) or every view in order[] (mode 1), the road
+// pass on road_grid workgroups, the resolve pass on a workgroup per group of
+// sixteen tiles of a view
+hipError_t launch_render_chip(const DevSim &s, const RenderOut &o, const ChipBufs &cb, int mode, int view_begin,
+                              int n_views, int road_grid, hipStream_t st);
 // batched (serving) launches over a device table of sims
 hipError_t launch_step_multi(const SimEntry *tab, int n_sims, int max_agents, hipStream_t st);
 hipError_t launch_render_multi(const SimEntry *tab, const int2 *items, int n_items, uint32_t *ctl,

@@ -644,6 +644,155 @@ __device__ __forceinline__ SceneRec uniform_scene(const SceneRec &r)
 }
 
 
+// ------------------------------------------------------------ wave helpers
+
+// inclusive prefix sum over the wavefront: Hillis-Steele within each row of
+// 16 lanes (DPP row shifts), then the row totals carried across rows (DPP row
+// broadcasts of lanes 15 and 31)
+__device__ __forceinline__ int wave_incl_scan(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);   // row_bcast:15 into rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);   // row_bcast:31 into rows 2, 3
+    return v;
+}
+
+// number of lanes whose inclusive prefix is <= g: the lane that owns item g
+__device__ __forceinline__ int owner_of(int incl, int g)
+{
+    int t = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1)
+        if (__shfl(incl, t + step - 1) <= g) t += step;
+    return min(t, 63);
+}
+
+__device__ __forceinline__ int wave_min(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ int lanes_below(unsigned long long m)
+{
+    return __popcll(m & ((1ull << lane_id()) - 1ull));
+}
+
+// keep the compiler from moving LDS accesses across this point (the
+// wavefront's own LDS operations execute in order)
+__device__ __forceinline__ void wave_lds_order() { __asm__ __volatile__("" ::: "memory"); }
+
+// ------------------------------------------------------------ road tests
+
+// Road points lie at camera height -h, so a road vertex at depth z snaps to
+// the row coordinate Y(z) = rint(fmaf(h / z, F256, CY256)), a non-increasing
+// function of z (correctly rounded division, fmaf and rint are monotone).
+// Every vertex a strip's clip can produce has a depth within
+// [max(zmin, z_near), min(zmax, z_far)] up to a rounding of the guard-band
+// crossings, so its triangles' sample rows lie among the rows whose sample
+// 256 j + 128 falls within [Y(zhi), Y(zlo)].  The estimate below uses the
+// hardware reciprocal; its error (below 2^-20 relative on the quotient term)
+// and the rounding of rint are covered by the margins.  True if no image row
+// has its sample in the widened range: then the set covers no sample.
+__device__ __forceinline__ bool road_rows_empty(const Cam &c, float zmin, float zmax)
+{
+    const float zlo = fmaxf(zmin, c.zn) * (1.0f - 0x1p-20f);
+    const float zhi = fminf(zmax, c.zf) * (1.0f + 0x1p-20f);
+    const float hF = c.h * c.F256;
+    const float ylo = fmaf(hF, __builtin_amdgcn_rcpf(zhi), c.CY256);
+    const float yhi = fmaf(hF, __builtin_amdgcn_rcpf(zlo), c.CY256);
+    const float a = fmaf(-fabsf(ylo), 0x1p-18f, ylo) - 4.0f;
+    const float b = fmaf(fabsf(yhi), 0x1p-18f, yhi) + 4.0f;
+    const float j0 = fmaxf(ceilf((a - 128.0f) * (1.0f / 256.0f)), 0.0f);
+    const float j1 = fminf(floorf((b - 128.0f) * (1.0f / 256.0f)), (float)(c.H - 1));
+    return !(j0 <= j1);
+}
+
+// Cheap rejection of a road strip (BIN false) or of a culling bin's bounding
+// box (BIN true) with camera-space corners (x[k], -h, z[k]): true only if it
+// certainly covers no sample.  The tests are the near, far and side tests of
+// outside() (same predicates and margins), the road depth limit of
+// road_beyond(), and the row-gap test.  A strip's corners are computed here
+// exactly as the setup computes them, so its near and far predicates are the
+// clipper's own; a bin's strips have corners inside its box, whose computed
+// depths can differ from the box corners' by rounding (below 2^-22 of
+// |x| + |z|), so a bin's depth tests carry that margin.
+template <bool BIN>
+__device__ __forceinline__ bool road_culled(const Cam &c, const float *x, const float *z)
+{
+    bool n = true, fa = true, l = true, r = true;
+    float zmin = INFINITY, zmax = -INFINITY;
+    const float zlim = fminf(c.road_zmax, c.zf);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float ax = fabsf(x[k]), az = fabsf(z[k]);
+        const float dz = BIN ? fmaf(ax + az, 0x1p-20f, 1e-6f) : 0.0f;
+        n = n && (z[k] - c.zn < -dz);
+        fa = fa && (z[k] - zlim > dz);
+        const float mx = 1e-3f * (ax + az) + 1e-6f;
+        r = r && (fmaf(-c.t_right, z[k], x[k]) > mx);
+        l = l && (fmaf(-c.t_left, z[k], -x[k]) > mx);
+        zmin = fminf(zmin, z[k] - dz);
+        zmax = fmaxf(zmax, z[k] + dz);
+    }
+    if (n || fa || l || r) return true;
+    return road_rows_empty(c, zmin, zmax);
+}
+
+// camera-space x and z of a ground point (world x, y)
+__device__ __forceinline__ void ground_xz(const Cam &c, float wx, float wy, float &x, float &z)
+{
+    const float dx = wx - c.px, dy = wy - c.py;
+    z = fmaf(dx, c.fx, dy * c.fy);
+    x = fmaf(dx, c.fy, -(dy * c.fx));
+}
+
+// camera-space corners of road slot g (global), as the setup computes them
+__device__ __forceinline__ void road_corners(const DevSim &s, const Cam &cam, int g, V3 *v)
+{
+    const float4 q0 = s.roads[2 * g], q1 = s.roads[2 * g + 1];
+    const float y = 0.0f - cam.h;
+    ground_xz(cam, q0.x, q0.y, v[0].x, v[0].z);
+    ground_xz(cam, q0.z, q0.w, v[1].x, v[1].z);
+    ground_xz(cam, q1.x, q1.y, v[2].x, v[2].z);
+    ground_xz(cam, q1.z, q1.w, v[3].x, v[3].z);
+    v[0].y = y; v[1].y = y; v[2].y = y; v[3].y = y;
+}
+
+// 16 pixels' RGB (byte 0 red) packed into the 48 bytes of their samples
+__device__ __forceinline__ void store16(uint8_t *dst, const uint32_t *c)
+{
+    typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+    uint32_t w[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        // bytes 4k .. 4k + 3 belong to pixels p = 4k / 3 and p + 1
+        const int p = (4 * k) / 3;
+        uint32_t sel = 0;
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) {
+            const int b = 4 * k + bb, px = b / 3, ch = b - 3 * px;
+            sel |= (uint32_t)(px == p ? ch : 4 + ch) << (8 * bb);
+        }
+        w[k] = __builtin_amdgcn_perm(c[p + 1 < 16 ? p + 1 : 15], c[p], sel);
+    }
+    u4v *out = reinterpret_cast<u4v *>(dst);
+    out[0] = u4v{w[0], w[1], w[2], w[3]};
+    out[1] = u4v{w[4], w[5], w[6], w[7]};
+    out[2] = u4v{w[8], w[9], w[10], w[11]};
+}
+
 // ------------------------------------------------------------ work queue
 
 // Take the next view of the persistent work queue: kQueues segments of the
@@ -651,16 +800,17 @@ __device__ __forceinline__ SceneRec uniform_scene(const SceneRec &r)
 // then read through one L2).  Workgroups are dispatched to the XCDs in turn,
 // so workgroup b starts on segment b mod kQueues (`cur`); an exhausted
 // segment is marked in the shared mask, which the same atomic returns, and
-// the caller moves on to the next segment not yet marked.  counter[q] is the
-// head of segment q, counter[kQueues] counts the workgroups that have left,
-// counter[kQueues + 1] is the exhausted mask.  Returns a queue position, or
+// the caller moves on to the next segment not yet marked.  counter[q k] is the
+// head of segment q, counter[kQueues k] counts the workgroups that have left,
+// counter[(kQueues + 1) k] is the exhausted mask (k = kCtrStride, one counter
+// per 256 bytes).  Returns a queue position, or
 // n_views when every segment is exhausted.  Called by one thread.
 __device__ __forceinline__ int queue_take(const DevSim &s, int &cur)
 {
     for (;;) {
-        const int pos = (int)atomicAdd(&s.counter[cur], 1u);
+        const int pos = (int)atomicAdd(&s.counter[cur * kCtrStride], 1u);
         if (pos < s.qseg[cur + 1] - s.qseg[cur]) return s.qseg[cur] + pos;
-        const uint32_t mask = atomicOr(&s.counter[kQueues + 1], 1u << cur) | (1u << cur);
+        const uint32_t mask = atomicOr(&s.counter[(kQueues + 1) * kCtrStride], 1u << cur) | (1u << cur);
         if (mask == (1u << kQueues) - 1u) return s.n_views;
         do cur = (cur + 1) % kQueues; while ((mask >> cur) & 1u);
     }
@@ -673,9 +823,9 @@ __device__ __forceinline__ int queue_take(const DevSim &s, int &cur)
 __device__ __forceinline__ void queue_leave(const DevSim &s)
 {
     __threadfence();
-    const uint32_t done = atomicAdd(&s.counter[kQueues], 1u);
+    const uint32_t done = atomicAdd(&s.counter[kQueues * kCtrStride], 1u);
     if (done == gridDim.x - 1) {
-        for (int q = 0; q < kQueues + 2; ++q) atomicExch(&s.counter[q], 0u);
+        for (int q = 0; q < kQueues + 2; ++q) atomicExch(&s.counter[q * kCtrStride], 0u);
         __threadfence();
     }
 }

@@ -1338,6 +1338,25 @@ hipError_t launch_step(const DevSim &s, const float *actions, int agent_begin, i
     return hipGetLastError();
 }
 
+hipError_t step_graph_node(hipGraph_t g, hipGraphExec_t exec, hipGraphNode_t *node, const DevSim &s,
+                           const float *actions)
+{
+    const int B = 256;
+    DevSim sv = s;
+    const float2 *act = reinterpret_cast<const float2 *>(actions);
+    int begin = 0, count = s.n_agents;
+    void *args[] = {&sv, &act, &begin, &count};
+    hipKernelNodeParams p{};
+    p.func = reinterpret_cast<void *>(k_step);
+    p.gridDim = dim3((count + B - 1) / B);
+    p.blockDim = dim3(B);
+    p.sharedMemBytes = 0;
+    p.kernelParams = args;
+    p.extra = nullptr;
+    if (exec) return hipGraphExecKernelNodeSetParams(exec, *node, &p);
+    return hipGraphAddKernelNode(node, g, nullptr, 0, &p);
+}
+
 hipError_t launch_step_jerk(const DevSim &s, const uint8_t *actions, hipStream_t st)
 {
     if (s.n_agents <= 0) return hipSuccess;

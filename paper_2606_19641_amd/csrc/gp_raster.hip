@@ -48,7 +48,8 @@ namespace {
 
 constexpr int kRing = 128;      // strips passed by the cheap test (road slot indices)
 constexpr int kWTris = 128;     // triangles staged for one span pass
-constexpr int kWClip = 68;      // road strips waiting for the clipper: a setup batch on top of < 4
+constexpr int kSetupBatch = kWTris / 2;   // strips set up at a time (two fan triangles each)
+constexpr int kWClip = kSetupBatch + 4;   // road strips waiting for the clipper: a setup batch on top of < 4
 constexpr int kWaveBytes = kRing * 4 + kWTris * 32 + kWClip * 4;
 static_assert(kWaveBytes % 16 == 0, "wave regions stay 16-byte aligned");
 static_assert(sizeof(TriGeo) == 32, "staged triangle size");
@@ -93,132 +94,6 @@ __host__ __device__ inline RgbLayout rgb_layout(int W, int H, const RgbCfg &c)
     l.waves = o; o = align16(o + (size_t)kWaveBytes * (size_t)c.waves);
     l.total = o;
     return l;
-}
-
-// ------------------------------------------------------------ wave helpers
-
-// inclusive prefix sum over the wavefront: Hillis-Steele within each row of
-// 16 lanes (DPP row shifts), then the row totals carried across rows (DPP row
-// broadcasts of lanes 15 and 31)
-__device__ __forceinline__ int wave_incl_scan(int v)
-{
-    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);   // row_shr:1
-    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);   // row_shr:2
-    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);   // row_shr:4
-    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);   // row_shr:8
-    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);   // row_bcast:15 into rows 1, 3
-    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);   // row_bcast:31 into rows 2, 3
-    return v;
-}
-
-// number of lanes whose inclusive prefix is <= g: the lane that owns item g
-__device__ __forceinline__ int owner_of(int incl, int g)
-{
-    int t = 0;
-#pragma unroll
-    for (int step = 32; step > 0; step >>= 1)
-        if (__shfl(incl, t + step - 1) <= g) t += step;
-    return min(t, 63);
-}
-
-__device__ __forceinline__ int wave_min(int v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
-    return v;
-}
-
-__device__ __forceinline__ int wave_max(int v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-    return v;
-}
-
-__device__ __forceinline__ int lanes_below(unsigned long long m)
-{
-    return __popcll(m & ((1ull << lane_id()) - 1ull));
-}
-
-// keep the compiler from moving LDS accesses across this point (the
-// wavefront's own LDS operations execute in order)
-__device__ __forceinline__ void wave_lds_order() { __asm__ __volatile__("" ::: "memory"); }
-
-// ------------------------------------------------------------ road tests
-
-// Road points lie at camera height -h, so a road vertex at depth z snaps to
-// the row coordinate Y(z) = rint(fmaf(h / z, F256, CY256)), a non-increasing
-// function of z (correctly rounded division, fmaf and rint are monotone).
-// Every vertex a strip's clip can produce has a depth within
-// [max(zmin, z_near), min(zmax, z_far)] up to a rounding of the guard-band
-// crossings, so its triangles' sample rows lie among the rows whose sample
-// 256 j + 128 falls within [Y(zhi), Y(zlo)].  The estimate below uses the
-// hardware reciprocal; its error (below 2^-20 relative on the quotient term)
-// and the rounding of rint are covered by the margins.  True if no image row
-// has its sample in the widened range: then the set covers no sample.
-__device__ __forceinline__ bool road_rows_empty(const Cam &c, float zmin, float zmax)
-{
-    const float zlo = fmaxf(zmin, c.zn) * (1.0f - 0x1p-20f);
-    const float zhi = fminf(zmax, c.zf) * (1.0f + 0x1p-20f);
-    const float hF = c.h * c.F256;
-    const float ylo = fmaf(hF, __builtin_amdgcn_rcpf(zhi), c.CY256);
-    const float yhi = fmaf(hF, __builtin_amdgcn_rcpf(zlo), c.CY256);
-    const float a = fmaf(-fabsf(ylo), 0x1p-18f, ylo) - 4.0f;
-    const float b = fmaf(fabsf(yhi), 0x1p-18f, yhi) + 4.0f;
-    const float j0 = fmaxf(ceilf((a - 128.0f) * (1.0f / 256.0f)), 0.0f);
-    const float j1 = fminf(floorf((b - 128.0f) * (1.0f / 256.0f)), (float)(c.H - 1));
-    return !(j0 <= j1);
-}
-
-// Cheap rejection of a road strip (BIN false) or of a culling bin's bounding
-// box (BIN true) with camera-space corners (x[k], -h, z[k]): true only if it
-// certainly covers no sample.  The tests are the near, far and side tests of
-// outside() (same predicates and margins), the road depth limit of
-// road_beyond(), and the row-gap test.  A strip's corners are computed here
-// exactly as the setup computes them, so its near and far predicates are the
-// clipper's own; a bin's strips have corners inside its box, whose computed
-// depths can differ from the box corners' by rounding (below 2^-22 of
-// |x| + |z|), so a bin's depth tests carry that margin.
-template <bool BIN>
-__device__ __forceinline__ bool road_culled(const Cam &c, const float *x, const float *z)
-{
-    bool n = true, fa = true, l = true, r = true;
-    float zmin = INFINITY, zmax = -INFINITY;
-    const float zlim = fminf(c.road_zmax, c.zf);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const float ax = fabsf(x[k]), az = fabsf(z[k]);
-        const float dz = BIN ? fmaf(ax + az, 0x1p-20f, 1e-6f) : 0.0f;
-        n = n && (z[k] - c.zn < -dz);
-        fa = fa && (z[k] - zlim > dz);
-        const float mx = 1e-3f * (ax + az) + 1e-6f;
-        r = r && (fmaf(-c.t_right, z[k], x[k]) > mx);
-        l = l && (fmaf(-c.t_left, z[k], -x[k]) > mx);
-        zmin = fminf(zmin, z[k] - dz);
-        zmax = fmaxf(zmax, z[k] + dz);
-    }
-    if (n || fa || l || r) return true;
-    return road_rows_empty(c, zmin, zmax);
-}
-
-// camera-space x and z of a ground point (world x, y)
-__device__ __forceinline__ void ground_xz(const Cam &c, float wx, float wy, float &x, float &z)
-{
-    const float dx = wx - c.px, dy = wy - c.py;
-    z = fmaf(dx, c.fx, dy * c.fy);
-    x = fmaf(dx, c.fy, -(dy * c.fx));
-}
-
-// camera-space corners of road slot g (global), as the setup computes them
-__device__ __forceinline__ void road_corners(const DevSim &s, const Cam &cam, int g, V3 *v)
-{
-    const float4 q0 = s.roads[2 * g], q1 = s.roads[2 * g + 1];
-    const float y = 0.0f - cam.h;
-    ground_xz(cam, q0.x, q0.y, v[0].x, v[0].z);
-    ground_xz(cam, q0.z, q0.w, v[1].x, v[1].z);
-    ground_xz(cam, q1.x, q1.y, v[2].x, v[2].z);
-    ground_xz(cam, q1.z, q1.w, v[3].x, v[3].z);
-    v[0].y = y; v[1].y = y; v[2].y = y; v[3].y = y;
 }
 
 // ------------------------------------------------------------ per-wave state
@@ -315,7 +190,7 @@ __device__ __forceinline__ int road_clip(const DevSim &s, const Cam &cam, WaveSt
     return stage_tris(ws, ok, t.g, false, none);
 }
 
-// Full setup of n (<= 64) strips from the ring: clip test, snap and the two
+// Full setup of n (<= kSetupBatch) strips from the ring: clip test, snap and the two
 // fan triangles of the strips that need no clipping (staged; returns how
 // many); the others join the clip queue (which has room: fewer than four
 // wait whenever a setup runs).
@@ -387,7 +262,9 @@ __device__ __forceinline__ bool load_unit(const DevSim &s, const SceneRec &sc, c
 // One setup pass over box face candidates [c0, c0 + P) (P <= 64): candidate c
 // is face c % 6 of box surv[c / 6] (use_surv), or of box c / 6 culled here.
 // Fast triangles and clipped faces are appended to the box list at *nbt;
-// returns false (appending nothing) if the worst case would not fit.
+// returns false as soon as the triangles would not fit (the list is then
+// incomplete: the caller takes the overflow path, which ignores it).  Eight
+// candidates at a time never overflow a list of 96 (at most 10 triangles each).
 __device__ __forceinline__ bool box_pass(const DevSim &s, const SceneRec &sc, const Cam &cam, int ego, const RgbLds &L,
                          lptr<const int32_t> surv, bool use_surv, int ncand, int c0, int P, int &nbt, int &bmin,
                          int &bmax)
@@ -410,7 +287,7 @@ __device__ __forceinline__ bool box_pass(const DevSim &s, const SceneRec &sc, co
     }
     const unsigned long long b0 = __ballot(v0), b1 = __ballot(v1), bc = __ballot(clip);
     const int n0 = __popcll(b0), nf = n0 + __popcll(b1), ncl = __popcll(bc);
-    if (nbt + nf + kMaxTrisPerCand * ncl > L.bcap) return false;
+    if (nbt + nf > L.bcap) return false;
     if (v0) lds_store(L.btris + nbt + lanes_below(b0), t0);
     if (v1) lds_store(L.btris + nbt + n0 + lanes_below(b1), t1);
     if (v0) { bmin = min(bmin, (int)t0.g.j0); bmax = max(bmax, (int)t0.g.j1); }
@@ -430,6 +307,7 @@ __device__ __forceinline__ bool box_pass(const DevSim &s, const SceneRec &sc, co
         TriRec t;
         const bool ok = clip_seg<true>(cam, Q, lv, 0, cam.H, t);
         const unsigned long long bo = __ballot(ok);
+        if (nbt + __popcll(bo) > L.bcap) return false;
         if (ok) {
             lds_store(L.btris + nbt + lanes_below(bo), t);
             bmin = min(bmin, (int)t.g.j0);
@@ -594,29 +472,6 @@ __device__ __forceinline__ void box_spans(const RgbLds &L, const Cam &cam, int n
             }
         }
     }
-}
-
-// 16 pixels' RGB (byte 0 red) packed into the 48 bytes of their samples
-__device__ __forceinline__ void store16(uint8_t *dst, const uint32_t *c)
-{
-    typedef uint32_t u4v __attribute__((ext_vector_type(4)));
-    uint32_t w[12];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-        // bytes 4k .. 4k + 3 belong to pixels p = 4k / 3 and p + 1
-        const int p = (4 * k) / 3;
-        uint32_t sel = 0;
-#pragma unroll
-        for (int bb = 0; bb < 4; ++bb) {
-            const int b = 4 * k + bb, px = b / 3, ch = b - 3 * px;
-            sel |= (uint32_t)(px == p ? ch : 4 + ch) << (8 * bb);
-        }
-        w[k] = __builtin_amdgcn_perm(c[p + 1 < 16 ? p + 1 : 15], c[p], sel);
-    }
-    u4v *out = reinterpret_cast<u4v *>(dst);
-    out[0] = u4v{w[0], w[1], w[2], w[3]};
-    out[1] = u4v{w[4], w[5], w[6], w[7]};
-    out[2] = u4v{w[8], w[9], w[10], w[11]};
 }
 
 // rows [c0, c1) from the group masks and spans: 16 samples (48 bytes) per
@@ -840,8 +695,8 @@ __device__ __forceinline__ void render_view_rgb(const DevSim &s, const RenderOut
         int ntri = 0;
         if (ws.nclip >= 4 || (final && ws.nclip > 0)) {
             ntri = road_clip(s, cam, ws);
-        } else if (ws.tail - ws.head >= 64 || (final && ws.tail > ws.head)) {
-            ntri = road_setup(s, cam, ws, min(64, ws.tail - ws.head));
+        } else if (ws.tail - ws.head >= kSetupBatch || (final && ws.tail > ws.head)) {
+            ntri = road_setup(s, cam, ws, min(kSetupBatch, ws.tail - ws.head));
         } else if (!final) {
             if (u >= n_units) {
                 final = true;

@@ -50,9 +50,26 @@ struct Layout {
     int64_t halted, infr, actu, signals, signal_color;
     int64_t scenes, views, state, cs, dims, agent_color, roads, road_index, road_color, bins, palette,
         queue, order, counter;
+    int64_t upload_end;   // the sections above are uploaded at creation
+    // the chip-wide rgb raster's buffers (present when chip is true); ctl and
+    // cov are zeroed at creation, the others need no initial value
+    bool chip;
+    int64_t chip_ctl, chip_cov, chip_sbins, chip_vinfo, chip_btri, chip_rinfo, chip_rtri, chip_rrows, chip_items,
+        chip_end;
+    int64_t bins_stride, btri_cap, rtri_cap;
     int64_t total;
     int64_t n_agents, n_roads, n_views, n_bins, n_static, n_signals;
 };
+
+// box triangles one view's list holds in the chip-wide raster (a view with
+// more is set up again per resolve item)
+constexpr int64_t kChipBoxTris = 128;
+
+// can the chip-wide raster serve this image size?
+bool chip_size_ok(int32_t width, int32_t height)
+{
+    return width % 16 == 0 && width >= 64 && width <= 1024 && height >= 1;
+}
 
 bool finite_cfg(const gp_config *c)
 {
@@ -149,7 +166,33 @@ Layout make_layout(const gp_config *cfg, const gp_scene_desc *sc, int32_t n)
     L.signal_color = take(L.n_signals);
     L.queue = take(4 * L.n_views);
     L.order = take(4 * L.n_views);
-    L.counter = take(4 * (gp::kQueues + 2));
+    L.counter = take(4 * (gp::kQueues + 2) * gp::kCtrStride);
+    L.upload_end = o;
+    L.chip = chip_size_ok(cfg->width, cfg->height);
+    if (L.chip) {
+        int64_t max_bins = 1, units = 0, max_roads = 0;
+        for (int s = 0; s < n; ++s) {
+            const int64_t nb = n_bins_of(sc[s].n_roads);
+            max_bins = std::max(max_bins, nb);
+            max_roads = std::max<int64_t>(max_roads, sc[s].n_roads);
+            units += (int64_t)sc[s].n_agents * cfg->n_cams * ((nb + 3) / 4);
+        }
+        const int64_t nw = (cfg->width + 63) / 64;
+        L.bins_stride = max_bins;
+        L.btri_cap = kChipBoxTris;
+        // road triangles a view's list holds (more go to the coverage words)
+        L.rtri_cap = std::min<int64_t>(1024, std::max<int64_t>(256, (max_roads / 8 + 63) / 64 * 64));
+        L.chip_ctl = take(4 * gp::CHIP_NCTL);
+        L.chip_cov = take(8 * nw * cfg->height * L.n_views);
+        L.chip_sbins = take(4 * L.bins_stride * L.n_views);
+        L.chip_vinfo = take(16 * L.n_views);
+        L.chip_btri = take(48 * L.btri_cap * L.n_views);
+        L.chip_rinfo = take(16 * L.n_views);
+        L.chip_rtri = take(32 * L.rtri_cap * L.n_views);
+        L.chip_rrows = take(4 * L.rtri_cap * L.n_views);
+        L.chip_items = take(8 * units);
+        L.chip_end = o;
+    }
     L.total = o;
     return L;
 }
@@ -160,9 +203,10 @@ bool valid_launch(const gp_launch &l)
     const bool bt = l.batch_tris == 256 || l.batch_tris == 512 || l.batch_tris == 1024 || l.batch_tris == 2048;
     const bool th = l.block_threads == 256 || l.block_threads == 512 || l.block_threads == 1024;
     const bool sc = l.sched == GP_SCHED_PLAIN || l.sched == GP_SCHED_PERSISTENT;
-    const bool ra = l.raster == GP_RASTER_BANDED || l.raster == GP_RASTER_SPLIT;
+    const bool ra = l.raster == GP_RASTER_BANDED || l.raster == GP_RASTER_SPLIT || l.raster == GP_RASTER_CHIP;
     const bool vw = l.view_waves == 1 || l.view_waves == 2 || l.view_waves == 4;
-    return br && bt && th && sc && ra && vw && l.blocks_per_cu >= 1 && l.blocks_per_cu <= 16;
+    const bool cw = l.road_wgs_per_cu >= 1 && l.road_wgs_per_cu <= 16;
+    return br && bt && th && sc && ra && vw && cw && l.blocks_per_cu >= 1 && l.blocks_per_cu <= 16;
 }
 
 // 2-D Morton code of 16-bit coordinates
@@ -267,9 +311,11 @@ struct gp_sim {
     hipStream_t capture_stream = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
+    hipGraphNode_t g_step = nullptr;   // the step's kernel node (its action pointer is updated in place)
     const float *g_act = nullptr;
     uint8_t *g_rgb = nullptr;
     gp_launch g_launch{};
+    gp::ChipBufs chip{};        // the chip-wide raster's buffers (lay.chip)
     int32_t road_uniform = 0;   // every road strip of every scene has one colour
     int32_t bins_cap = 1;       // culling bins of the largest scene
 };
@@ -307,6 +353,13 @@ gp::RgbCfg rgb_cfg(const gp_sim *sim, const gp_launch &l)
     return c;
 }
 
+// can this render take the chip-wide rasteriser?
+bool chip_ok(const gp_sim *sim, const gp::RenderOut &o, const gp_launch &l, int kind)
+{
+    return l.raster == GP_RASTER_CHIP && kind == 1 && sim->lay.chip && sim->cfg.cam_height > 0.0f &&
+           reinterpret_cast<uintptr_t>(o.rgb) % 16 == 0 && sim->bins_cap <= sim->lay.bins_stride;
+}
+
 // can this render take the split rasteriser?
 bool split_ok(const gp_sim *sim, const gp::RenderOut &o, const gp_launch &l, int kind)
 {
@@ -325,6 +378,21 @@ gp_status render_impl(gp_sim *sim, const gp::RenderOut &o, const gp_launch &l, h
     const bool split = split_ok(sim, o, l, kind);
     const gp::RgbCfg rc = rgb_cfg(sim, l);
     hipError_t e;
+    if (chip_ok(sim, o, l, kind)) {
+        const int rg = l.road_wgs_per_cu * sim->n_cu;
+        if (l.sched == GP_SCHED_PLAIN) {
+            for (int s = 0; s < sim->n_scenes; ++s) {
+                const gp::SceneRec &r = sim->scenes[s];
+                e = gp::launch_render_chip(sim->dev, o, sim->chip, 0, r.view_base, r.n_agents * sim->cfg.n_cams, rg,
+                                           st);
+                if (e != hipSuccess) return hip_fail(e, "render launch");
+            }
+            return GP_OK;
+        }
+        e = gp::launch_render_chip(sim->dev, o, sim->chip, 1, 0, (int)sim->lay.n_views, rg, st);
+        if (e != hipSuccess) return hip_fail(e, "render launch");
+        return GP_OK;
+    }
     if (l.sched == GP_SCHED_PLAIN) {
         for (int s = 0; s < sim->n_scenes; ++s) {
             const gp::SceneRec &r = sim->scenes[s];
@@ -372,13 +440,14 @@ void drop_graph(gp_sim *sim)
     if (sim->graph) (void)hipGraphDestroy(sim->graph);
     sim->gexec = nullptr;
     sim->graph = nullptr;
+    sim->g_step = nullptr;
 }
 
 bool same_launch(const gp_launch &a, const gp_launch &b)
 {
     return a.sched == b.sched && a.band_rows == b.band_rows && a.batch_tris == b.batch_tris &&
            a.block_threads == b.block_threads && a.blocks_per_cu == b.blocks_per_cu && a.raster == b.raster &&
-           a.view_waves == b.view_waves;
+           a.view_waves == b.view_waves && a.road_wgs_per_cu == b.road_wgs_per_cu;
 }
 
 }  // namespace
@@ -421,7 +490,7 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
     if (lds > 0) sim->max_lds = (size_t)lds;
 
     // host image of the workspace
-    std::vector<unsigned char> host((size_t)L.total, 0);
+    std::vector<unsigned char> host((size_t)L.upload_end, 0);
     auto at = [&](int64_t off) { return host.data() + off; };
     sim->scenes.resize(n_scenes);
     auto *views = reinterpret_cast<gp::ViewRec *>(at(L.views));
@@ -544,7 +613,9 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
 
     unsigned char *base = static_cast<unsigned char *>(d_workspace);
     hipStream_t hs = static_cast<hipStream_t>(stream);
-    e = hipMemcpyAsync(base, host.data(), (size_t)L.total, hipMemcpyHostToDevice, hs);
+    e = hipMemcpyAsync(base, host.data(), (size_t)L.upload_end, hipMemcpyHostToDevice, hs);
+    // the chip-wide raster's counters and coverage words start at zero
+    if (e == hipSuccess && L.chip) e = hipMemsetAsync(base + L.chip_ctl, 0, (size_t)(L.chip_sbins - L.chip_ctl), hs);
     if (e == hipSuccess) e = hipStreamSynchronize(hs);
     if (e != hipSuccess) { delete sim; return hip_fail(e, "workspace upload"); }
 
@@ -568,6 +639,24 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
     D.queue = reinterpret_cast<const int32_t *>(base + L.queue);
     D.order = reinterpret_cast<const int32_t *>(base + L.order);
     D.counter = reinterpret_cast<uint32_t *>(base + L.counter);
+    if (L.chip) {
+        gp::ChipBufs &C = sim->chip;
+        C.ctl = reinterpret_cast<uint32_t *>(base + L.chip_ctl);
+        C.cov = reinterpret_cast<unsigned long long *>(base + L.chip_cov);
+        C.sbins = reinterpret_cast<int32_t *>(base + L.chip_sbins);
+        C.vinfo = reinterpret_cast<int4 *>(base + L.chip_vinfo);
+        C.btri = base + L.chip_btri;
+        C.rinfo = reinterpret_cast<int4 *>(base + L.chip_rinfo);
+        C.rtri = base + L.chip_rtri;
+        C.rrows = reinterpret_cast<int32_t *>(base + L.chip_rrows);
+        C.rtri_cap = (int32_t)L.rtri_cap;
+        C.items = reinterpret_cast<uint2 *>(base + L.chip_items);
+        C.bins_stride = (int32_t)L.bins_stride;
+        C.btri_cap = (int32_t)L.btri_cap;
+        C.nw = (cfg->width + 63) / 64;
+        C.rows_per_item = std::max(1, 64 / (cfg->width / 16));
+        C.items_per_view = (cfg->height + C.rows_per_item - 1) / C.rows_per_item;
+    }
     D.n_scenes = n_scenes;
     D.n_agents = (int32_t)L.n_agents;
     D.n_boxes = (int32_t)(L.n_agents + L.n_static);
@@ -620,13 +709,18 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
     // views per CU) where it can run
     l.raster = GP_RASTER_BANDED;
     l.view_waves = 2;
+    l.road_wgs_per_cu = 8;
     {
+        // rgb renders: the wave-split raster where eight views fit a CU, else
+        // the chip-wide passes where the image size allows them
         gp_launch t = l;
         t.raster = GP_RASTER_SPLIT;
         if (cfg->width % 16 == 0 && cfg->cam_height > 0.0f &&
             gp::rgb_lds_bytes(cfg->width, cfg->height, rgb_cfg(sim, t)) * 8 <= 160u * 1024u) {
             l.raster = GP_RASTER_SPLIT;
             l.blocks_per_cu = 8;
+        } else if (L.chip && cfg->cam_height > 0.0f) {
+            l.raster = GP_RASTER_CHIP;
         }
     }
     sim->launch = l;
@@ -678,23 +772,42 @@ gp_status gp_sim_step_render_graph(gp_sim *sim, const float *d_actions, uint8_t 
         return fail(GP_EINVAL, "misaligned pointer");
     gp_launch l = sim->launch;
     l.sched = GP_SCHED_PERSISTENT;
-    if (!sim->gexec || sim->g_act != d_actions || sim->g_rgb != d_rgb || !same_launch(l, sim->g_launch)) {
+    if (!sim->gexec || sim->g_rgb != d_rgb || !same_launch(l, sim->g_launch)) {
+        // the step as an explicit kernel node (so that a new action buffer
+        // only updates that node's arguments), then the render, captured,
+        // as a child graph that depends on it
         drop_graph(sim);
-        hipError_t e = hipStreamBeginCapture(sim->capture_stream, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) return hip_fail(e, "begin capture");
-        gp_status st = step_impl(sim, d_actions, l, sim->capture_stream);
-        gp::RenderOut o{d_rgb, nullptr, nullptr};
-        if (st == GP_OK) st = render_impl(sim, o, l, sim->capture_stream);
         hipGraph_t g = nullptr;
-        e = hipStreamEndCapture(sim->capture_stream, &g);
-        if (st != GP_OK) { if (g) (void)hipGraphDestroy(g); return st; }
-        if (e != hipSuccess) return hip_fail(e, "end capture");
+        hipError_t e = hipGraphCreate(&g, 0);
+        if (e != hipSuccess) return hip_fail(e, "graph create");
         sim->graph = g;
+        if (sim->lay.n_agents > 0) {
+            e = gp::step_graph_node(g, nullptr, &sim->g_step, sim->dev, d_actions);
+            if (e != hipSuccess) { drop_graph(sim); return hip_fail(e, "step node"); }
+        }
+        e = hipStreamBeginCapture(sim->capture_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) { drop_graph(sim); return hip_fail(e, "begin capture"); }
+        gp::RenderOut o{d_rgb, nullptr, nullptr};
+        gp_status st = render_impl(sim, o, l, sim->capture_stream);
+        hipGraph_t rg = nullptr;
+        e = hipStreamEndCapture(sim->capture_stream, &rg);
+        if (st != GP_OK) { if (rg) (void)hipGraphDestroy(rg); drop_graph(sim); return st; }
+        if (e != hipSuccess) { drop_graph(sim); return hip_fail(e, "end capture"); }
+        hipGraphNode_t child = nullptr;
+        e = hipGraphAddChildGraphNode(&child, g, sim->g_step ? &sim->g_step : nullptr, sim->g_step ? 1 : 0, rg);
+        (void)hipGraphDestroy(rg);       // the child node holds its own copy
+        if (e != hipSuccess) { drop_graph(sim); return hip_fail(e, "render node"); }
         e = hipGraphInstantiate(&sim->gexec, g, nullptr, nullptr, 0);
         if (e != hipSuccess) { drop_graph(sim); return hip_fail(e, "graph instantiate"); }
         sim->g_act = d_actions;
         sim->g_rgb = d_rgb;
         sim->g_launch = l;
+    } else if (sim->g_act != d_actions) {
+        if (sim->g_step) {
+            hipError_t e = gp::step_graph_node(nullptr, sim->gexec, &sim->g_step, sim->dev, d_actions);
+            if (e != hipSuccess) { drop_graph(sim); return hip_fail(e, "step node update"); }
+        }
+        sim->g_act = d_actions;
     }
     hipError_t e = hipGraphLaunch(sim->gexec, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "graph launch");

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libgigapix.so")
 
 GP_OK, GP_EINVAL, GP_ENOMEM, GP_EDEVICE, GP_ESTATE = 0, -1, -2, -3, -4
 SCHED_PLAIN, SCHED_PERSISTENT = 0, 1
+RASTER_BANDED, RASTER_SPLIT, RASTER_CHIP = 0, 1, 2
 MAX_CAMS = 4
 
 EXPORTS = ("gp_sim_required_bytes", "gp_sim_create", "gp_sim_set_launch", "gp_sim_get_launch",
@@ -53,7 +54,7 @@ class SceneDesc(C.Structure):
 class Launch(C.Structure):
     _fields_ = [("sched", C.c_int32), ("band_rows", C.c_int32), ("batch_tris", C.c_int32),
                 ("block_threads", C.c_int32), ("blocks_per_cu", C.c_int32), ("raster", C.c_int32),
-                ("view_waves", C.c_int32)]
+                ("view_waves", C.c_int32), ("road_wgs_per_cu", C.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -220,6 +221,10 @@ class Sim:
         self.n_agents = int(L.gp_sim_num_agents(h))
         self.n_scenes = int(L.gp_sim_num_scenes(h))
         self.workspace_bytes = int(nbytes)
+        self.light = None
+        self.scene_shapes = tuple((int(getattr(s, "n_agents", 0)), int(getattr(s, "n_roads", 0)),
+                                   int(getattr(s, "n_static", 0)), int(getattr(s, "n_signals", 0)))
+                                  for s in scenes)
 
     # -- lifecycle
     def close(self):
@@ -288,9 +293,11 @@ class Sim:
         frame) and ambient term; None turns shading off."""
         if light is None:
             _check(lib().gp_sim_set_light(self._h, None))
+            self.light = None
             return
         arr = (C.c_float * 4)(*[float(x) for x in light])
         _check(lib().gp_sim_set_light(self._h, C.cast(arr, C.c_void_p)))
+        self.light = tuple(float(x) for x in light)
 
     def get_actuators(self, stream=None):
         """float32 [n_agents, 4]: longitudinal and lateral acceleration, steering angle, 0."""

@@ -150,6 +150,10 @@ class Server:
         fp = int(self.ex.footprint(scene))
         if fp > self.arena.capacity:
             raise ServeError(f"rollout footprint {fp} exceeds the arena ({self.arena.capacity} bytes)")
+        cap = getattr(self.ex, "max_batch_agents", None)
+        if cap is not None and scene.agent_state.shape[0] > cap:
+            raise ServeError(f"rollout of {scene.agent_state.shape[0]} agents exceeds the executor's batch "
+                             f"({cap} agents)")
         r = Rollout(self._next_rollout, scene, int(scene.agent_state.shape[0]),
                     int(scene.agent_state.shape[0]) * self.ex.n_cams, fp)
         self._next_rollout += 1
@@ -247,7 +251,16 @@ class Server:
         while self.ex.free_slots() > 0:
             if not self._ready:
                 break
-            ready = sorted(self._ready.values(), key=lambda r: r.pending[0].t_arrival)[:self.max_batch]
+            # oldest first, as many rollouts as the executor's batch holds
+            cap = getattr(self.ex, "max_batch_agents", None)
+            ready, agents = [], 0
+            for r in sorted(self._ready.values(), key=lambda r: r.pending[0].t_arrival):
+                if len(ready) == self.max_batch:
+                    break
+                if cap is not None and agents + r.n_agents > cap:
+                    continue        # waits for the next batch (open() made sure it fits alone)
+                ready.append(r)
+                agents += r.n_agents
             reqs = [r.pending.popleft() for r in ready]
             for r in ready:
                 del self._ready[r.id]
@@ -257,8 +270,19 @@ class Server:
                 r.inflight = q
                 q.batch = token
             self.batches[token] = (ready, reqs)
+            try:
+                self.ex.launch(token, [r.handle for r in ready], [q.actions for q in reqs], now)
+            except Exception:
+                # nothing was queued: put the requests back at the head of
+                # their rollouts' queues and leave the server as it was
+                del self.batches[token]
+                for r, q in zip(ready, reqs):
+                    r.inflight = None
+                    q.batch = None
+                    r.pending.appendleft(q)
+                    self._mark(r)
+                raise
             self.batch_sizes.append(len(ready))
-            self.ex.launch(token, [r.handle for r in ready], [q.actions for q in reqs], now)
             launched += 1
         return launched
 
@@ -313,6 +337,10 @@ class GpuExecutor:
                 "event": None, "token": None,
             })
         self.max_batch_agents = max_batch_agents
+        # optional event pair around every batch (device_spans), for checking
+        # that batches of different streams overlapped on the device
+        self.record_spans = False
+        self.spans = []
         # Creating a sim uploads its scene and waits for that upload.  On a
         # stream of its own (non-blocking, like every torch stream) the wait
         # covers the upload only, not the batches queued on the slots' streams
@@ -349,11 +377,26 @@ class GpuExecutor:
         if sum(x.n_agents for x in sims) > self.max_batch_agents:
             raise ServeError("batch larger than the executor's batch buffer")
         with self.torch.cuda.stream(slot["stream"]):
+            t0 = None
+            if self.record_spans:
+                t0 = self.torch.cuda.Event(enable_timing=True)
+                t0.record(slot["stream"])
             self.gp.batch_step_render(sims, actions, [h["rgb"] for h in handles], slot["ws"],
                                       slot["staging"], stream=slot["stream"])
-            ev = self.torch.cuda.Event()
+            ev = self.torch.cuda.Event(enable_timing=self.record_spans)
             ev.record(slot["stream"])
+        if self.record_spans:
+            self.spans.append((t0, ev))
         slot["event"], slot["token"] = ev, token
+
+    def device_spans(self):
+        """(start, end) in ms of every recorded batch on the device, relative
+        to the first batch's start (needs record_spans; synchronises)."""
+        self.torch.cuda.synchronize()
+        if not self.spans:
+            return []
+        base = self.spans[0][0]
+        return [(base.elapsed_time(a), base.elapsed_time(b)) for a, b in self.spans]
 
     def poll(self, now):
         out = []
@@ -370,8 +413,10 @@ class VirtualExecutor:
     and render are delegated to `run(handle, actions)` (e.g. the oracle)."""
 
     def __init__(self, n_cams: int = 1, n_slots: int = 2, base: float = 1e-4, per_view: float = 1e-6,
-                 footprint_fn: Optional[Callable] = None, run: Optional[Callable] = None):
+                 footprint_fn: Optional[Callable] = None, run: Optional[Callable] = None,
+                 max_batch_agents: Optional[int] = None):
         self.n_cams = n_cams
+        self.max_batch_agents = max_batch_agents
         self.n_slots = n_slots
         self.base, self.per_view = base, per_view
         self.footprint_fn = footprint_fn or (lambda sc: 4096 + 64 * sc.agent_state.shape[0] + 32 * sc.road_xy.shape[0])
@@ -396,6 +441,8 @@ class VirtualExecutor:
         return self.n_slots - len(self.busy)
 
     def launch(self, token, handles, actions, now):
+        if self.max_batch_agents is not None and sum(a.shape[0] for a in actions) > self.max_batch_agents:
+            raise ServeError("batch larger than the executor's batch buffer")
         views = sum(a.shape[0] * self.n_cams for a in actions)
         self.busy[token] = now + self.base + self.per_view * views
         if self.run:

@@ -97,6 +97,57 @@ def test_step_clamps():
         assert cs[k, 0] == c and cs[k, 1] == s
 
 
+def _f32_exact(x):
+    """binary32 nearest to the exact rational x, ties to even (one rounding)."""
+    from fractions import Fraction
+    x = Fraction(x)
+    c = np.float32(float(x))
+    best = None
+    for cand in (np.nextafter(c, np.float32(-np.inf)), c, np.nextafter(c, np.float32(np.inf))):
+        d = abs(Fraction(float(cand)) - x)
+        even = (int(np.array(cand).view(np.uint32)) & 1) == 0
+        if best is None or d < best[0] or (d == best[0] and even):
+            best = (d, cand)
+    return best[1]
+
+
+def _fmaf(a, b, c):
+    # fused a * b + c of binary32 operands, rounded once
+    from fractions import Fraction
+    return _f32_exact(Fraction(float(np.float32(a))) * Fraction(float(np.float32(b))) + Fraction(float(np.float32(c))))
+
+
+def test_step_acceleration_and_steer_clamp_values():
+    # App. A ("Action Space and Dynamics") clips the acceleration; the bounds
+    # read here are [-6, 3] m/s^2 and |steer| <= 0.5 rad.  From v = 10 (far
+    # from the speed bounds) the new speed is the fused v + a dt with a at the
+    # bound, so a wrong bound changes the value.
+    dt = np.float32(0.1)
+    st = np.array([[0, 0, 0, 10.0]] * 4, dtype=np.float32)
+    dm = np.full((4, 3), 4.5, dtype=np.float32)
+    act = np.array([[100.0, 0.0], [-100.0, 0.0], [np.nan, 0.0], [2.5, 0.0]], dtype=np.float32)
+    out, _ = oracle.step(st, dm, act, 0.1)
+    assert out[0, 3] == _fmaf(3.0, dt, 10.0)
+    assert out[1, 3] == _fmaf(-6.0, dt, 10.0)
+    assert out[2, 3] == _fmaf(-6.0, dt, 10.0)      # NaN takes the lower bound
+    assert out[3, 3] == _fmaf(2.5, dt, 10.0)       # inside the bounds: unchanged
+    # steering: a command past the bound turns like 0.5 rad, whose heading
+    # change v1 dt tan(0.5) / (0.6 L) is fixed in float64 (a bound of 0.45 or
+    # 0.55 would move it by more than 10%)
+    st2 = np.array([[0, 0, 0, 10.0]] * 3, dtype=np.float32)
+    act2 = np.array([[0.0, 3.0], [0.0, -3.0], [0.0, np.nan]], dtype=np.float32)
+    out2, _ = oracle.step(st2, dm[:3], act2, 0.1)
+    v1 = float(_fmaf(0.0, dt, 10.0))
+    dpsi = v1 * float(dt) * math.tan(0.5) / (0.6 * 4.5)
+    assert abs(float(out2[0, 2]) - dpsi) <= 1e-6 * dpsi
+    assert abs(float(out2[1, 2]) + dpsi) <= 1e-6 * dpsi
+    assert abs(float(out2[2, 2]) + dpsi) <= 1e-6 * dpsi   # NaN steer: -0.5
+    # speed bounds by value: 0 and 30 exactly
+    st3 = np.array([[0, 0, 0, 0.2], [0, 0, 0, 29.95]], dtype=np.float32)
+    out3, _ = oracle.step(st3, dm[:2], np.array([[-6.0, 0.0], [3.0, 0.0]], np.float32), 0.1)
+    assert out3[0, 3] == np.float32(0.0) and out3[1, 3] == np.float32(30.0)
+
+
 def test_step_heading_wraps_into_half_open_interval():
     st = np.array([[0, 0, np.float32(3.1), 20.0], [0, 0, np.float32(-3.1), 20.0]], dtype=np.float32)
     dm = np.full((2, 3), 4.0, dtype=np.float32)

@@ -199,3 +199,51 @@ def test_poisson_arrivals_rate_and_order():
     assert abs(len(t) - 10000) < 5 * np.sqrt(10000)
     gaps = np.diff(t)
     assert abs(gaps.mean() - 1 / 5000.0) < 0.05 / 5000.0 * 20
+
+
+def test_batches_capped_by_executor_agents_and_oversize_rollout_refused():
+    ex = serve.VirtualExecutor(n_slots=1, max_batch_agents=10)
+    srv = serve.Server(ex, budget_bytes=1 << 30)
+    with pytest.raises(serve.ServeError):
+        srv.open(_tiny_scene(1, n_agents=11))         # no batch could ever hold it
+    ids = [srv.open(_tiny_scene(30 + i, n_agents=4)) for i in range(5)]
+    clock, advance = _virtual_clock()
+    for k, rid in enumerate(ids):
+        srv.submit(rid, np.zeros((4, 2), np.float32), now=k * 1e-6)
+    t = 0.0
+    while not srv.idle():
+        srv.pump(t)
+        t += 1e-3
+    assert len([q for q in srv.done if q.status == serve.OK]) == 5
+    # 4-agent rollouts, at most 10 agents per batch: never more than two together
+    assert max(srv.batch_sizes) == 2 and sum(srv.batch_sizes) == 5
+
+
+class _FailingExecutor(serve.VirtualExecutor):
+    def __init__(self, fails):
+        super().__init__(n_slots=2)
+        self.fails = fails
+
+    def launch(self, token, handles, actions, now):
+        if self.fails > 0:
+            self.fails -= 1
+            raise RuntimeError("device refused the batch")
+        return super().launch(token, handles, actions, now)
+
+
+def test_failed_launch_leaves_requests_queued():
+    ex = _FailingExecutor(fails=1)
+    srv = serve.Server(ex, budget_bytes=1 << 30)
+    a, b = srv.open(_tiny_scene(40)), srv.open(_tiny_scene(41))
+    qa = srv.submit(a, np.zeros((4, 2), np.float32), now=0.0)
+    qb = srv.submit(b, np.zeros((4, 2), np.float32), now=0.0)
+    with pytest.raises(RuntimeError):
+        srv.pump(0.0)
+    assert not srv.batches and srv.batch_sizes == []
+    assert qa.status is None and qb.status is None and qa.batch is None
+    # the next pump serves them, in order, and the server drains
+    t = 0.0
+    while not srv.idle():
+        srv.pump(t)
+        t += 1e-3
+    assert qa.status == serve.OK and qb.status == serve.OK
