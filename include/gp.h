@@ -184,6 +184,23 @@ gp_status gp_sim_render(gp_sim *sim, uint8_t *d_rgb, float *d_depth, int32_t *d_
  * differ.  Arguments as gp_sim_render (rgb need not be 4-byte aligned). */
 gp_status gp_sim_render_raycast(gp_sim *sim, uint8_t *d_rgb, float *d_depth, int32_t *d_primid, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc): gp_sim_render
+ * of the rgb image only, through the chip-wide raster, with that raster's
+ * scratch (work counters, coverage words, culling-bin, box- and road-triangle
+ * lists, road items) taken from a static device array of 64 MiB instead of
+ * the sim's workspace.  The call allocates nothing; each GPU holds its own
+ * array until the process ends.  d_rgb: device uint8
+ * [num_views][height][width][3], 16-byte aligned.  The sim's device must be
+ * current.  Every call on a GPU shares that GPU's array and clears what must
+ * start at zero, so calls that overlap on one GPU (other streams, other host
+ * threads) race: serialise them.  Returns GP_EINVAL when the sim's scratch
+ * would exceed 64 MiB (for instance 4,096 views at 512x512), when the image
+ * width is not a multiple of 16 in 64..1024, or when the sim's rgb renders
+ * need the general kernel (mixed road colours, the light, traffic lights);
+ * images are bit-identical to gp_sim_render's. */
+gp_status gp_sim_render_noalloc(gp_sim *sim, uint8_t *d_rgb, void *stream);
+
 /* Step then render (rgb only) as one hipGraph replay.  The graph is built on
  * first use and rebuilt when the image pointer or the launch settings change;
  * a new d_actions pointer only updates the step node's arguments, so callers

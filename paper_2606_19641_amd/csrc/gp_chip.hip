@@ -838,6 +838,21 @@ __global__ __launch_bounds__(256) void k_chip_resolve(DevSim s, RenderOut o, Chi
 
 }  // namespace
 
+// zero the counters and the coverage words (a fill kernel, not a memset node:
+// callers may capture this into a graph)
+__global__ void k_chip_clear(ChipBufs cb, size_t cov_words)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < CHIP_NCTL) cb.ctl[i] = 0u;
+    for (size_t k = i; k < cov_words; k += (size_t)gridDim.x * blockDim.x) cb.cov[k] = 0ull;
+}
+
+hipError_t launch_chip_clear(const ChipBufs &cb, size_t cov_words, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_chip_clear, dim3(1024), dim3(256), 0, st, cb, cov_words);
+    return hipGetLastError();
+}
+
 hipError_t launch_render_chip(const DevSim &s, const RenderOut &o, const ChipBufs &cb, int mode, int view_begin,
                               int n_views, int road_grid, hipStream_t st)
 {

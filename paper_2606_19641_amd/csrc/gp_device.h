@@ -166,6 +166,8 @@ size_t rgb_lds_bytes(int width, int height, const RgbCfg &c);
 // sixteen tiles of a view
 hipError_t launch_render_chip(const DevSim &s, const RenderOut &o, const ChipBufs &cb, int mode, int view_begin,
                               int n_views, int road_grid, hipStream_t st);
+// zero the chip-wide raster's counters and the first cov_words coverage words
+hipError_t launch_chip_clear(const ChipBufs &cb, size_t cov_words, hipStream_t st);
 // batched (serving) launches over a device table of sims
 hipError_t launch_step_multi(const SimEntry *tab, int n_sims, int max_agents, hipStream_t st);
 hipError_t launch_render_multi(const SimEntry *tab, const int2 *items, int n_items, uint32_t *ctl,

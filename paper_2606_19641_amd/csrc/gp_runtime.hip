@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <climits>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -763,6 +764,86 @@ gp_status gp_sim_render(gp_sim *sim, uint8_t *d_rgb, float *d_depth, int32_t *d_
         return fail(GP_EINVAL, "depth/primid must be 4-byte aligned");
     gp::RenderOut o{d_rgb, d_depth, d_primid};
     return render_impl(sim, o, sim->launch, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
+
+namespace {
+
+// The scratch of gp_sim_render_noalloc: the chip-wide raster's counters,
+// coverage words, surviving-bin lists, box and road triangle lists and road
+// items, in one file-scope device array instead of the sim's workspace.  Each
+// GPU the library runs on holds its own copy until the process ends; every
+// call on that GPU shares it.  In host code `scratch` names a host-side
+// stand-in, not the device array: its device address is taken once per
+// device with hipGetSymbolAddress, with that device current, and only that
+// address is ever passed to kernels.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+gp_status scratch_of(int device, unsigned char **out)
+{
+    if (device < 0 || device >= kMaxDevices) return fail(GP_EINVAL, "device %d out of range", device);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e, "address of the static scratch");
+        g_scratch_ptr[device] = static_cast<unsigned char *>(p);
+    }
+    *out = g_scratch_ptr[device];
+    return GP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gp_status gp_sim_render_noalloc(gp_sim *sim, uint8_t *d_rgb, void *stream)
+{
+    if (!sim || !d_rgb) return fail(GP_EINVAL, "NULL argument");
+    if (reinterpret_cast<uintptr_t>(d_rgb) % 16 != 0) return fail(GP_EINVAL, "rgb must be 16-byte aligned");
+    if (!sim->lay.chip)
+        return fail(GP_EINVAL, "image size %dx%d: the chip-wide raster needs width %% 16 == 0 and 64 <= width <= 1024",
+                    sim->cfg.width, sim->cfg.height);
+    if (!sim->dev.road_color_uniform)
+        return fail(GP_EINVAL, "rgb renders of this sim need the general kernel (road colours, light or traffic lights)");
+    if (sim->bins_cap > sim->lay.bins_stride) return fail(GP_EINVAL, "culling bins exceed the layout");
+    const int64_t need = sim->lay.chip_end - sim->lay.chip_ctl;
+    if (need > (int64_t)kNoAllocScratchBytes)
+        return fail(GP_EINVAL, "this sim needs %lld bytes of scratch, the static buffer holds %lld",
+                    (long long)need, (long long)kNoAllocScratchBytes);
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != sim->device) return fail(GP_EINVAL, "the sim's device (%d) must be current (%d is)", sim->device, dev);
+    unsigned char *base = nullptr;
+    gp_status st = scratch_of(dev, &base);
+    if (st != GP_OK) return st;
+    const Layout &L = sim->lay;
+    gp::ChipBufs C = sim->chip;
+    C.ctl = reinterpret_cast<uint32_t *>(base);
+    C.cov = reinterpret_cast<unsigned long long *>(base + (L.chip_cov - L.chip_ctl));
+    C.sbins = reinterpret_cast<int32_t *>(base + (L.chip_sbins - L.chip_ctl));
+    C.vinfo = reinterpret_cast<int4 *>(base + (L.chip_vinfo - L.chip_ctl));
+    C.btri = base + (L.chip_btri - L.chip_ctl);
+    C.rinfo = reinterpret_cast<int4 *>(base + (L.chip_rinfo - L.chip_ctl));
+    C.rtri = base + (L.chip_rtri - L.chip_ctl);
+    C.rrows = reinterpret_cast<int32_t *>(base + (L.chip_rrows - L.chip_ctl));
+    C.items = reinterpret_cast<uint2 *>(base + (L.chip_items - L.chip_ctl));
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    // the previous call (maybe of another sim, with another layout) leaves
+    // anything in the array: zero the counters and coverage words first
+    e = gp::launch_chip_clear(C, (size_t)((L.chip_sbins - L.chip_cov) / 8), hs);
+    if (e != hipSuccess) return hip_fail(e, "scratch clear");
+    const gp::RenderOut o{d_rgb, nullptr, nullptr};
+    e = gp::launch_render_chip(sim->dev, o, C, 1, 0, (int)L.n_views, std::max(1, sim->launch.road_wgs_per_cu) * sim->n_cu,
+                               hs);
+    if (e != hipSuccess) return hip_fail(e, "render launch");
+    return GP_OK;
 }
 
 gp_status gp_sim_step_render_graph(gp_sim *sim, const float *d_actions, uint8_t *d_rgb, void *stream)

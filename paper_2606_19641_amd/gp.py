@@ -103,10 +103,11 @@ def lib() -> C.CDLL:
         L.gp_sim_set_light.argtypes = [vp, vp]
         L.gp_sim_set_signal_colors.argtypes = [vp, vp, vp]
         L.gp_sim_render_raycast.argtypes = [vp, vp, vp, vp, vp]
+        L.gp_sim_render_noalloc.argtypes = [vp, vp, vp]
         L.gp_sim_num_signals.argtypes = [vp]
         L.gp_sim_num_signals.restype = C.c_int64
         for name in ("gp_sim_check_infractions", "gp_sim_fork", "gp_sim_step_jerk", "gp_sim_get_actuators",
-                     "gp_sim_set_light", "gp_sim_set_signal_colors", "gp_sim_render_raycast",
+                     "gp_sim_set_light", "gp_sim_set_signal_colors", "gp_sim_render_raycast", "gp_sim_render_noalloc",
                      "gp_batch_step_render", "gp_sim_create", "gp_sim_set_launch", "gp_sim_get_launch",
                      "gp_sim_step", "gp_sim_render", "gp_sim_step_render_graph", "gp_sim_get_state",
                      "gp_sim_set_state"):
@@ -317,6 +318,14 @@ class Sim:
         _check(lib().gp_sim_render(self._h, rgb.data_ptr(), d.data_ptr() if d is not None else None,
                                    p.data_ptr() if p is not None else None, _stream_handle(stream)))
         return rgb, d, p
+
+    def render_noalloc(self, rgb=None, stream=None):
+        """rgb render whose scratch is the library's static device array (no
+        allocation in the call); returns rgb."""
+        rgb = self.new_rgb() if rgb is None else rgb
+        self._check_tensor(rgb, (self.n_views, self.camera.height, self.camera.width, 3), "uint8")
+        _check(lib().gp_sim_render_noalloc(self._h, rgb.data_ptr(), _stream_handle(stream)))
+        return rgb
 
     def step_render_graph(self, actions, rgb, stream=None):
         self._check_tensor(actions, (self.n_agents, 2), "float32")
