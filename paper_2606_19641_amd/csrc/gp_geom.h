@@ -420,6 +420,132 @@ __device__ __forceinline__ bool row_span(const TriGeo &t, int j, int W, int &xl_
     return xl <= xr;
 }
 
+// ------------------------------------------------------------ road quads
+//
+// A road strip's two fan triangles (0, 1, 2) and (0, 2, 3) cover, together,
+// exactly the samples of the quad's own four-edge test (the same top-left
+// rule on each edge) when the snapped quad is strictly convex and neither end
+// of the shared diagonal 0-2 lies on a sample point:
+//  - a sample strictly on one side of the diagonal can only be in the
+//    triangle on that side, and there the two quad edges the triangle lacks
+//    are strictly positive (strict convexity: the triangle meets their lines
+//    only at the diagonal's ends), so the triangle's test is the quad's;
+//  - a sample on the diagonal line has E = 0 for the diagonal in both
+//    triangles, run in opposite directions, so exactly one of the two counts
+//    it as a top-left edge; strictly between the ends it is inside the quad
+//    and inside that triangle, beyond an end both fail an edge through that
+//    end, as the quad does;
+//  - only the diagonal's ends themselves can differ (two edges meet there), so
+//    a quad with an end on a sample point keeps its triangles.
+// Coverage is all a road strip contributes in the rgb rasters (strips share
+// one plane and colour), so such a strip is rasterised as one quad.
+
+// A road primitive: a positively oriented triangle (nv 3, vertices 0..2) or
+// convex quad (nv 4), its sample rows [j0, j1], and whether it needs the
+// int64 span path (triangles only).
+struct Prim {
+    int32_t X0, Y0, X1, Y1, X2, Y2, X3, Y3;
+    int16_t j0, j1;
+    int16_t huge, nv;
+    int32_t pad0, pad1;
+};
+static_assert(sizeof(Prim) == 48, "Prim layout");
+
+__device__ __forceinline__ Prim prim_of(const TriGeo &t)
+{
+    Prim p;
+    p.X0 = t.X0; p.Y0 = t.Y0; p.X1 = t.X1; p.Y1 = t.Y1; p.X2 = t.X2; p.Y2 = t.Y2;
+    p.X3 = t.X0; p.Y3 = t.Y0;
+    p.j0 = t.j0; p.j1 = t.j1; p.huge = t.huge; p.nv = 3;
+    p.pad0 = 0; p.pad1 = 0;
+    return p;
+}
+
+// The quad of snapped corners X[k], Y[k] when it may replace its two fan
+// triangles (see above; also below 2^25 subpixels, the fp64 span range):
+// returns 1 with q set (positively oriented, rows [j0, j1] within [r0, r1)),
+// 0 if it covers no sample (bounding box without a sample), -1 when the
+// triangles must be used.
+__device__ __forceinline__ int make_quad(const Cam &c, const int32_t *X, const int32_t *Y, int r0, int r1, Prim &q)
+{
+    const int32_t lim = 1 << 25;
+    int32_t xmin = X[0], xmax = X[0], ymin = Y[0], ymax = Y[0];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+        xmin = min(xmin, X[k]); xmax = max(xmax, X[k]);
+        ymin = min(ymin, Y[k]); ymax = max(ymax, Y[k]);
+    }
+    if (xmin <= -lim || xmax >= lim || ymin <= -lim || ymax >= lim) return -1;
+    // the diagonal's ends on a sample point
+    if ((((X[0] - 128) & 255) == 0 && ((Y[0] - 128) & 255) == 0) ||
+        (((X[2] - 128) & 255) == 0 && ((Y[2] - 128) & 255) == 0))
+        return -1;
+    // strict convexity: the turn at every corner has one strict sign
+    int npos = 0, nneg = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int a = k, b = (k + 1) & 3, d = (k + 2) & 3;
+        const int64_t cr = (int64_t)(X[b] - X[a]) * (int64_t)(Y[d] - Y[b]) -
+                           (int64_t)(Y[b] - Y[a]) * (int64_t)(X[d] - X[b]);
+        npos += cr > 0;
+        nneg += cr < 0;
+    }
+    if (!(npos == 4 || nneg == 4)) return -1;
+    const int i0 = max((xmin - 128 + 255) >> 8, 0), i1 = min((xmax - 128) >> 8, c.W - 1);
+    const int j0 = max((ymin - 128 + 255) >> 8, r0), j1 = min((ymax - 128) >> 8, r1 - 1);
+    if (i0 > i1 || j0 > j1) return 0;
+    // positive orientation (every corner turn > 0, the orientation make_tri
+    // gives road triangles after its swap): reverse a quad turning the other
+    // way, keeping corner 0 and the diagonal 0-2 (its fan triangles are then
+    // the two swapped ones)
+    if (npos == 4) {
+        q.X0 = X[0]; q.Y0 = Y[0]; q.X1 = X[1]; q.Y1 = Y[1]; q.X2 = X[2]; q.Y2 = Y[2]; q.X3 = X[3]; q.Y3 = Y[3];
+    } else {
+        q.X0 = X[0]; q.Y0 = Y[0]; q.X1 = X[3]; q.Y1 = Y[3]; q.X2 = X[2]; q.Y2 = Y[2]; q.X3 = X[1]; q.Y3 = Y[1];
+    }
+    q.j0 = (int16_t)j0; q.j1 = (int16_t)j1;
+    q.huge = 0; q.nv = 4;
+    q.pad0 = 0; q.pad1 = 0;
+    return 1;
+}
+
+// Samples [xl, xr] of row j covered by a primitive (row_span for triangles;
+// the same exact per-edge bounds over the quad's four edges).
+__device__ __forceinline__ bool prim_span(const Prim &p, int j, int W, int &xl_out, int &xr_out)
+{
+    if (p.nv == 3) {
+        TriGeo t;
+        t.X0 = p.X0; t.Y0 = p.Y0; t.X1 = p.X1; t.Y1 = p.Y1; t.X2 = p.X2; t.Y2 = p.Y2;
+        t.j0 = p.j0; t.j1 = p.j1; t.huge = p.huge; t.pad = 0;
+        return row_span(t, j, W, xl_out, xr_out);
+    }
+    const int32_t X[4] = {p.X0, p.X1, p.X2, p.X3}, Y[4] = {p.Y0, p.Y1, p.Y2, p.Y3};
+    const double Sy = 256.0 * (double)j + 128.0;
+    const double Wd = (double)W;
+    double lo = 0.0, hi = Wd - 1.0;
+    bool empty = false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int k1 = (k + 1) & 3;
+        const int32_t dX = X[k1] - X[k], dY = Y[k1] - Y[k];
+        const double tk = (dY < 0 || (dY == 0 && dX > 0)) ? 0.0 : 1.0;
+        const double P = fma((double)dX, Sy - (double)Y[k], (double)dY * ((double)X[k] - 128.0));
+        const double N = P - tk;
+        empty = empty || (dY == 0 && N < 0.0);
+        const double D = 256.0 * (double)abs(dY);
+        const double qe = (double)((float)N * __builtin_amdgcn_rcpf((float)D));
+        double f = fmin(fmax(floor(qe), -Wd - 1.0), Wd + 1.0);
+        const double r = fma(-D, f, N);
+        f = r < 0.0 ? f - 1.0 : (r >= D ? f + 1.0 : f);
+        hi = dY > 0 ? fmin(hi, f) : hi;
+        lo = dY < 0 ? fmax(lo, -f) : lo;
+    }
+    const int xl = (int)lo, xr = empty ? -1 : (int)hi;
+    xl_out = xl;
+    xr_out = xr;
+    return xl <= xr;
+}
+
 // Pointers into LDS keep their address space in the type, so every access
 // through them is a ds_* instruction (a generic pointer would make the
 // compiler issue flat instructions, which go through the vector-memory path).

@@ -22,7 +22,7 @@
 //              coordinate is a non-increasing function of its depth; a strip
 //              whose depth range maps between two sample rows covers none).
 //              Survivors' camera-space corners go to the wave's ring; full
-//              setup (clip test, snap, the two fan triangles) runs 64 at a
+//              setup (clip test, snap, a quad or the two fan triangles) runs 48 at a
 //              time, and each batch of triangles is rasterised at once: per
 //              (triangle, row) the exact span of covered samples is OR-ed
 //              into the view's road coverage bitmask.  Strips that need
@@ -47,17 +47,16 @@ namespace gp {
 namespace {
 
 constexpr int kRing = 128;      // strips passed by the cheap test (road slot indices)
-constexpr int kWTris = 128;     // triangles staged for one span pass
+constexpr int kWTris = 96;      // road primitives (quads, triangles) staged for one span pass
 constexpr int kSetupBatch = kWTris / 2;   // strips set up at a time (two fan triangles each)
 constexpr int kWClip = kSetupBatch + 4;   // road strips waiting for the clipper: a setup batch on top of < 4
-constexpr int kWaveBytes = kRing * 4 + kWTris * 32 + kWClip * 4;
+constexpr int kWaveBytes = kRing * 4 + kWTris * 48 + kWClip * 4;
 static_assert(kWaveBytes % 16 == 0, "wave regions stay 16-byte aligned");
-static_assert(sizeof(TriGeo) == 32, "staged triangle size");
+static_assert(sizeof(Prim) == 48, "staged primitive size");
 
 // LDS counters
 enum { R_NSB = 0, R_NEXT, R_NBT, R_BOVF, R_BMIN, R_BMAX, R_NCNT = 8 };
 constexpr int kBoxClip = 64;     // box faces waiting for the clipper (one setup pass)
-constexpr int kSurvCap = kWTris * 8;  // boxes listed after culling (ints in the triangle staging's memory)
 
 struct RgbLds {
     lptr<int32_t> cnt;               // [R_NCNT]
@@ -100,7 +99,7 @@ __host__ __device__ inline RgbLayout rgb_layout(int W, int H, const RgbCfg &c)
 
 struct WaveSt {
     lptr<int32_t> ring;      // [kRing] road slots (global) that passed the cheap test
-    lptr<TriGeo> tris;       // [kWTris]
+    lptr<Prim> tris;         // [kWTris] road primitives
     lptr<int32_t> clipq;     // [kWClip] road slots (global) that need the clipper
     int head, tail;          // ring positions (wave-uniform, only grow)
     int nclip;               // queued strips
@@ -131,7 +130,7 @@ __device__ __forceinline__ void road_spans(const RgbLds &L, const Cam &cam, cons
         const int t = t0 + ln;
         int c = 0;
         if (t < n) {
-            const int32_t jj = ((lptr<const int32_t>)(ws.tris + t))[6];     // j0 | j1 << 16
+            const int32_t jj = ((lptr<const int32_t>)(ws.tris + t))[8];     // j0 | j1 << 16
             c = (jj >> 16) - (int)(int16_t)(jj & 0xFFFF);
         }
         const int incl = wave_incl_scan(c);
@@ -148,10 +147,10 @@ __device__ __forceinline__ void road_spans(const RgbLds &L, const Cam &cam, cons
                 act = gi < total;
             }
             if (act) {
-                const TriGeo tg = lds_load((lptr<TriGeo>)(ws.tris + t0 + o));
-                const int j = tg.j0 + extra;
+                const Prim pr = lds_load(ws.tris + t0 + o);
+                const int j = pr.j0 + extra;
                 int xl, xr;
-                if (row_span(tg, j, cam.W, xl, xr)) or_span(L.bits + (size_t)j * L.nw, xl, xr);
+                if (prim_span(pr, j, cam.W, xl, xr)) or_span(L.bits + (size_t)j * L.nw, xl, xr);
             }
         }
     }
@@ -159,12 +158,12 @@ __device__ __forceinline__ void road_spans(const RgbLds &L, const Cam &cam, cons
 }
 
 // Stage the triangles held by the lanes (v0: t0, v1: t1); returns how many.
-__device__ __forceinline__ int stage_tris(const WaveSt &ws, bool v0, const TriGeo &t0, bool v1, const TriGeo &t1)
+__device__ __forceinline__ int stage_tris(const WaveSt &ws, bool v0, const Prim &t0, bool v1, const Prim &t1)
 {
     const unsigned long long b0 = __ballot(v0), b1 = __ballot(v1);
     const int n0 = __popcll(b0);
-    if (v0) lds_store((lptr<TriGeo>)(ws.tris + lanes_below(b0)), t0);
-    if (v1) lds_store((lptr<TriGeo>)(ws.tris + n0 + lanes_below(b1)), t1);
+    if (v0) lds_store(ws.tris + lanes_below(b0), t0);
+    if (v1) lds_store(ws.tris + n0 + lanes_below(b1), t1);
     return n0 + __popcll(b1);
 }
 
@@ -186,8 +185,8 @@ __device__ __forceinline__ int road_clip(const DevSim &s, const Cam &cam, WaveSt
     ws.nclip -= m;
     TriRec t;
     const bool ok = clip_seg<false>(cam, P, live, 0, cam.H, t);
-    TriGeo none = {};
-    return stage_tris(ws, ok, t.g, false, none);
+    Prim none = {};
+    return stage_tris(ws, ok, prim_of(t.g), false, none);
 }
 
 // Full setup of n (<= kSetupBatch) strips from the ring: clip test, snap and the two
@@ -210,16 +209,25 @@ __device__ __forceinline__ int road_setup(const DevSim &s, const Cam &cam, WaveS
     const unsigned long long cb = __ballot(clip);
     if (clip) ws.clipq[ws.nclip + lanes_below(cb)] = g;
     ws.nclip += __popcll(cb);
-    TriGeo t0, t1;
+    Prim p0 = {}, p1 = {};
     bool v0 = false, v1 = false;
     if (live && !clip) {
         int32_t X[4], Y[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) snap(cam, v[k], X[k], Y[k]);
-        v0 = make_tri(cam, false, X[0], Y[0], X[1], Y[1], X[2], Y[2], 0, cam.H, t0);
-        v1 = make_tri(cam, false, X[0], Y[0], X[2], Y[2], X[3], Y[3], 0, cam.H, t1);
+        // one quad where it covers exactly what the two fan triangles cover
+        const int qs = make_quad(cam, X, Y, 0, cam.H, p0);
+        if (qs > 0) {
+            v0 = true;
+        } else if (qs < 0) {
+            TriGeo t0, t1;
+            v0 = make_tri(cam, false, X[0], Y[0], X[1], Y[1], X[2], Y[2], 0, cam.H, t0);
+            v1 = make_tri(cam, false, X[0], Y[0], X[2], Y[2], X[3], Y[3], 0, cam.H, t1);
+            if (v0) p0 = prim_of(t0);
+            if (v1) p1 = prim_of(t1);
+        }
     }
-    return stage_tris(ws, v0, t0, v1, t1);
+    return stage_tris(ws, v0, p0, v1, p1);
 }
 
 // The cheap test of one unit's strips (loaded by load_unit into q0, q1); the
@@ -259,15 +267,38 @@ __device__ __forceinline__ bool load_unit(const DevSim &s, const SceneRec &sc, c
 
 // ------------------------------------------------------------ boxes
 
+// Reserve n entries of the box list: at the wave's own count nbt (shared
+// false: the overflow path's private list), or through the view's LDS
+// counter (shared: several wavefronts append); returns the first entry, or
+// -1 (marking the view overflowed when shared) if they would not fit.
+__device__ __forceinline__ int box_reserve(const RgbLds &L, bool shared, int &nbt, int n)
+{
+    if (!shared) {
+        if (nbt + n > L.bcap) return -1;
+        const int at = nbt;
+        nbt += n;
+        return at;
+    }
+    int at = 0;
+    if (lane_id() == 0 && n > 0) at = lds_add(L.cnt + R_NBT, n);
+    at = __builtin_amdgcn_readfirstlane(__shfl(at, 0));
+    if (at + n > L.bcap) {
+        if (lane_id() == 0) L.cnt[R_BOVF] = 1;
+        return -1;
+    }
+    return at;
+}
+
 // One setup pass over box face candidates [c0, c0 + P) (P <= 64): candidate c
 // is face c % 6 of box surv[c / 6] (use_surv), or of box c / 6 culled here.
-// Fast triangles and clipped faces are appended to the box list at *nbt;
-// returns false as soon as the triangles would not fit (the list is then
-// incomplete: the caller takes the overflow path, which ignores it).  Eight
-// candidates at a time never overflow a list of 96 (at most 10 triangles each).
+// Fast triangles and clipped faces (clip queue cq) are appended to the box
+// list (box_reserve); returns false as soon as the triangles would not fit
+// (the list is then incomplete: the view takes the overflow path, which
+// ignores it).  Eight candidates at a time never overflow a private list of
+// 96 (at most 10 triangles each).
 __device__ __forceinline__ bool box_pass(const DevSim &s, const SceneRec &sc, const Cam &cam, int ego, const RgbLds &L,
-                         lptr<const int32_t> surv, bool use_surv, int ncand, int c0, int P, int &nbt, int &bmin,
-                         int &bmax)
+                         lptr<const int32_t> surv, bool use_surv, int ncand, int c0, int P, lptr<int32_t> cq,
+                         bool shared, int &nbt, int &bmin, int &bmax)
 {
     const int ln = (int)lane_id();
     const int c = c0 + ln;
@@ -287,13 +318,13 @@ __device__ __forceinline__ bool box_pass(const DevSim &s, const SceneRec &sc, co
     }
     const unsigned long long b0 = __ballot(v0), b1 = __ballot(v1), bc = __ballot(clip);
     const int n0 = __popcll(b0), nf = n0 + __popcll(b1), ncl = __popcll(bc);
-    if (nbt + nf > L.bcap) return false;
-    if (v0) lds_store(L.btris + nbt + lanes_below(b0), t0);
-    if (v1) lds_store(L.btris + nbt + n0 + lanes_below(b1), t1);
+    const int at = box_reserve(L, shared, nbt, nf);
+    if (at < 0) return false;
+    if (v0) lds_store(L.btris + at + lanes_below(b0), t0);
+    if (v1) lds_store(L.btris + at + n0 + lanes_below(b1), t1);
     if (v0) { bmin = min(bmin, (int)t0.g.j0); bmax = max(bmax, (int)t0.g.j1); }
     if (v1) { bmin = min(bmin, (int)t1.g.j0); bmax = max(bmax, (int)t1.g.j1); }
-    nbt += nf;
-    if (clip) L.cq[lanes_below(bc)] = j * 8 + f;
+    if (clip) cq[lanes_below(bc)] = j * 8 + f;
     wave_lds_order();
     // the clipped faces, four per wavefront
     for (int q0 = 0; q0 < ncl; q0 += 4) {
@@ -301,59 +332,47 @@ __device__ __forceinline__ bool box_pass(const DevSim &s, const SceneRec &sc, co
         const bool lv = q < ncl;
         Poly Q = {};
         if (lv) {
-            const int code = L.cq[q];
+            const int code = cq[q];
             build_face(s, sc, cam, code >> 3, code & 7, Q);
         }
         TriRec t;
         const bool ok = clip_seg<true>(cam, Q, lv, 0, cam.H, t);
         const unsigned long long bo = __ballot(ok);
-        if (nbt + __popcll(bo) > L.bcap) return false;
+        const int ato = box_reserve(L, shared, nbt, __popcll(bo));
+        if (ato < 0) return false;
         if (ok) {
-            lds_store(L.btris + nbt + lanes_below(bo), t);
+            lds_store(L.btris + ato + lanes_below(bo), t);
             bmin = min(bmin, (int)t.g.j0);
             bmax = max(bmax, (int)t.g.j1);
         }
-        nbt += __popcll(bo);
     }
     return true;
 }
 
-// The box unit: cull every box of the scene, list the survivors, set up their
-// faces into the view's box triangle list.  Publishes the list length, its
-// row range and whether it overflowed.
+// Box unit k: cull boxes [kBoxUnit k, kBoxUnit (k + 1)) of the scene, list
+// the survivors, set up their faces into the view's box triangle list
+// (shared by the wavefronts; its row range kept with LDS min / max).  scr:
+// 128 ints of the wavefront's staging (survivors, then the clip queue).
+constexpr int kBoxUnit = 16;
 __device__ __forceinline__ void do_boxes(const DevSim &s, const SceneRec &sc, const Cam &cam, int ego, const RgbLds &L,
-                         lptr<int32_t> surv)
+                                         int k, lptr<int32_t> scr)
 {
     const int ln = (int)lane_id();
     const int nbox = sc.n_agents + sc.n_static;
-    int ns = 0;
-    bool ovf = false;
-    for (int b0 = 0; b0 < nbox && !ovf; b0 += 64) {
-        const int j = b0 + ln;
-        const bool keep = j < nbox && j != ego && !box_outside(s, sc, cam, j);
-        const unsigned long long bm = __ballot(keep);
-        if (ns + __popcll(bm) > kSurvCap) {
-            ovf = true;          // more visible boxes than the list holds
-            break;
-        }
-        if (keep) surv[ns + lanes_below(bm)] = j;
-        ns += __popcll(bm);
-    }
+    const int j = kBoxUnit * k + ln;
+    const bool keep = ln < kBoxUnit && j < nbox && j != ego && !box_outside(s, sc, cam, j);
+    const unsigned long long bm = __ballot(keep);
+    if (keep) scr[lanes_below(bm)] = j;
+    const int ns = __popcll(bm);
     wave_lds_order();
     int nbt = 0, bmin = 0x7FFFFFFF, bmax = -1;
-    for (int c0 = 0; c0 < 6 * ns && !ovf; c0 += 64) {
-        if (!box_pass(s, sc, cam, ego, L, surv, true, 6 * ns, c0, 64, nbt, bmin, bmax)) {
-            ovf = true;
-            break;
-        }
-    }
+    for (int c0 = 0; c0 < 6 * ns; c0 += 64)
+        if (!box_pass(s, sc, cam, ego, L, scr, true, 6 * ns, c0, 64, scr + 64, true, nbt, bmin, bmax)) break;
     bmin = wave_min(bmin);
     bmax = wave_max(bmax);
-    if (ln == 0) {
-        L.cnt[R_NBT] = nbt;
-        L.cnt[R_BOVF] = ovf ? 1 : 0;
-        L.cnt[R_BMIN] = bmin;
-        L.cnt[R_BMAX] = bmax;
+    if (ln == 0 && bmax >= 0) {
+        lds_min(L.cnt + R_BMIN, bmin);
+        lds_max(L.cnt + R_BMAX, bmax);
     }
 }
 
@@ -638,7 +657,7 @@ __device__ __forceinline__ void render_view_rgb(const DevSim &s, const RenderOut
     const int W = cam.W, H = cam.H;
 
     for (int p = tid; p < H * L.nw; p += B) L.bits[p] = 0ull;
-    if (tid < R_NCNT) L.cnt[tid] = 0;
+    if (tid < R_NCNT) L.cnt[tid] = tid == R_BMIN ? 0x7FFFFFFF : (tid == R_BMAX ? -1 : 0);
     __syncthreads();
 
     // ---- A: road culling bins
@@ -668,14 +687,16 @@ __device__ __forceinline__ void render_view_rgb(const DevSim &s, const RenderOut
     }
     __syncthreads();
 
-    // ---- B: work units (0: boxes, u >= 1: surviving bins 4 (u - 1) .. 4 (u - 1) + 3)
+    // ---- B: work units (u < nbu: boxes kBoxUnit u .. kBoxUnit u + kBoxUnit - 1,
+    // then surviving bins 4 (u - nbu) .. 4 (u - nbu) + 3)
     const int nsb = L.cnt[R_NSB];
-    const int n_units = 1 + (nsb + 3) / 4;
+    const int nbu = (sc.n_agents + sc.n_static + kBoxUnit - 1) / kBoxUnit;
+    const int n_units = nbu + (nsb + 3) / 4;
     lptr<unsigned char> wbase = L.waves + (size_t)wv * kWaveBytes;
     WaveSt ws;
-    ws.tris = (lptr<TriGeo>)wbase;
-    ws.ring = (lptr<int32_t>)(wbase + kWTris * 32);
-    ws.clipq = (lptr<int32_t>)(wbase + kWTris * 32 + kRing * 4);
+    ws.tris = (lptr<Prim>)wbase;
+    ws.ring = (lptr<int32_t>)(wbase + kWTris * 48);
+    ws.clipq = (lptr<int32_t>)(wbase + kWTris * 48 + kRing * 4);
     ws.head = ws.tail = ws.nclip = 0;
     auto take = [&]() -> int {
         int u = 0;
@@ -689,7 +710,7 @@ __device__ __forceinline__ void render_view_rgb(const DevSim &s, const RenderOut
     int u = take();
     float4 q0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), q1 = q0;
     int gq = 0;
-    bool live = load_unit(s, sc, L, nsb, u - 1, gq, q0, q1);
+    bool live = load_unit(s, sc, L, nsb, u - nbu, gq, q0, q1);
     bool final = false;
     for (;;) {
         int ntri = 0;
@@ -705,10 +726,10 @@ __device__ __forceinline__ void render_view_rgb(const DevSim &s, const RenderOut
             const int un = take();
             float4 n0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), n1 = n0;
             int gn = 0;
-            const bool nlive = load_unit(s, sc, L, nsb, un - 1, gn, n0, n1);
-            if (u == 0) {
-                // the box unit is the first one dealt: this wave's staging is still empty
-                do_boxes(s, sc, cam, ego, L, (lptr<int32_t>)ws.tris);
+            const bool nlive = load_unit(s, sc, L, nsb, un - nbu, gn, n0, n1);
+            if (u < nbu) {
+                // the triangle staging is free between iterations: survivors and clip queue
+                do_boxes(s, sc, cam, ego, L, u, (lptr<int32_t>)ws.tris);
             } else {
                 road_unit(cam, ws, live, gq, q0, q1);
             }
@@ -770,7 +791,8 @@ __device__ __forceinline__ void render_view_rgb(const DevSim &s, const RenderOut
             const int ncand = 6 * (sc.n_agents + sc.n_static);
             for (int c0 = 0; c0 < ncand; c0 += 8) {
                 int n = 0, bmn = 0, bmx = 0;
-                (void)box_pass(s, sc, cam, ego, L, (lptr<const int32_t>)L.sbins, false, ncand, c0, 8, n, bmn, bmx);
+                (void)box_pass(s, sc, cam, ego, L, (lptr<const int32_t>)L.sbins, false, ncand, c0, 8, L.cq, false, n, bmn,
+                               bmx);
                 wave_lds_order();
                 box_band(L, cam, keys, n, 0, 1, b0, b1);
                 wave_lds_order();
