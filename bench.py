@@ -32,13 +32,25 @@ COPY_BYTES = 256 << 20
 # the workloads' episodes: 100 steps of random actions from the initial placement
 EPISODE_STEPS = 100
 COUNTERS = os.path.join(ROOT, "profiles", "k_render_rgb_uniform128_counters.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_2606_19641_amd", "csrc", "gp_kernels.hip")
+RASTER_KERNELS = {0: "k_render (banded)", 1: "k_render_rgb (wave-split)",
+                  2: "k_chip_setup + k_chip_roads + k_chip_resolve (chip-wide)"}
 
 
 def kernel_source_sha() -> str:
-    import hashlib
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    """sha256 over the HIP sources and headers (the tuner's cache key uses it too)."""
+    from paper_2606_19641_amd import tune
+    return tune.kernel_source_sha()
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def measured_counters(workload_name: str, launch: dict):
@@ -141,6 +153,7 @@ def cpu_baseline(w, budget_s: float):
     done, steps, dt = _oracle_rate(w, budget_s, threads)
     d1, _, t1 = _oracle_rate(w, max(1.0, budget_s / 4), 1)
     return {"value": done / dt, "unit": "agent-views/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
             "single_thread_value": d1 / t1,
             "sample": f"{done} views over {steps} step(s) of the same workload ({w.n_views} views per "
                       f"step; agent step + every view; {threads} threads, {dt:.1f} s); single thread: "
@@ -465,7 +478,11 @@ def main():
         "dtype": "f32",
         "data": "synthetic (seeded scenes standing in for nuPlan)",
         "config": {"workload": _describe(w), "views_per_step": V, "seed": w.seed,
-                   "schedule": "persistent work queue (one workgroup per view when the views fit the resident grid) + hipGraph (step + render)",
+                   "schedule": ("one workgroup per view, the dispatcher balancing uneven views"
+                                if launch.get("raster") == 1 else
+                                "three chip-wide passes" if launch.get("raster") == 2 else
+                                "persistent work queue (one workgroup per view when the views fit the resident grid)")
+                               + " + hipGraph (step + render)",
                    "launch": launch},
         "plain_value": plain,
         "batched_over_plain": (batched / plain) if plain else None,
@@ -478,7 +495,7 @@ def main():
         "render_rates": rates,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": meas["traffic"] if meas else None,
-                     "kernel": "k_render", "bytes_per_launch": rb,
+                     "kernel": RASTER_KERNELS.get(launch.get("raster"), "k_render"), "bytes_per_launch": rb,
                      "valu_busy_pct": meas["valu_busy_pct"] if meas else None,
                      "lds_bank_conflict_pct": meas["lds_bank_conflict_pct"] if meas else None},
         # the plain VALU roof beside the HBM one: wave instructions x 64 lanes

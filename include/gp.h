@@ -205,7 +205,10 @@ gp_status gp_sim_render_noalloc(gp_sim *sim, uint8_t *d_rgb, void *stream);
  * first use and rebuilt when the image pointer or the launch settings change;
  * a new d_actions pointer only updates the step node's arguments, so callers
  * may pass each step's own action buffer without a copy.  Uses the persistent
- * schedule whatever the current launch setting. */
+ * schedule whatever the current launch setting.  A sim of at most 64 views
+ * launches the step and the render directly instead (same kernels and
+ * images): at that size a graph replay costs more host time than the two
+ * launches. */
 gp_status gp_sim_step_render_graph(gp_sim *sim, const float *d_actions, uint8_t *d_rgb, void *stream);
 
 /* Traffic-light states: d_colors, device uint8 [num_signals], the palette

@@ -420,6 +420,82 @@ __device__ __forceinline__ bool row_span(const TriGeo &t, int j, int W, int &xl_
     return xl <= xr;
 }
 
+// The same exact spans, written with a branch per edge orientation and the
+// int64 path inline: the banded kernels' form (fewer registers live there
+// than with row_span's branch-free form and out-of-line int64 path, which
+// keeps them at three wavefronts per SIMD).  Identical results.
+__device__ __forceinline__ bool row_span_int64_inl(const TriGeo &t, int j, int W, int &xl_out, int &xr_out)
+{
+    const int32_t X[3] = {t.X0, t.X1, t.X2}, Y[3] = {t.Y0, t.Y1, t.Y2};
+    int xl = 0, xr = W - 1;
+    const int64_t Sy = 256 * (int64_t)j + 128;
+    for (int k = 0; k < 3; ++k) {
+        const int k1 = (k == 2) ? 0 : k + 1;
+        const int64_t dX = (int64_t)X[k1] - X[k], dY = (int64_t)Y[k1] - Y[k];
+        const int64_t tk = (dY < 0 || (dY == 0 && dX > 0)) ? 0 : 1;
+        const int64_t P = dX * (Sy - Y[k]) + dY * ((int64_t)X[k] - 128);
+        if (dY == 0) {
+            if (P < tk) return false;
+            continue;
+        }
+        if (dY > 0) {
+            const int64_t ic = floor_div64(P - tk, 256 * dY);
+            xr = (int)min((int64_t)xr, max(ic, (int64_t)-1));
+        } else {
+            // i >= (tk - P) / (256 |dY|), rounded up: ceil(-x) = -floor(x)
+            const int64_t ic = -floor_div64(P - tk, 256 * (-dY));
+            xl = (int)max((int64_t)xl, min(ic, (int64_t)W));
+        }
+    }
+    xl_out = xl;
+    xr_out = xr;
+    return xl <= xr;
+}
+
+__device__ __forceinline__ bool row_span_banded(const TriGeo &t, int j, int W, int &xl_out, int &xr_out)
+{
+    const int32_t X[3] = {t.X0, t.X1, t.X2}, Y[3] = {t.Y0, t.Y1, t.Y2};
+    int xl = 0, xr = W - 1;
+    if (!t.huge) {
+        // every term is an integer below 2^53: fp64 is exact here
+        const double Sy = 256.0 * (double)j + 128.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int k1 = (k == 2) ? 0 : k + 1;
+            const int32_t dX = X[k1] - X[k], dY = Y[k1] - Y[k];
+            const double tk = (dY < 0 || (dY == 0 && dX > 0)) ? 0.0 : 1.0;
+            const double P = fma((double)dX, Sy - (double)Y[k], (double)dY * ((double)X[k] - 128.0));
+            if (dY == 0) {
+                if (P < tk) return false;
+                continue;
+            }
+            const double D = 256.0 * (double)dY;
+            // estimate of (P - tk) / D from a binary32 reciprocal: relative
+            // error below 2^-21, so within 1 of the quotient wherever the
+            // quotient lies in [-2, W + 1]; outside that range the clamp
+            // below decides, and the exact test that follows moves the
+            // estimate by at most one to the exact boundary
+            const double q = (double)((float)(P - tk) * __builtin_amdgcn_rcpf((float)D));
+            if (dY > 0) {            // E decreases with i: i <= q
+                double ic = fmin(fmax(floor(q), -1.0), (double)W);
+                if (P - D * ic < tk) ic -= 1.0;
+                else if (P - D * (ic + 1.0) >= tk) ic += 1.0;
+                xr = min(xr, (int)ic);
+            } else {                 // E increases with i: i >= q
+                double ic = fmin(fmax(ceil(q), -1.0), (double)W);
+                if (P - D * ic < tk) ic += 1.0;
+                else if (P - D * (ic - 1.0) >= tk) ic -= 1.0;
+                xl = max(xl, (int)ic);
+            }
+        }
+    } else {
+        return row_span_int64_inl(t, j, W, xl_out, xr_out);
+    }
+    xl_out = xl;
+    xr_out = xr;
+    return xl <= xr;
+}
+
 // ------------------------------------------------------------ road quads
 //
 // A road strip's two fan triangles (0, 1, 2) and (0, 2, 3) cover, together,

@@ -436,7 +436,7 @@ __device__ __noinline__ void raster_roads(Lds L, int W, int n)
         const TriGeo tg = lds_load(L.rtris + t);
         const int j = tg.j0 + (gi - L.scan[t]);
         int xl, xr;
-        if (!row_span(tg, j, W, xl, xr)) continue;
+        if (!row_span_banded(tg, j, W, xl, xr)) continue;
         lptr<unsigned long long> row = L.road + (size_t)j * L.nw;
         const int w0 = xl >> 6, w1 = xr >> 6;
         for (int wd = w0; wd <= w1; ++wd) {
@@ -505,7 +505,7 @@ __device__ __noinline__ void raster_tris(Lds L, int W, float cx, float cy, int n
             }
             const TriRec tr = lds_load(L.tris + t);
             j = max((int)tr.g.j0, b0) + (gi - start);
-            has = row_span(tr.g, j, W, xl, xr);
+            has = row_span_banded(tr.g, j, W, xl, xr);
             A = tr.A; B = tr.B; Cc = tr.C; key = tr.keylo;
         }
         unsigned long long m = __ballot(has);
@@ -1237,7 +1237,7 @@ __device__ __forceinline__ void load_palette(const DevSim &s, Lds &L, int fast)
 // BLOCK is the launch's block size: the bound lets the register allocator
 // use what a BLOCK-thread workgroup can have instead of assuming 1024 threads.
 template <int KIND, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_render(DevSim s, RenderOut o, LaunchCfg lc, int persistent,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 256 ? 3 : 1))) void k_render(DevSim s, RenderOut o, LaunchCfg lc, int persistent,
                                                   int view_begin)
 {
     constexpr int FAST = KIND == 1 ? 1 : 0;
@@ -1269,7 +1269,7 @@ __global__ __launch_bounds__(BLOCK) void k_render(DevSim s, RenderOut o, LaunchC
 // counts the workgroups that have left; the last one zeroes both.  Every sim
 // of the batch has W x H images; the palette is reloaded when the sim changes.
 template <int KIND, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_render_multi(const SimEntry *__restrict__ tab,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(BLOCK == 256 ? 3 : 1))) void k_render_multi(const SimEntry *__restrict__ tab,
                                                         const int2 *__restrict__ items, int n_items,
                                                         uint32_t *ctl, LaunchCfg lc, int W, int H)
 {

@@ -46,16 +46,16 @@ namespace gp {
 
 namespace {
 
-constexpr int kRing = 128;      // strips passed by the cheap test (road slot indices)
+constexpr int kSharedRing = 256;   // strips passed by the cheap test, one ring per view (road slot indices)
 constexpr int kWTris = 96;      // road primitives (quads, triangles) staged for one span pass
 constexpr int kSetupBatch = kWTris / 2;   // strips set up at a time (two fan triangles each)
-constexpr int kWClip = kSetupBatch + 4;   // road strips waiting for the clipper: a setup batch on top of < 4
-constexpr int kWaveBytes = kRing * 4 + kWTris * 48 + kWClip * 4;
+constexpr int kWClip = kSetupBatch;       // road strips of one setup job waiting for the clipper
+constexpr int kWaveBytes = kWTris * 48 + kWClip * 4;
 static_assert(kWaveBytes % 16 == 0, "wave regions stay 16-byte aligned");
 static_assert(sizeof(Prim) == 48, "staged primitive size");
 
 // LDS counters
-enum { R_NSB = 0, R_NEXT, R_NBT, R_BOVF, R_BMIN, R_BMAX, R_NCNT = 8 };
+enum { R_NSB = 0, R_NEXT, R_NBT, R_BOVF, R_BMIN, R_BMAX, R_RING, R_RESV, R_JOB, R_NCNT = 12 };
 constexpr int kBoxClip = 64;     // box faces waiting for the clipper (one setup pass)
 
 struct RgbLds {
@@ -66,6 +66,7 @@ struct RgbLds {
     lptr<TriRec> btris;              // [bcap] the view's box triangles
     lptr<int32_t> sbins;             // [bins_cap] surviving bins: start * 128 + count
     lptr<int32_t> cq;                // [kBoxClip] box faces to clip (box * 8 + face)
+    lptr<int32_t> sring;             // [kSharedRing] strips that passed the cheap test (this round)
     lptr<unsigned char> waves;       // K regions of kWaveBytes
     int nw, bcap, krows;
     int region;                      // bytes from sbins to the end (free after the units)
@@ -75,7 +76,7 @@ __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t
 
 // byte offsets of the LDS sections (shared by the carve and the size query)
 struct RgbLayout {
-    size_t cnt, pal, lut, bits, btris, sbins, cq, waves, total;
+    size_t cnt, pal, lut, bits, btris, sbins, cq, sring, waves, total;
 };
 
 __host__ __device__ inline RgbLayout rgb_layout(int W, int H, const RgbCfg &c)
@@ -90,6 +91,7 @@ __host__ __device__ inline RgbLayout rgb_layout(int W, int H, const RgbCfg &c)
     l.btris = o; o = align16(o + sizeof(TriRec) * (size_t)c.bcap);
     l.cq = o; o = align16(o + 4 * (size_t)kBoxClip);
     l.sbins = o; o = align16(o + 4 * (size_t)c.bins_cap);
+    l.sring = o; o = align16(o + 4 * (size_t)kSharedRing);
     l.waves = o; o = align16(o + (size_t)kWaveBytes * (size_t)c.waves);
     l.total = o;
     return l;
@@ -98,10 +100,8 @@ __host__ __device__ inline RgbLayout rgb_layout(int W, int H, const RgbCfg &c)
 // ------------------------------------------------------------ per-wave state
 
 struct WaveSt {
-    lptr<int32_t> ring;      // [kRing] road slots (global) that passed the cheap test
     lptr<Prim> tris;         // [kWTris] road primitives
     lptr<int32_t> clipq;     // [kWClip] road slots (global) that need the clipper
-    int head, tail;          // ring positions (wave-uniform, only grow)
     int nclip;               // queued strips
 };
 
@@ -189,11 +189,11 @@ __device__ __forceinline__ int road_clip(const DevSim &s, const Cam &cam, WaveSt
     return stage_tris(ws, ok, prim_of(t.g), false, none);
 }
 
-// Full setup of n (<= kSetupBatch) strips from the ring: clip test, snap and the two
-// fan triangles of the strips that need no clipping (staged; returns how
-// many); the others join the clip queue (which has room: fewer than four
-// wait whenever a setup runs).
-__device__ __forceinline__ int road_setup(const DevSim &s, const Cam &cam, WaveSt &ws, int n)
+// Full setup of the n (<= kSetupBatch) strips ring[a .. a + n): clip test,
+// snap and a quad or the two fan triangles of the strips that need no
+// clipping (staged; returns how many); the others join the wave's clip queue
+// (empty when a job starts).
+__device__ __forceinline__ int road_setup(const DevSim &s, const Cam &cam, const RgbLds &L, WaveSt &ws, int a, int n)
 {
     const int ln = (int)lane_id();
     wave_lds_order();
@@ -201,10 +201,9 @@ __device__ __forceinline__ int road_setup(const DevSim &s, const Cam &cam, WaveS
     int g = 0;
     V3 v[4] = {};
     if (live) {
-        g = ws.ring[(ws.head + ln) & (kRing - 1)];
+        g = L.sring[a + ln];
         road_corners(s, cam, g, v);
     }
-    ws.head += n;
     const bool clip = live && needs_clip(cam, v);
     const unsigned long long cb = __ballot(clip);
     if (clip) ws.clipq[ws.nclip + lanes_below(cb)] = g;
@@ -231,8 +230,8 @@ __device__ __forceinline__ int road_setup(const DevSim &s, const Cam &cam, WaveS
 }
 
 // The cheap test of one unit's strips (loaded by load_unit into q0, q1); the
-// survivors' camera-space corners go to the ring.
-__device__ __forceinline__ void road_unit(const Cam &cam, WaveSt &ws, bool live, int g, const float4 &q0,
+// survivors' slots go to the view's ring (64 entries were reserved).
+__device__ __forceinline__ void road_unit(const Cam &cam, const RgbLds &L, bool live, int g, const float4 &q0,
                                           const float4 &q1)
 {
     float x[4], z[4];
@@ -242,8 +241,10 @@ __device__ __forceinline__ void road_unit(const Cam &cam, WaveSt &ws, bool live,
     ground_xz(cam, q1.z, q1.w, x[3], z[3]);
     const bool pass = live && !road_culled<false>(cam, x, z);
     const unsigned long long bm = __ballot(pass);
-    if (pass) ws.ring[(ws.tail + lanes_below(bm)) & (kRing - 1)] = g;
-    ws.tail += __popcll(bm);
+    int base = 0;
+    if (lane_id() == 0 && bm != 0ull) base = lds_add(L.cnt + R_RING, __popcll(bm));
+    base = __shfl(base, 0);
+    if (pass) L.sring[base + lanes_below(bm)] = g;
 }
 
 // strip data of unit u (lane l: strip l % 16 of surviving bin 4 u + l / 16)
@@ -687,64 +688,84 @@ __device__ __forceinline__ void render_view_rgb(const DevSim &s, const RenderOut
     }
     __syncthreads();
 
-    // ---- B: work units (u < nbu: boxes kBoxUnit u .. kBoxUnit u + kBoxUnit - 1,
-    // then surviving bins 4 (u - nbu) .. 4 (u - nbu) + 3)
+    // ---- B: rounds of two steps, each dealt over the view's wavefronts
+    // through LDS counters.  B1: the units (u < nbu: boxes kBoxUnit u ..
+    // kBoxUnit u + kBoxUnit - 1; then four surviving bins each): box set-up, or
+    // the cheap test of a road unit's strips with the survivors appended to
+    // the view's ring (a road unit is taken only with 64 free ring entries
+    // reserved).  B2: set-up jobs of kSetupBatch ring strips: set-up, the
+    // clipper for the strips that need it, and the spans of every primitive.
+    // A round ends when the ring is full or the units are used up.
     const int nsb = L.cnt[R_NSB];
     const int nbu = (sc.n_agents + sc.n_static + kBoxUnit - 1) / kBoxUnit;
     const int n_units = nbu + (nsb + 3) / 4;
     lptr<unsigned char> wbase = L.waves + (size_t)wv * kWaveBytes;
     WaveSt ws;
     ws.tris = (lptr<Prim>)wbase;
-    ws.ring = (lptr<int32_t>)(wbase + kWTris * 48);
-    ws.clipq = (lptr<int32_t>)(wbase + kWTris * 48 + kRing * 4);
-    ws.head = ws.tail = ws.nclip = 0;
+    ws.clipq = (lptr<int32_t>)(wbase + kWTris * 48);
+    ws.nclip = 0;
+    // the next unit with its ring entries reserved, or n_units (none left, or
+    // the ring cannot take another road unit this round)
     auto take = [&]() -> int {
-        int u = 0;
-        if (ln == 0) u = lds_add(L.cnt + R_NEXT, 1);
+        int u = n_units;
+        if (ln == 0) {
+            const int r = lds_add(L.cnt + R_RESV, 64);
+            if (r + 64 <= kSharedRing) {
+                u = min(lds_add(L.cnt + R_NEXT, 1), n_units);
+                if (u < nbu || u == n_units) lds_add(L.cnt + R_RESV, -64);   // no strips from it
+            } else {
+                lds_add(L.cnt + R_RESV, -64);
+            }
+        }
         return __builtin_amdgcn_readfirstlane(__shfl(u, 0));
     };
-    // One action per iteration, every part of the pipeline at one place in
-    // the code: clip when four strips wait, set up when a batch of 64 waits,
-    // else take the next unit (the box unit or four bins) and prefetch the
-    // strips of the one after it; at the end, drain the ring and the queue.
-    int u = take();
-    float4 q0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), q1 = q0;
-    int gq = 0;
-    bool live = load_unit(s, sc, L, nsb, u - nbu, gq, q0, q1);
-    bool final = false;
     for (;;) {
-        int ntri = 0;
-        if (ws.nclip >= 4 || (final && ws.nclip > 0)) {
-            ntri = road_clip(s, cam, ws);
-        } else if (ws.tail - ws.head >= kSetupBatch || (final && ws.tail > ws.head)) {
-            ntri = road_setup(s, cam, ws, min(kSetupBatch, ws.tail - ws.head));
-        } else if (!final) {
-            if (u >= n_units) {
-                final = true;
-                continue;
-            }
+        // B1, the next unit's strips loaded while the current one is tested
+        int u = take();
+        float4 q0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), q1 = q0;
+        int gq = 0;
+        bool live = u < n_units && load_unit(s, sc, L, nsb, u - nbu, gq, q0, q1);
+        while (u < n_units) {
             const int un = take();
             float4 n0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), n1 = n0;
             int gn = 0;
-            const bool nlive = load_unit(s, sc, L, nsb, un - nbu, gn, n0, n1);
-            if (u < nbu) {
-                // the triangle staging is free between iterations: survivors and clip queue
-                do_boxes(s, sc, cam, ego, L, u, (lptr<int32_t>)ws.tris);
-            } else {
-                road_unit(cam, ws, live, gq, q0, q1);
-            }
+            const bool nlive = un < n_units && load_unit(s, sc, L, nsb, un - nbu, gn, n0, n1);
+            if (u < nbu)
+                do_boxes(s, sc, cam, ego, L, u, (lptr<int32_t>)ws.tris);   // the staging is free here
+            else
+                road_unit(cam, L, live, gq, q0, q1);
             u = un;
             q0 = n0;
             q1 = n1;
             gq = gn;
             live = nlive;
-            continue;
-        } else {
-            break;
         }
-        if (ntri > 0) road_spans(L, cam, ws, ntri);
+        __syncthreads();
+        const int nring = L.cnt[R_RING];
+        const bool more = L.cnt[R_NEXT] < n_units;
+        // B2
+        for (;;) {
+            int j = 0;
+            if (ln == 0) j = lds_add(L.cnt + R_JOB, 1);
+            j = __builtin_amdgcn_readfirstlane(__shfl(j, 0));
+            const int a = j * kSetupBatch;
+            if (a >= nring) break;
+            int ntri = road_setup(s, cam, L, ws, a, min(kSetupBatch, nring - a));
+            if (ntri > 0) road_spans(L, cam, ws, ntri);
+            while (ws.nclip > 0) {
+                ntri = road_clip(s, cam, ws);
+                if (ntri > 0) road_spans(L, cam, ws, ntri);
+            }
+        }
+        __syncthreads();
+        if (!more) break;
+        if (tid == 0) {
+            L.cnt[R_RING] = 0;
+            L.cnt[R_RESV] = 0;
+            L.cnt[R_JOB] = 0;
+        }
+        __syncthreads();
     }
-    __syncthreads();
 
     // ---- C: resolve
     uint8_t *img = o.rgb + 3 * ((int64_t)view * W * H);
@@ -813,6 +834,7 @@ __device__ __forceinline__ void carve_rgb(unsigned char *smem, RgbLds &L, int W,
     L.btris = (lptr<TriRec>)(smem + l.btris);
     L.sbins = (lptr<int32_t>)(smem + l.sbins);
     L.cq = (lptr<int32_t>)(smem + l.cq);
+    L.sring = (lptr<int32_t>)(smem + l.sring);
     L.waves = (lptr<unsigned char>)(smem + l.waves);
     L.nw = (W + 63) >> 6;
     L.bcap = c.bcap;

@@ -405,15 +405,17 @@ gp_status render_impl(gp_sim *sim, const gp::RenderOut &o, const gp_launch &l, h
         return GP_OK;
     }
     const int64_t resident = (int64_t)l.blocks_per_cu * sim->n_cu;
-    if (sim->lay.n_views <= resident) {
+    if (sim->lay.n_views <= resident || split) {
         // every view gets a workgroup of its own: one launch over all views,
         // without the queue (whose empty segments would cost each workgroup a
-        // chain of device-scope atomics before it finds its view)
+        // chain of device-scope atomics before it finds its view).  The
+        // wave-split raster always launches so: with more views than fit the
+        // chip at once, the dispatcher hands each freed slot the next view
+        // (XCD-ordered), which balances uneven views without atomics
         e = split ? gp::launch_render_rgb(sim->dev, o, rc, 1, 0, (int)sim->lay.n_views, st)
                   : gp::launch_render(sim->dev, o, c, kind, 0, 0, (int)sim->lay.n_views, st);
     } else {
-        e = split ? gp::launch_render_rgb(sim->dev, o, rc, 2, 0, (int)resident, st)
-                  : gp::launch_render(sim->dev, o, c, kind, 1, 0, (int)resident, st);
+        e = gp::launch_render(sim->dev, o, c, kind, 1, 0, (int)resident, st);
     }
     if (e != hipSuccess) return hip_fail(e, "render launch");
     return GP_OK;
@@ -846,6 +848,9 @@ gp_status gp_sim_render_noalloc(gp_sim *sim, uint8_t *d_rgb, void *stream)
     return GP_OK;
 }
 
+// sims of at most this many views step and render by direct launches
+constexpr int64_t kGraphMinViews = 64;
+
 gp_status gp_sim_step_render_graph(gp_sim *sim, const float *d_actions, uint8_t *d_rgb, void *stream)
 {
     if (!sim || !d_actions || !d_rgb) return fail(GP_EINVAL, "NULL argument");
@@ -853,10 +858,19 @@ gp_status gp_sim_step_render_graph(gp_sim *sim, const float *d_actions, uint8_t 
         return fail(GP_EINVAL, "misaligned pointer");
     gp_launch l = sim->launch;
     l.sched = GP_SCHED_PERSISTENT;
+    if (sim->lay.n_views <= kGraphMinViews) {
+        // a few views render in less time than a graph replay costs on the
+        // host: the step and the render are launched directly
+        hipStream_t hs = static_cast<hipStream_t>(stream);
+        gp_status st = step_impl(sim, d_actions, l, hs);
+        if (st != GP_OK) return st;
+        const gp::RenderOut o{d_rgb, nullptr, nullptr};
+        return render_impl(sim, o, l, hs);
+    }
     if (!sim->gexec || sim->g_rgb != d_rgb || !same_launch(l, sim->g_launch)) {
         // the step as an explicit kernel node (so that a new action buffer
-        // only updates that node's arguments), then the render, captured,
-        // as a child graph that depends on it
+        // only updates that node's arguments), then the render's kernels,
+        // captured into the same graph behind it
         drop_graph(sim);
         hipGraph_t g = nullptr;
         hipError_t e = hipGraphCreate(&g, 0);
@@ -866,18 +880,16 @@ gp_status gp_sim_step_render_graph(gp_sim *sim, const float *d_actions, uint8_t 
             e = gp::step_graph_node(g, nullptr, &sim->g_step, sim->dev, d_actions);
             if (e != hipSuccess) { drop_graph(sim); return hip_fail(e, "step node"); }
         }
-        e = hipStreamBeginCapture(sim->capture_stream, hipStreamCaptureModeThreadLocal);
+        // the render's kernels captured into the same graph, after the step node
+        e = hipStreamBeginCaptureToGraph(sim->capture_stream, g, sim->g_step ? &sim->g_step : nullptr, nullptr,
+                                         sim->g_step ? 1 : 0, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) { drop_graph(sim); return hip_fail(e, "begin capture"); }
         gp::RenderOut o{d_rgb, nullptr, nullptr};
         gp_status st = render_impl(sim, o, l, sim->capture_stream);
         hipGraph_t rg = nullptr;
         e = hipStreamEndCapture(sim->capture_stream, &rg);
-        if (st != GP_OK) { if (rg) (void)hipGraphDestroy(rg); drop_graph(sim); return st; }
+        if (st != GP_OK) { drop_graph(sim); return st; }
         if (e != hipSuccess) { drop_graph(sim); return hip_fail(e, "end capture"); }
-        hipGraphNode_t child = nullptr;
-        e = hipGraphAddChildGraphNode(&child, g, sim->g_step ? &sim->g_step : nullptr, sim->g_step ? 1 : 0, rg);
-        (void)hipGraphDestroy(rg);       // the child node holds its own copy
-        if (e != hipSuccess) { drop_graph(sim); return hip_fail(e, "render node"); }
         e = hipGraphInstantiate(&sim->gexec, g, nullptr, nullptr, 0);
         if (e != hipSuccess) { drop_graph(sim); return hip_fail(e, "graph instantiate"); }
         sim->g_act = d_actions;
