@@ -13,6 +13,7 @@ needs no communication and this benchmark runs on one GPU only.
 from __future__ import annotations
 
 import argparse
+import glob
 import gc
 import json
 import os
@@ -31,7 +32,6 @@ HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 256 << 20
 # the workloads' episodes: 100 steps of random actions from the initial placement
 EPISODE_STEPS = 100
-COUNTERS = os.path.join(ROOT, "profiles", "k_render_rgb_uniform128_counters.txt")
 RASTER_KERNELS = {0: "k_render (banded)", 1: "k_render_rgb (wave-split)",
                   2: "k_chip_setup + k_chip_roads + k_chip_resolve (chip-wide)"}
 
@@ -54,28 +54,29 @@ def cpu_model() -> str:
 
 
 def measured_counters(workload_name: str, launch: dict):
-    """HBM traffic and VALU busy of the render kernel from the committed rocprofv3
-    counter summary, or None when that summary was taken on another kernel source,
-    workload or launch setting."""
-    if not os.path.exists(COUNTERS):
-        return None
-    kv = {}
-    with open(COUNTERS) as f:
-        for line in f:
-            if ":" in line and not line.startswith((" ", "#", "\t")):
-                k, v = line.split(":", 1)
-                kv[k.strip()] = v.strip()
-    try:
-        same = (kv["kernel_source_sha256"] == kernel_source_sha() and kv["workload"] == workload_name
-                and json.loads(kv["launch"]) == launch)
-        if not same:
-            return None
-        return {"traffic": float(kv["traffic_bytes_per_launch"]),
-                "valu_busy_pct": float(kv["valu_busy_pct"]),
-                "lds_bank_conflict_pct": float(kv["lds_bank_conflict_pct"]),
-                "valu_insts": float(kv["valu_insts_per_launch"])}
-    except (KeyError, ValueError):
-        return None
+    """HBM traffic and VALU busy of the render kernel from a committed rocprofv3
+    counter summary (profiles/*_counters.txt) taken on the same kernel source,
+    workload and launch setting, or None when there is none."""
+    sha = kernel_source_sha()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_counters.txt"))):
+        kv = {}
+        with open(path) as f:
+            for line in f:
+                if ":" in line and not line.startswith((" ", "#", "\t")):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        try:
+            if not (kv["kernel_source_sha256"] == sha and kv["workload"] == workload_name
+                    and json.loads(kv["launch"]) == launch):
+                continue
+            return {"traffic": float(kv["traffic_bytes_per_launch"]),
+                    "valu_busy_pct": float(kv["valu_busy_pct"]),
+                    "lds_bank_conflict_pct": float(kv["lds_bank_conflict_pct"]),
+                    "valu_insts": float(kv["valu_insts_per_launch"]),
+                    "source": os.path.relpath(path, ROOT)}
+        except (KeyError, ValueError):
+            continue
+    return None
 
 
 def _workload(args):
@@ -497,7 +498,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": meas["traffic"] if meas else None,
                      "kernel": RASTER_KERNELS.get(launch.get("raster"), "k_render"), "bytes_per_launch": rb,
                      "valu_busy_pct": meas["valu_busy_pct"] if meas else None,
-                     "lds_bank_conflict_pct": meas["lds_bank_conflict_pct"] if meas else None},
+                     "lds_bank_conflict_pct": meas["lds_bank_conflict_pct"] if meas else None,
+                     "counters_from": meas["source"] if meas else None},
         # the plain VALU roof beside the HBM one: wave instructions x 64 lanes
         # over the kernel time, against 256 CUs x 64 lanes x 2.4 GHz
         "valu_roof": ({"achieved": meas["valu_insts"] * 64 / (render_ms * 1e-3), "peak": VALU_PEAK,
