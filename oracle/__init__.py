@@ -184,9 +184,10 @@ def cover_tri(X, Y, W: int, H: int, count=None) -> np.ndarray:
 class View:
     """Output of one rendered view."""
 
-    def __init__(self, rgb, depth, primid, n_tri, n_frag):
+    def __init__(self, rgb, depth, primid, n_tri, n_frag, key=None):
         self.rgb, self.depth, self.primid = rgb, depth, primid
         self.n_tri, self.n_frag = n_tri, n_frag
+        self.key = key      # [H, W] uint64: each pixel's winning key (0 for background)
 
 
 def render_view(state, dims, agent_color, road_xy, road_color, camera, palette,
@@ -235,7 +236,7 @@ def render_view(state, dims, agent_color, road_xy, road_color, camera, palette,
     nt = lib().gpo_render_view(C.byref(sc), C.byref(cm), int(ego), C.c_float(cam_dir[0]),
                                C.c_float(cam_dir[1]), _ptr(key), _ptr(rgb), _ptr(depth),
                                _ptr(prim), C.byref(nf))
-    return View(rgb, depth, prim, int(nt), int(nf.value))
+    return View(rgb, depth, prim, int(nt), int(nf.value), key.reshape(H, W))
 
 
 def render_scene_view(scene, camera, palette, ego: int, cam: int = 0, light=None, backend: str = "raster") -> View:

@@ -229,6 +229,19 @@ __device__ __forceinline__ int road_setup(const DevSim &s, const Cam &cam, const
     return stage_tris(ws, v0, p0, v1, p1);
 }
 
+// One set-up job: the n ring strips from a set up, their primitives
+// rasterised into the coverage bitmask, then the strips that needed the
+// clipper, four at a time.
+__device__ __forceinline__ void setup_job(const DevSim &s, const Cam &cam, const RgbLds &L, WaveSt &ws, int a, int n)
+{
+    int ntri = road_setup(s, cam, L, ws, a, n);
+    if (ntri > 0) road_spans(L, cam, ws, ntri);
+    while (ws.nclip > 0) {
+        ntri = road_clip(s, cam, ws);
+        if (ntri > 0) road_spans(L, cam, ws, ntri);
+    }
+}
+
 // The cheap test of one unit's strips (loaded by load_unit into q0, q1); the
 // survivors' slots go to the view's ring (64 entries were reserved).
 __device__ __forceinline__ void road_unit(const Cam &cam, const RgbLds &L, bool live, int g, const float4 &q0,
@@ -643,7 +656,85 @@ __device__ __forceinline__ void resolve_band(const RgbLds &L, const Cam &cam, lp
     }
 }
 
+// Box rows [kr0, kr1) through bands of 64-bit keys (the whole workgroup; the
+// region from the surviving-bin list on is free): the view's box triangle
+// list, or, if it overflowed (ovf), the box faces streamed through it eight
+// candidates at a time (at most 96 triangles per pass) with the boxes culled
+// again.  wv / nwv: this wavefront among the workgroup's.
+__device__ __forceinline__ void key_band_rows(const DevSim &s, const SceneRec &sc, const Cam &cam, int ego, const RgbLds &L,
+                                              uint8_t *img, uint32_t road_rgb, uint32_t bg_rgb, int kr0, int kr1, bool ovf,
+                                              int nbt, int wv, int nwv)
+{
+    const int W = cam.W;
+    lptr<unsigned long long> keys = (lptr<unsigned long long>)L.sbins;
+    for (int b0 = kr0; b0 < kr1; b0 += L.krows) {
+        const int b1 = min(b0 + L.krows, kr1);
+        __syncthreads();
+        for (int p = (int)threadIdx.x; p < (b1 - b0) * W; p += (int)blockDim.x) keys[p] = 0ull;
+        __syncthreads();
+        if (!ovf) {
+            box_band(L, cam, keys, nbt, wv, nwv, b0, b1);
+        } else if (wv == 0) {
+            const int ncand = 6 * (sc.n_agents + sc.n_static);
+            for (int c0 = 0; c0 < ncand; c0 += 8) {
+                int n = 0, bmn = 0, bmx = 0;
+                (void)box_pass(s, sc, cam, ego, L, (lptr<const int32_t>)L.sbins, false, ncand, c0, 8, L.cq, false, n, bmn,
+                               bmx);
+                wave_lds_order();
+                box_band(L, cam, keys, n, 0, 1, b0, b1);
+                wave_lds_order();
+            }
+        }
+        __syncthreads();
+        resolve_band(L, cam, keys, img, road_rgb, bg_rgb, b0, b1);
+    }
+}
+
 // ------------------------------------------------------------ per view
+
+// Issue priority of the view's wavefronts (0..3) against the other views'
+// on the same SIMDs.  Every view of a launch is resident at once, so the
+// launch lasts as long as its slowest view: a view with much work left
+// raises its priority and the views with little fill the gaps.  Only the
+// instruction issue order changes, never a result.
+__device__ __forceinline__ void view_priority(int p)
+{
+    p = __builtin_amdgcn_readfirstlane(p);
+    if (p >= 3) __builtin_amdgcn_s_setprio(3);
+    else if (p == 2) __builtin_amdgcn_s_setprio(2);
+    else if (p == 1) __builtin_amdgcn_s_setprio(1);
+    else __builtin_amdgcn_s_setprio(0);
+}
+
+// The scene's road culling bins [b0, b0 + 64) against the view (frustum, road
+// depth limit and row-gap test); the survivors are appended to the view's
+// list of surviving bins.
+__device__ __forceinline__ void cull_bins(const DevSim &s, const SceneRec &sc, const Cam &cam, const RgbLds &L, int b0)
+{
+    const int ln = (int)lane_id();
+    const int b = b0 + ln;
+    bool keep = false;
+    int rec = 0;
+    if (b < sc.n_bins) {
+        const RoadBin bn = s.bins[sc.bin_base + b];
+        float x[4], z[4];
+        ground_xz(cam, bn.xmin, bn.ymin, x[0], z[0]);
+        ground_xz(cam, bn.xmax, bn.ymin, x[1], z[1]);
+        ground_xz(cam, bn.xmax, bn.ymax, x[2], z[2]);
+        ground_xz(cam, bn.xmin, bn.ymax, x[3], z[3]);
+        keep = !road_culled<true>(cam, x, z);
+        rec = bn.start * 128 + bn.count;
+    }
+    const unsigned long long bm = __ballot(keep);
+    const int nk = __popcll(bm);
+    int base = 0;
+    if (nk > 0) {
+        const int leader = __ffsll((long long)bm) - 1;
+        if (ln == leader) base = lds_add(L.cnt + R_NSB, nk);
+        base = __shfl(base, leader);
+    }
+    if (keep) L.sbins[base + lanes_below(bm)] = rec;
+}
 
 template <int K>
 __device__ __forceinline__ void render_view_rgb(const DevSim &s, const RenderOut &o, const RgbLds &L, int view)
@@ -662,30 +753,7 @@ __device__ __forceinline__ void render_view_rgb(const DevSim &s, const RenderOut
     __syncthreads();
 
     // ---- A: road culling bins
-    for (int b0 = 64 * wv; b0 < sc.n_bins; b0 += B) {
-        const int b = b0 + ln;
-        bool keep = false;
-        int rec = 0;
-        if (b < sc.n_bins) {
-            const RoadBin bn = s.bins[sc.bin_base + b];
-            float x[4], z[4];
-            ground_xz(cam, bn.xmin, bn.ymin, x[0], z[0]);
-            ground_xz(cam, bn.xmax, bn.ymin, x[1], z[1]);
-            ground_xz(cam, bn.xmax, bn.ymax, x[2], z[2]);
-            ground_xz(cam, bn.xmin, bn.ymax, x[3], z[3]);
-            keep = !road_culled<true>(cam, x, z);
-            rec = bn.start * 128 + bn.count;
-        }
-        const unsigned long long bm = __ballot(keep);
-        const int nk = __popcll(bm);
-        int base = 0;
-        if (nk > 0) {
-            const int leader = __ffsll((long long)bm) - 1;
-            if (ln == leader) base = lds_add(L.cnt + R_NSB, nk);
-            base = __shfl(base, leader);
-        }
-        if (keep) L.sbins[base + lanes_below(bm)] = rec;
-    }
+    for (int b0 = 64 * wv; b0 < sc.n_bins; b0 += B) cull_bins(s, sc, cam, L, b0);
     __syncthreads();
 
     // ---- B: rounds of two steps, each dealt over the view's wavefronts
@@ -697,6 +765,9 @@ __device__ __forceinline__ void render_view_rgb(const DevSim &s, const RenderOut
     // clipper for the strips that need it, and the spans of every primitive.
     // A round ends when the ring is full or the units are used up.
     const int nsb = L.cnt[R_NSB];
+    // road work ahead grows with the surviving bins (a mean view keeps about a dozen)
+    const int prio_b = nsb >= 24 ? 2 : (nsb >= 16 ? 1 : 0);
+    view_priority(prio_b);
     const int nbu = (sc.n_agents + sc.n_static + kBoxUnit - 1) / kBoxUnit;
     const int n_units = nbu + (nsb + 3) / 4;
     lptr<unsigned char> wbase = L.waves + (size_t)wv * kWaveBytes;
@@ -750,12 +821,7 @@ __device__ __forceinline__ void render_view_rgb(const DevSim &s, const RenderOut
             j = __builtin_amdgcn_readfirstlane(__shfl(j, 0));
             const int a = j * kSetupBatch;
             if (a >= nring) break;
-            int ntri = road_setup(s, cam, L, ws, a, min(kSetupBatch, nring - a));
-            if (ntri > 0) road_spans(L, cam, ws, ntri);
-            while (ws.nclip > 0) {
-                ntri = road_clip(s, cam, ws);
-                if (ntri > 0) road_spans(L, cam, ws, ntri);
-            }
+            setup_job(s, cam, L, ws, a, min(kSetupBatch, nring - a));
         }
         __syncthreads();
         if (!more) break;
@@ -778,6 +844,8 @@ __device__ __forceinline__ void render_view_rgb(const DevSim &s, const RenderOut
         kr0 = L.cnt[R_BMIN];
         kr1 = L.cnt[R_BMAX] + 1;
     }
+    // the box rows are the costly part of the resolve (a mean view has about a dozen)
+    view_priority(max(prio_b, kr1 - kr0 >= 64 ? 3 : (kr1 - kr0 >= 32 ? 2 : 0)));
     resolve_lut(L, cam, img, 0, kr0);
     resolve_lut(L, cam, img, kr1, H);
     const uint32_t road_rgb = L.pal[s.road_color0], bg_rgb = L.pal[0];
@@ -796,32 +864,7 @@ __device__ __forceinline__ void render_view_rgb(const DevSim &s, const RenderOut
         }
         return;
     }
-    // the key band path: lists that overflowed (streamed through the list)
-    lptr<unsigned long long> keys = (lptr<unsigned long long>)L.sbins;   // free after the units
-    for (int b0 = kr0; b0 < kr1; b0 += L.krows) {
-        const int b1 = min(b0 + L.krows, kr1);
-        __syncthreads();
-        for (int p = tid; p < (b1 - b0) * W; p += B) keys[p] = 0ull;
-        __syncthreads();
-        if (!ovf) {
-            box_band(L, cam, keys, nbt, wv, K, b0, b1);
-        } else if (wv == 0) {
-            // the list could not hold every box triangle: stream the box
-            // faces through it eight candidates at a time (at most 96
-            // triangles per pass), culling the boxes again
-            const int ncand = 6 * (sc.n_agents + sc.n_static);
-            for (int c0 = 0; c0 < ncand; c0 += 8) {
-                int n = 0, bmn = 0, bmx = 0;
-                (void)box_pass(s, sc, cam, ego, L, (lptr<const int32_t>)L.sbins, false, ncand, c0, 8, L.cq, false, n, bmn,
-                               bmx);
-                wave_lds_order();
-                box_band(L, cam, keys, n, 0, 1, b0, b1);
-                wave_lds_order();
-            }
-        }
-        __syncthreads();
-        resolve_band(L, cam, keys, img, road_rgb, bg_rgb, b0, b1);
-    }
+    key_band_rows(s, sc, cam, ego, L, img, road_rgb, bg_rgb, kr0, kr1, ovf, nbt, wv, K);
 }
 
 __device__ __forceinline__ void carve_rgb(unsigned char *smem, RgbLds &L, int W, int H, const RgbCfg &c)

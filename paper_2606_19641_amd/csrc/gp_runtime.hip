@@ -485,13 +485,6 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
     sim->cfg = *cfg;
     sim->n_scenes = n_scenes;
     sim->lay = L;
-    hipError_t e = hipGetDevice(&sim->device);
-    if (e != hipSuccess) { delete sim; return hip_fail(e, "hipGetDevice"); }
-    (void)hipDeviceGetAttribute(&sim->n_cu, hipDeviceAttributeMultiprocessorCount, sim->device);
-    int lds = 0;
-    (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, sim->device);
-    if (lds > 0) sim->max_lds = (size_t)lds;
-
     // host image of the workspace
     std::vector<unsigned char> host((size_t)L.upload_end, 0);
     auto at = [&](int64_t off) { return host.data() + off; };
@@ -613,6 +606,14 @@ gp_status gp_sim_create(const gp_config *cfg, const gp_scene_desc *scenes, int32
             ord[b] = queue[next[q]++];
         }
     }
+
+    // the device (everything above is host work on the host image)
+    hipError_t e = hipGetDevice(&sim->device);
+    if (e != hipSuccess) { delete sim; return hip_fail(e, "hipGetDevice"); }
+    (void)hipDeviceGetAttribute(&sim->n_cu, hipDeviceAttributeMultiprocessorCount, sim->device);
+    int lds = 0;
+    (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, sim->device);
+    if (lds > 0) sim->max_lds = (size_t)lds;
 
     unsigned char *base = static_cast<unsigned char *>(d_workspace);
     hipStream_t hs = static_cast<hipStream_t>(stream);

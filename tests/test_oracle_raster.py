@@ -297,3 +297,62 @@ def test_vertex_snap_rounds_to_nearest_subpixel(frac, covered):
     row = res // 2
     assert bool(v.primid[row, i] >= 0) == covered
     assert v.primid[row, i - 1] >= 0
+
+
+# ------------------------------------------------------------------ compositing
+
+_FAR = 1.0e5     # a position no camera of these scenes sees (beyond the far plane)
+
+
+def _only(scene, ego, box=None, road=None):
+    """The scene with one primitive group kept: the ego, box `box` and road
+    strip `road` where they are given; every other agent is moved far away
+    and every other strip collapsed to a far point, so that the numbering of
+    what is kept (6 box + face, 6 n_agents + strip) is unchanged."""
+    st = scene.agent_state.copy()
+    keep = {ego} | ({box} if box is not None else set())
+    for a in range(scene.n_agents):
+        if a not in keep:
+            st[a, 0] = _FAR
+            st[a, 1] = _FAR
+    rx = np.full_like(scene.road_xy, _FAR)
+    if road is not None:
+        rx[road] = scene.road_xy[road]
+    return g.Scene(agent_state=st, agent_dims=scene.agent_dims, agent_color=scene.agent_color,
+                   road_xy=rx, road_color=scene.road_color)
+
+
+@pytest.mark.parametrize("which", ["small", "crowded"])
+def test_render_is_the_per_pixel_max_of_single_primitive_renders(which):
+    """The depth test composes: every pixel's key in the full render is the
+    largest of its keys over renders that hold one box (its faces) or one
+    road strip each, and a pixel no single render covers is background.  A
+    depth test that lets a later primitive win regardless of depth, a key
+    that depends on what else was drawn, or coverage lost or added through
+    other primitives breaks the identity."""
+    if which == "small":
+        w = g.workload("small")
+        scene, cam, views = w.scenes[0], w.camera, [(0, 0), (5, 0)]
+    else:
+        scene, cam = g.crowded_scene(11, n_agents=12, n_roads=40), g.camera_for(48, cams=g.FRONT_AND_SIDES)
+        views = [(0, 0), (3, 1), (7, 2)]
+    pal = g.mixed_palette()
+    for ego, k in views:
+        full = oracle.render_scene_view(scene, cam, pal, ego, k)
+        comp = np.zeros_like(full.key)
+        drawn = 0
+        for b in range(scene.n_agents):
+            if b == ego:
+                continue
+            v = oracle.render_scene_view(_only(scene, ego, box=b), cam, pal, ego, k)
+            drawn += int((v.key != 0).any())
+            comp = np.maximum(comp, v.key)
+        for r in range(scene.n_roads):
+            v = oracle.render_scene_view(_only(scene, ego, road=r), cam, pal, ego, k)
+            drawn += int((v.key != 0).any())
+            comp = np.maximum(comp, v.key)
+        assert drawn >= 3, "too few primitives in view for the check to mean anything"
+        assert (full.key != 0).any() and (full.key == 0).any()
+        assert np.array_equal(comp, full.key), np.argwhere(comp != full.key)[:5]
+        empty = oracle.render_scene_view(_only(scene, ego), cam, pal, ego, k)
+        assert not empty.key.any()
