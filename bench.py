@@ -34,6 +34,8 @@ COPY_BYTES = 256 << 20
 EPISODE_STEPS = 100
 RASTER_KERNELS = {0: "k_render (banded)", 1: "k_render_rgb (wave-split)",
                   2: "k_chip_setup + k_chip_roads + k_chip_resolve (chip-wide)"}
+# the kernel field of a counter summary (profsum hbm --kernel) for each rasteriser
+COUNTER_KERNELS = {0: "k_render<", 1: "k_render_rgb", 2: "k_chip"}
 
 
 def kernel_source_sha() -> str:
@@ -55,8 +57,9 @@ def cpu_model() -> str:
 
 def measured_counters(workload_name: str, launch: dict):
     """HBM traffic and VALU busy of the render kernel from a committed rocprofv3
-    counter summary (profiles/*_counters.txt) taken on the same kernel source,
-    workload and launch setting, or None when there is none."""
+    counter summary (profiles/*_counters.txt) of that kernel taken on the same
+    kernel source, workload and launch setting, or None when there is none."""
+    kernel = COUNTER_KERNELS.get(launch.get("raster"))
     sha = kernel_source_sha()
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_counters.txt"))):
         kv = {}
@@ -67,7 +70,7 @@ def measured_counters(workload_name: str, launch: dict):
                     kv[k.strip()] = v.strip()
         try:
             if not (kv["kernel_source_sha256"] == sha and kv["workload"] == workload_name
-                    and json.loads(kv["launch"]) == launch):
+                    and kv["kernel"] == kernel and json.loads(kv["launch"]) == launch):
                 continue
             return {"traffic": float(kv["traffic_bytes_per_launch"]),
                     "valu_busy_pct": float(kv["valu_busy_pct"]),
