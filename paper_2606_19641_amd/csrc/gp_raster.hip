@@ -749,7 +749,10 @@ __device__ __forceinline__ void render_view_rgb(const DevSim &s, const RenderOut
     const int W = cam.W, H = cam.H;
 
     for (int p = tid; p < H * L.nw; p += B) L.bits[p] = 0ull;
-    if (tid < R_NCNT) L.cnt[tid] = tid == R_BMIN ? 0x7FFFFFFF : (tid == R_BMAX ? -1 : 0);
+    // road units are numbered after the box units (dealt as jobs, below)
+    if (tid < R_NCNT)
+        L.cnt[tid] = tid == R_BMIN ? 0x7FFFFFFF
+                   : (tid == R_BMAX ? -1 : (tid == R_NEXT ? (sc.n_agents + sc.n_static + kBoxUnit - 1) / kBoxUnit : 0));
     __syncthreads();
 
     // ---- A: road culling bins
@@ -757,13 +760,16 @@ __device__ __forceinline__ void render_view_rgb(const DevSim &s, const RenderOut
     __syncthreads();
 
     // ---- B: rounds of two steps, each dealt over the view's wavefronts
-    // through LDS counters.  B1: the units (u < nbu: boxes kBoxUnit u ..
-    // kBoxUnit u + kBoxUnit - 1; then four surviving bins each): box set-up, or
-    // the cheap test of a road unit's strips with the survivors appended to
-    // the view's ring (a road unit is taken only with 64 free ring entries
-    // reserved).  B2: set-up jobs of kSetupBatch ring strips: set-up, the
-    // clipper for the strips that need it, and the spans of every primitive.
-    // A round ends when the ring is full or the units are used up.
+    // through LDS counters.  B1: the road units (four surviving bins each,
+    // numbered from nbu on): the cheap test of the unit's strips with the
+    // survivors appended to the view's ring (a unit is taken only with 64
+    // free ring entries reserved).  B2: the jobs -- in the first round the box
+    // units first (boxes kBoxUnit k .. kBoxUnit k + kBoxUnit - 1: cull, face
+    // set-up and clipping into the box list, which is needed only by the
+    // resolve, so a long box unit overlaps the other wavefront's road jobs),
+    // then set-up jobs of kSetupBatch ring strips: set-up, the clipper for
+    // the strips that need it, and the spans of every primitive.  A round
+    // ends when the ring is full or the units are used up.
     const int nsb = L.cnt[R_NSB];
     // road work ahead grows with the surviving bins (a mean view keeps about a dozen)
     const int prio_b = nsb >= 24 ? 2 : (nsb >= 16 ? 1 : 0);
@@ -783,13 +789,14 @@ __device__ __forceinline__ void render_view_rgb(const DevSim &s, const RenderOut
             const int r = lds_add(L.cnt + R_RESV, 64);
             if (r + 64 <= kSharedRing) {
                 u = min(lds_add(L.cnt + R_NEXT, 1), n_units);
-                if (u < nbu || u == n_units) lds_add(L.cnt + R_RESV, -64);   // no strips from it
+                if (u == n_units) lds_add(L.cnt + R_RESV, -64);   // no unit left
             } else {
                 lds_add(L.cnt + R_RESV, -64);
             }
         }
         return __builtin_amdgcn_readfirstlane(__shfl(u, 0));
     };
+    int box_jobs = nbu;          // box units still to deal (first round)
     for (;;) {
         // B1, the next unit's strips loaded while the current one is tested
         int u = take();
@@ -801,10 +808,7 @@ __device__ __forceinline__ void render_view_rgb(const DevSim &s, const RenderOut
             float4 n0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), n1 = n0;
             int gn = 0;
             const bool nlive = un < n_units && load_unit(s, sc, L, nsb, un - nbu, gn, n0, n1);
-            if (u < nbu)
-                do_boxes(s, sc, cam, ego, L, u, (lptr<int32_t>)ws.tris);   // the staging is free here
-            else
-                road_unit(cam, L, live, gq, q0, q1);
+            road_unit(cam, L, live, gq, q0, q1);
             u = un;
             q0 = n0;
             q1 = n1;
@@ -818,12 +822,17 @@ __device__ __forceinline__ void render_view_rgb(const DevSim &s, const RenderOut
         for (;;) {
             int j = 0;
             if (ln == 0) j = lds_add(L.cnt + R_JOB, 1);
-            j = __builtin_amdgcn_readfirstlane(__shfl(j, 0));
+            j = __builtin_amdgcn_readfirstlane(__shfl(j, 0)) - box_jobs;
+            if (j < 0) {
+                do_boxes(s, sc, cam, ego, L, j + box_jobs, (lptr<int32_t>)ws.tris);   // the staging is free here
+                continue;
+            }
             const int a = j * kSetupBatch;
             if (a >= nring) break;
             setup_job(s, cam, L, ws, a, min(kSetupBatch, nring - a));
         }
         __syncthreads();
+        box_jobs = 0;
         if (!more) break;
         if (tid == 0) {
             L.cnt[R_RING] = 0;
