@@ -855,25 +855,31 @@ __device__ __forceinline__ void render_view_rgb(const DevSim &s, const RenderOut
     }
     // the box rows are the costly part of the resolve (a mean view has about a dozen)
     view_priority(max(prio_b, kr1 - kr0 >= 64 ? 3 : (kr1 - kr0 >= 32 ? 2 : 0)));
-    resolve_lut(L, cam, img, 0, kr0);
-    resolve_lut(L, cam, img, kr1, H);
     const uint32_t road_rgb = L.pal[s.road_color0], bg_rgb = L.pal[0];
     const int mrows = mask_rows_fit(L.region, nbt, W);
-    if (!ovf && nbt <= kMaskTris && mrows >= 1) {
-        // box rows through row masks, in chunks of rows whose items fit
+    if (!ovf && nbt <= kMaskTris && mrows >= 1 && kr0 < kr1) {
+        // box rows through row masks, in chunks of rows whose items fit; the
+        // rows outside them (the pattern table: coverage bits and table only)
+        // go with the first chunk's spans (which write the free region only)
         for (int c0 = kr0; c0 < kr1; c0 += mrows) {
             const int c1 = min(c0 + mrows, kr1);
-            __syncthreads();
+            if (c0 != kr0) __syncthreads();
             lptr<unsigned long long> M = (lptr<unsigned long long>)L.sbins;
             for (int p = tid; p < 2 * (W >> 4) * (c1 - c0); p += B) M[p] = 0ull;
             __syncthreads();
+            if (c0 == kr0) {
+                resolve_lut(L, cam, img, 0, kr0);
+                resolve_lut(L, cam, img, kr1, H);
+            }
             box_spans(L, cam, nbt, c0, c1, wv, K);
             __syncthreads();
             resolve_masks(L, cam, img, road_rgb, bg_rgb, c0, c1, wv, K);
         }
         return;
     }
-    key_band_rows(s, sc, cam, ego, L, img, road_rgb, bg_rgb, kr0, kr1, ovf, nbt, wv, K);
+    resolve_lut(L, cam, img, 0, kr0);
+    resolve_lut(L, cam, img, kr1, H);
+    if (kr0 < kr1) key_band_rows(s, sc, cam, ego, L, img, road_rgb, bg_rgb, kr0, kr1, ovf, nbt, wv, K);
 }
 
 __device__ __forceinline__ void carve_rgb(unsigned char *smem, RgbLds &L, int W, int H, const RgbCfg &c)
