@@ -46,8 +46,8 @@ namespace gp {
 
 namespace {
 
-constexpr int kSharedRing = 256;   // strips passed by the cheap test, one ring per view (road slot indices)
-constexpr int kWTris = 96;      // road primitives (quads, triangles) staged for one span pass
+constexpr int kSharedRing = 1024;  // strips passed by the cheap test, one ring per view (road slot indices)
+constexpr int kWTris = 64;      // road primitives (quads, triangles) staged for one span pass
 constexpr int kSetupBatch = kWTris / 2;   // strips set up at a time (two fan triangles each)
 constexpr int kWClip = kSetupBatch;       // road strips of one setup job waiting for the clipper
 constexpr int kWaveBytes = kWTris * 48 + kWClip * 4;

@@ -45,7 +45,7 @@ DEFAULT_SPACE = (
 # the short search the benchmark runs before timing (a few hundred renders)
 BENCH_SPACE = (
     _grid(raster=(2,), road_wgs_per_cu=(4, 8, 16))
-    + [dict(raster=1, view_waves=2, blocks_per_cu=8)]
+    + [dict(raster=1, view_waves=2, blocks_per_cu=8), dict(raster=1, view_waves=4, blocks_per_cu=4)]
     + _grid(raster=(0,), band_rows=(8, 16, 32), batch_tris=(256,), block_threads=(256,), blocks_per_cu=(2, 3))
     + _grid(raster=(0,), band_rows=(16,), batch_tris=(256, 512), block_threads=(512,), blocks_per_cu=(1, 2))
 )
