@@ -548,11 +548,14 @@ __device__ __forceinline__ void resolve_masks(const RgbLds &L, const Cam &cam, u
                 const uint32_t in = ((2u << hi) - 1u) & ~((1u << lo) - 1u);
                 const float bdv = fmaf(pk.y, dv, pk.z);
                 const uint32_t keylo = __float_as_uint(pk.w);
+                // branch-free: the three tests combined bitwise, so that each
+                // sample is a select and not a branch around the compare
 #pragma unroll
                 for (int m = 0; m < 16; ++m) {
                     const float invz = fmaf(pk.x, du0 + (float)m, bdv);
                     const unsigned long long key = ((unsigned long long)__float_as_uint(invz) << 32) | keylo;
-                    best[m] = (((in >> m) & 1u) && invz > 0.0f && key > best[m]) ? key : best[m];
+                    const bool take = (((in >> m) & 1u) != 0u) & (invz > 0.0f) & (key > best[m]);
+                    best[m] = take ? key : best[m];
                 }
             }
         }
@@ -561,9 +564,9 @@ __device__ __forceinline__ void resolve_masks(const RgbLds &L, const Cam &cam, u
         for (int m = 0; m < 16; ++m) {
             const unsigned long long kb = best[m];
             const bool road = (bits >> m) & 1u;
-            const bool box = kb != 0ull && (!road || (uint32_t)(kb >> 32) >= rzb);
-            c[m] = road ? road_rgb : bg_rgb;
-            if (box) c[m] = L.pal[(uint32_t)kb & 0xFFu];
+            const bool box = (kb != 0ull) & (!road | ((uint32_t)(kb >> 32) >= rzb));
+            const uint32_t boxc = L.pal[(uint32_t)kb & 0xFFu];   // any index is a palette entry
+            c[m] = box ? boxc : (road ? road_rgb : bg_rgb);
         }
         store16(img + 3 * ((int64_t)j * W + i), c);
     }
