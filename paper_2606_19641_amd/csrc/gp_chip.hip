@@ -828,9 +828,9 @@ __global__ __launch_bounds__(256) void k_chip_resolve(DevSim s, RenderOut o, Chi
         for (int m = 0; m < 16; ++m) {
             const unsigned long long kb = best[m];
             const bool road = (bits >> m) & 1u;
-            const bool box = kb != 0ull && (!road || (uint32_t)(kb >> 32) >= rzb);
-            c[m] = road ? road_rgb : bg_rgb;
-            if (box) c[m] = s_pal[(uint32_t)kb & 0xFFu];
+            const bool box = (kb != 0ull) & (!road | ((uint32_t)(kb >> 32) >= rzb));
+            const uint32_t boxc = s_pal[(uint32_t)kb & 0xFFu];   // any index is a palette entry
+            c[m] = box ? boxc : (road ? road_rgb : bg_rgb);
         }
         if (p.act) store16(reinterpret_cast<uint8_t *>(out), c);
     }

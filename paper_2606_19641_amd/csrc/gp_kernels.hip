@@ -853,8 +853,11 @@ __device__ __forceinline__ uint32_t fast_color(const Lds &L, bool road, float rz
                                               uint32_t road_rgb, uint32_t bg_rgb)
 {
     if (KEYS) {
-        const bool box = kb != 0ull && (!road || (uint32_t)(kb >> 32) >= __float_as_uint(rz));
-        if (box) return L.pal[(uint32_t)kb & 0xFFu];
+        // branch-free: both tests combined bitwise, the palette read
+        // unconditional (every index is an entry), then one select
+        const bool box = (kb != 0ull) & (!road | ((uint32_t)(kb >> 32) >= __float_as_uint(rz)));
+        const uint32_t boxc = L.pal[(uint32_t)kb & 0xFFu];
+        return box ? boxc : (road ? road_rgb : bg_rgb);
     }
     return road ? road_rgb : bg_rgb;
 }
@@ -865,7 +868,7 @@ __device__ __forceinline__ uint32_t fast_pixel(const Cam &cam, const Lds &L, int
 {
     const float dv = ((float)j + 0.5f) - cam.cy;
     const float rz = fmaf(cam.road.B, dv, cam.road.C);
-    const bool road = rz > 0.0f && ((L.road[(size_t)j * L.nw + (i >> 6)] >> (i & 63)) & 1ull);
+    const bool road = (rz > 0.0f) & (((L.road[(size_t)j * L.nw + (i >> 6)] >> (i & 63)) & 1ull) != 0ull);
     const unsigned long long kb = KEYS ? L.zb[(size_t)(j - zb0) * cam.W + i] : 0ull;
     return fast_color<KEYS>(L, road, rz, kb, road_rgb, bg_rgb);
 }

@@ -635,8 +635,9 @@ __device__ __forceinline__ void resolve_band(const RgbLds &L, const Cam &cam, lp
         for (int m = 0; m < 16; ++m) {
             const unsigned long long kb = kp[m];
             const bool road = (bits >> m) & 1u;
-            const bool box = kb != 0ull && (!road || (uint32_t)(kb >> 32) >= rzb);
-            c[m] = box ? L.pal[(uint32_t)kb & 0xFFu] : (road ? road_rgb : bg_rgb);
+            const bool box = (kb != 0ull) & (!road | ((uint32_t)(kb >> 32) >= rzb));
+            const uint32_t boxc = L.pal[(uint32_t)kb & 0xFFu];   // any index is a palette entry
+            c[m] = box ? boxc : (road ? road_rgb : bg_rgb);
         }
         u4 *out = reinterpret_cast<u4 *>(img + 3 * ((int64_t)j * W + i));
 #pragma unroll
