@@ -745,7 +745,7 @@ __global__ __launch_bounds__(256) void k_chip_resolve(DevSim s, RenderOut o, Chi
                 bool in = false;
                 if (t < nsr) {
                     const int32_t jj = ((lptr<const int32_t>)(sr + t))[6];
-                    in = (int)(int16_t)(jj & 0xFFFF) <= rl && (jj >> 16) >= r0;
+                    in = ((int)(int16_t)(jj & 0xFFFF) <= rl) & ((jj >> 16) >= r0);
                 }
                 const unsigned long long m = __ballot(in);
                 if (m == 0ull) continue;
@@ -793,7 +793,7 @@ __global__ __launch_bounds__(256) void k_chip_resolve(DevSim s, RenderOut o, Chi
                 bool in = false;
                 if (ln < kBoxBatch && t < nsb) {
                     const int32_t jj = ((lptr<const int32_t>)(sb + t))[6];
-                    in = (int)(int16_t)(jj & 0xFFFF) <= rl && (jj >> 16) >= r0;
+                    in = ((int)(int16_t)(jj & 0xFFFF) <= rl) & ((jj >> 16) >= r0);
                 }
                 const unsigned long long m = __ballot(in);
                 if (m == 0ull) continue;

@@ -195,16 +195,16 @@ __device__ __forceinline__ bool outside(const Cam &c, const V3 *v)
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const float ax = fabsf(v[k].x), ay = fabsf(v[k].y), az = fabsf(v[k].z);
-        n = n && (v[k].z - c.zn < 0.0f);
-        fa = fa && (c.zf - v[k].z < 0.0f);
+        n = n & (v[k].z - c.zn < 0.0f);
+        fa = fa & (c.zf - v[k].z < 0.0f);
         const float mx = 1e-3f * (ax + az) + 1e-6f;
         const float my = 1e-3f * (ay + az) + 1e-6f;
-        r = r && (fmaf(-c.t_right, v[k].z, v[k].x) > mx);
-        l = l && (fmaf(-c.t_left, v[k].z, -v[k].x) > mx);
-        t = t && (fmaf(-c.t_top, v[k].z, v[k].y) > my);
-        b = b && (fmaf(-c.t_bottom, v[k].z, -v[k].y) > my);
+        r = r & (fmaf(-c.t_right, v[k].z, v[k].x) > mx);
+        l = l & (fmaf(-c.t_left, v[k].z, -v[k].x) > mx);
+        t = t & (fmaf(-c.t_top, v[k].z, v[k].y) > my);
+        b = b & (fmaf(-c.t_bottom, v[k].z, -v[k].y) > my);
     }
-    return n || fa || l || r || t || b;
+    return n | fa | l | r | t | b;
 }
 
 // Whole-box rejection by the box's bounding cylinder (radius hl + hw >= half
@@ -220,13 +220,10 @@ __device__ __forceinline__ bool box_outside(const DevSim &s, const SceneRec &sc,
     const float x = fmaf(ox, c.fy, -(oy * c.fx));
     const float m = 1e-3f * (fabsf(x) + fabsf(z) + r + dm.z + c.h) + 1e-4f;
     const float zmax = z + r, zmin = z - r;
-    if (zmax < c.zn - m) return true;
-    if (zmin > c.zf + m) return true;
-    if (x - c.t_right * z - r * (1.0f + c.t_right) > m) return true;
-    if (-x - c.t_left * z - r * (1.0f + c.t_left) > m) return true;
-    if (-(dm.z - c.h) - c.t_bottom * zmax > m) return true;
-    if (-c.h - c.t_top * zmax > m) return true;
-    return false;
+    // the six tests combined bitwise (no divergent early exits)
+    return (zmax < c.zn - m) | (zmin > c.zf + m) | (x - c.t_right * z - r * (1.0f + c.t_right) > m) |
+           (-x - c.t_left * z - r * (1.0f + c.t_left) > m) | (-(dm.z - c.h) - c.t_bottom * zmax > m) |
+           (-c.h - c.t_top * zmax > m);
 }
 
 // Road geometry lies at camera height -h, so a road point at depth z projects
@@ -236,7 +233,7 @@ __device__ __forceinline__ bool box_outside(const DevSim &s, const SceneRec &sc,
 // above the horizon) and covers no sample.
 __device__ __forceinline__ bool road_beyond(const Cam &c, const V3 *v)
 {
-    return v[0].z > c.road_zmax && v[1].z > c.road_zmax && v[2].z > c.road_zmax && v[3].z > c.road_zmax;
+    return (v[0].z > c.road_zmax) & (v[1].z > c.road_zmax) & (v[2].z > c.road_zmax) & (v[3].z > c.road_zmax);
 }
 
 __device__ __forceinline__ bool bin_outside(const DevSim &s, const Cam &c, const RoadBin &b)
@@ -246,7 +243,7 @@ __device__ __forceinline__ bool bin_outside(const DevSim &s, const Cam &c, const
     v[1] = to_cam(c, b.xmax - c.px, b.ymin - c.py, 0.0f);
     v[2] = to_cam(c, b.xmax - c.px, b.ymax - c.py, 0.0f);
     v[3] = to_cam(c, b.xmin - c.px, b.ymax - c.py, 0.0f);
-    return outside(c, v) || road_beyond(c, v);
+    return outside(c, v) | road_beyond(c, v);
 }
 
 // clip plane signed distance; >= 0 is inside
@@ -268,7 +265,7 @@ __device__ __forceinline__ bool needs_clip(const Cam &c, const V3 *v)
 #pragma unroll
     for (int k = 0; k < 4; ++k)
 #pragma unroll
-        for (int pl = 0; pl < 6; ++pl) ok = ok && (plane_dist(pl, c, v[k]) >= 0.0f);
+        for (int pl = 0; pl < 6; ++pl) ok = ok & (plane_dist(pl, c, v[k]) >= 0.0f);
     return !ok;
 }
 
@@ -394,7 +391,7 @@ __device__ __forceinline__ bool row_span(const TriGeo &t, int j, int W, int &xl_
             const double tk = (dY < 0 || (dY == 0 && dX > 0)) ? 0.0 : 1.0;
             const double P = fma((double)dX, Sy - (double)Y[k], (double)dY * ((double)X[k] - 128.0));
             const double N = P - tk;
-            empty = empty || (dY == 0 && N < 0.0);
+            empty = empty | ((dY == 0) & (N < 0.0));
             const double D = 256.0 * (double)abs(dY);
             // floor(N / D) from a binary32 reciprocal estimate (relative
             // error below 2^-21, so within 1 of the quotient wherever it lies
@@ -607,7 +604,7 @@ __device__ __forceinline__ bool prim_span(const Prim &p, int j, int W, int &xl_o
         const double tk = (dY < 0 || (dY == 0 && dX > 0)) ? 0.0 : 1.0;
         const double P = fma((double)dX, Sy - (double)Y[k], (double)dY * ((double)X[k] - 128.0));
         const double N = P - tk;
-        empty = empty || (dY == 0 && N < 0.0);
+        empty = empty | ((dY == 0) & (N < 0.0));
         const double D = 256.0 * (double)abs(dY);
         const double qe = (double)((float)N * __builtin_amdgcn_rcpf((float)D));
         double f = fmin(fmax(floor(qe), -Wd - 1.0), Wd + 1.0);
@@ -783,7 +780,7 @@ __device__ __forceinline__ bool clip_seg(const Cam &cam, const Poly &P, bool liv
         const bool ia = da >= 0.0f, ib = db >= 0.0f;
         // every vertex of every segment inside: the walks emit the polygons unchanged
         if (__ballot(act && !ia) == 0ull) continue;
-        const bool e0 = act && ia, e1 = act && (ia != ib);
+        const bool e0 = act & ia, e1 = act & (ia != ib);
         V3 r = v;
         if (e1) {
             const V3 pin = sel_v3(ia, v, b), pout = sel_v3(ia, b, v);
@@ -940,16 +937,16 @@ __device__ __forceinline__ bool road_culled(const Cam &c, const float *x, const 
     for (int k = 0; k < 4; ++k) {
         const float ax = fabsf(x[k]), az = fabsf(z[k]);
         const float dz = BIN ? fmaf(ax + az, 0x1p-20f, 1e-6f) : 0.0f;
-        n = n && (z[k] - c.zn < -dz);
-        fa = fa && (z[k] - zlim > dz);
+        n = n & (z[k] - c.zn < -dz);
+        fa = fa & (z[k] - zlim > dz);
         const float mx = 1e-3f * (ax + az) + 1e-6f;
-        r = r && (fmaf(-c.t_right, z[k], x[k]) > mx);
-        l = l && (fmaf(-c.t_left, z[k], -x[k]) > mx);
+        r = r & (fmaf(-c.t_right, z[k], x[k]) > mx);
+        l = l & (fmaf(-c.t_left, z[k], -x[k]) > mx);
         zmin = fminf(zmin, z[k] - dz);
         zmax = fmaxf(zmax, z[k] + dz);
     }
-    if (n || fa || l || r) return true;
-    return road_rows_empty(c, zmin, zmax);
+    // combined bitwise (no branch; the row test is cheap next to a divergent exit)
+    return n | fa | l | r | road_rows_empty(c, zmin, zmax);
 }
 
 // camera-space x and z of a ground point (world x, y)

@@ -233,7 +233,7 @@ __device__ __forceinline__ bool footprints_overlap(float4 si, float2 ci, float h
     for (int e = 0; e < 4; ++e) {
         const float ri = reach(hli, hwi, ci.x, ci.y, ax[e], ay[e]);
         const float rj = reach(hlj, hwj, cj.x, cj.y, ax[e], ay[e]);
-        sep = sep || (fabsf(dot2(dx, dy, ax[e], ay[e])) >= ri + rj);
+        sep = sep | (fabsf(dot2(dx, dy, ax[e], ay[e])) >= ri + rj);
     }
     return !sep;
 }
