@@ -243,7 +243,7 @@ __device__ __forceinline__ bool bin_outside(const DevSim &s, const Cam &c, const
     v[1] = to_cam(c, b.xmax - c.px, b.ymin - c.py, 0.0f);
     v[2] = to_cam(c, b.xmax - c.px, b.ymax - c.py, 0.0f);
     v[3] = to_cam(c, b.xmin - c.px, b.ymax - c.py, 0.0f);
-    return outside(c, v) | road_beyond(c, v);
+    return ((int)outside(c, v) | (int)road_beyond(c, v)) != 0;
 }
 
 // clip plane signed distance; >= 0 is inside

@@ -46,10 +46,11 @@ namespace gp {
 
 namespace {
 
-constexpr int kSharedRing = 1024;  // strips passed by the cheap test, one ring per view (road slot indices)
+constexpr int kSharedRing = 768;   // strips passed by the cheap test, one ring per view (road slot indices)
 constexpr int kWTris = 64;      // road primitives (quads, triangles) staged for one span pass
-constexpr int kSetupBatch = kWTris / 2;   // strips set up at a time (two fan triangles each)
-constexpr int kWClip = kSetupBatch;       // road strips of one setup job waiting for the clipper
+constexpr int kSetupBatch = kWTris;       // strips of one set-up job at most (one quad each; the rest are queued)
+constexpr int kWClip = kSetupBatch;       // strips of one job waiting for the clipper (from the front) or
+                                          // for their fan triangles (from the back)
 constexpr int kWaveBytes = kWTris * 48 + kWClip * 4;
 static_assert(kWaveBytes % 16 == 0, "wave regions stay 16-byte aligned");
 static_assert(sizeof(Prim) == 48, "staged primitive size");
@@ -101,8 +102,9 @@ __host__ __device__ inline RgbLayout rgb_layout(int W, int H, const RgbCfg &c)
 
 struct WaveSt {
     lptr<Prim> tris;         // [kWTris] road primitives
-    lptr<int32_t> clipq;     // [kWClip] road slots (global) that need the clipper
-    int nclip;               // queued strips
+    lptr<int32_t> clipq;     // [kWClip] road slots (global): nclip for the clipper at the front,
+                             // nfan for their two fan triangles at the back
+    int nclip, nfan;         // queued strips
 };
 
 // OR the samples [xl, xr] of one row into its coverage words
@@ -189,10 +191,37 @@ __device__ __forceinline__ int road_clip(const DevSim &s, const Cam &cam, WaveSt
     return stage_tris(ws, ok, prim_of(t.g), false, none);
 }
 
+// The two fan triangles of up to 32 queued strips (the last ones queued at
+// the back of the queue); stages them and returns how many.  Their corners
+// and snap are computed again, as the set-up computed them.
+__device__ __forceinline__ int road_fan(const DevSim &s, const Cam &cam, WaveSt &ws)
+{
+    const int m = min(ws.nfan, 32);
+    const int ln = (int)lane_id();
+    Prim p0 = {}, p1 = {};
+    bool v0 = false, v1 = false;
+    if (ln < m) {
+        const int g = ws.clipq[kWClip - ws.nfan + ln];
+        V3 v[4];
+        road_corners(s, cam, g, v);
+        int32_t X[4], Y[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) snap(cam, v[k], X[k], Y[k]);
+        TriGeo t0, t1;
+        v0 = make_tri(cam, false, X[0], Y[0], X[1], Y[1], X[2], Y[2], 0, cam.H, t0);
+        v1 = make_tri(cam, false, X[0], Y[0], X[2], Y[2], X[3], Y[3], 0, cam.H, t1);
+        if (v0) p0 = prim_of(t0);
+        if (v1) p1 = prim_of(t1);
+    }
+    ws.nfan -= m;
+    return stage_tris(ws, v0, p0, v1, p1);
+}
+
 // Full setup of the n (<= kSetupBatch) strips ring[a .. a + n): clip test,
-// snap and a quad or the two fan triangles of the strips that need no
-// clipping (staged; returns how many); the others join the wave's clip queue
-// (empty when a job starts).
+// snap, and the quad of the strips whose quad covers exactly what their two
+// fan triangles cover (staged; returns how many); strips that need the
+// clipper join the front of the wave's queue, strips that need their fan
+// triangles its back (both empty when a job starts).
 __device__ __forceinline__ int road_setup(const DevSim &s, const Cam &cam, const RgbLds &L, WaveSt &ws, int a, int n)
 {
     const int ln = (int)lane_id();
@@ -208,37 +237,38 @@ __device__ __forceinline__ int road_setup(const DevSim &s, const Cam &cam, const
     const unsigned long long cb = __ballot(clip);
     if (clip) ws.clipq[ws.nclip + lanes_below(cb)] = g;
     ws.nclip += __popcll(cb);
-    Prim p0 = {}, p1 = {};
-    bool v0 = false, v1 = false;
+    Prim p0 = {};
+    bool v0 = false, fan = false;
     if (live && !clip) {
         int32_t X[4], Y[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) snap(cam, v[k], X[k], Y[k]);
         // one quad where it covers exactly what the two fan triangles cover
         const int qs = make_quad(cam, X, Y, 0, cam.H, p0);
-        if (qs > 0) {
-            v0 = true;
-        } else if (qs < 0) {
-            TriGeo t0, t1;
-            v0 = make_tri(cam, false, X[0], Y[0], X[1], Y[1], X[2], Y[2], 0, cam.H, t0);
-            v1 = make_tri(cam, false, X[0], Y[0], X[2], Y[2], X[3], Y[3], 0, cam.H, t1);
-            if (v0) p0 = prim_of(t0);
-            if (v1) p1 = prim_of(t1);
-        }
+        v0 = qs > 0;
+        fan = qs < 0;
     }
-    return stage_tris(ws, v0, p0, v1, p1);
+    const unsigned long long fb = __ballot(fan);
+    if (fan) ws.clipq[kWClip - 1 - (ws.nfan + lanes_below(fb))] = g;
+    ws.nfan += __popcll(fb);
+    Prim none = {};
+    return stage_tris(ws, v0, p0, false, none);
 }
 
 // One set-up job: the n ring strips from a set up, their primitives
-// rasterised into the coverage bitmask, then the strips that needed the
-// clipper, four at a time.
+// rasterised into the coverage bitmask, then the strips that needed their fan
+// triangles (32 at a time) and those that needed the clipper (four at a time).
 __device__ __forceinline__ void setup_job(const DevSim &s, const Cam &cam, const RgbLds &L, WaveSt &ws, int a, int n)
 {
     int ntri = road_setup(s, cam, L, ws, a, n);
-    if (ntri > 0) road_spans(L, cam, ws, ntri);
-    while (ws.nclip > 0) {
-        ntri = road_clip(s, cam, ws);
+    for (;;) {
         if (ntri > 0) road_spans(L, cam, ws, ntri);
+        if (ws.nfan > 0)
+            ntri = road_fan(s, cam, ws);
+        else if (ws.nclip > 0)
+            ntri = road_clip(s, cam, ws);
+        else
+            break;
     }
 }
 
@@ -771,9 +801,10 @@ __device__ __forceinline__ void render_view_rgb(const DevSim &s, const RenderOut
     // units first (boxes kBoxUnit k .. kBoxUnit k + kBoxUnit - 1: cull, face
     // set-up and clipping into the box list, which is needed only by the
     // resolve, so a long box unit overlaps the other wavefront's road jobs),
-    // then set-up jobs of kSetupBatch ring strips: set-up, the clipper for
-    // the strips that need it, and the spans of every primitive.  A round
-    // ends when the ring is full or the units are used up.
+    // then set-up jobs of up to kSetupBatch ring strips: set-up, the fan
+    // triangles and the clipper for the strips that need them, and the spans
+    // of every primitive.  A round ends when the ring is full or the units
+    // are used up.
     const int nsb = L.cnt[R_NSB];
     // road work ahead grows with the surviving bins (a mean view keeps about a dozen)
     const int prio_b = nsb >= 24 ? 2 : (nsb >= 16 ? 1 : 0);
@@ -785,6 +816,7 @@ __device__ __forceinline__ void render_view_rgb(const DevSim &s, const RenderOut
     ws.tris = (lptr<Prim>)wbase;
     ws.clipq = (lptr<int32_t>)(wbase + kWTris * 48);
     ws.nclip = 0;
+    ws.nfan = 0;
     // the next unit with its ring entries reserved, or n_units (none left, or
     // the ring cannot take another road unit this round)
     auto take = [&]() -> int {
@@ -822,6 +854,11 @@ __device__ __forceinline__ void render_view_rgb(const DevSim &s, const RenderOut
         __syncthreads();
         const int nring = L.cnt[R_RING];
         const bool more = L.cnt[R_NEXT] < n_units;
+        // the ring cut into jobs of at most kSetupBatch strips, as many as a
+        // multiple of the wavefronts, of equal size: a job's set-up takes about
+        // the same time for any number of strips up to a wavefront's width
+        const int njobs = (max(K, (nring + kSetupBatch - 1) / kSetupBatch) + K - 1) / K * K;
+        const int jsz = (nring + njobs - 1) / njobs;
         // B2
         for (;;) {
             int j = 0;
@@ -831,9 +868,9 @@ __device__ __forceinline__ void render_view_rgb(const DevSim &s, const RenderOut
                 do_boxes(s, sc, cam, ego, L, j + box_jobs, (lptr<int32_t>)ws.tris);   // the staging is free here
                 continue;
             }
-            const int a = j * kSetupBatch;
+            const int a = j * jsz;
             if (a >= nring) break;
-            setup_job(s, cam, L, ws, a, min(kSetupBatch, nring - a));
+            setup_job(s, cam, L, ws, a, min(jsz, nring - a));
         }
         __syncthreads();
         box_jobs = 0;
