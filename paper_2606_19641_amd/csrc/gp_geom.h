@@ -859,14 +859,27 @@ __device__ __forceinline__ int wave_incl_scan(int v)
     return v;
 }
 
-// number of lanes whose inclusive prefix is <= g: the lane that owns item g
+// number of lanes whose inclusive prefix (non-decreasing over the lanes) is
+// <= g, at most 63: the lane that owns item g.  A binary search whose first
+// three levels probe lanes that are the same for every lane (31; 15 or 47; 7,
+// 23, 39 or 55), read as scalars, and whose last three levels are replaced by
+// counting lanes t .. t + 6 with seven independent shuffles: one cross-lane
+// round trip instead of six dependent ones.  Every lane of the wavefront takes
+// part.
 __device__ __forceinline__ int owner_of(int incl, int g)
 {
-    int t = 0;
+    const int s31 = __builtin_amdgcn_readlane(incl, 31);
+    const int s15 = __builtin_amdgcn_readlane(incl, 15), s47 = __builtin_amdgcn_readlane(incl, 47);
+    const int s7 = __builtin_amdgcn_readlane(incl, 7), s23 = __builtin_amdgcn_readlane(incl, 23);
+    const int s39 = __builtin_amdgcn_readlane(incl, 39), s55 = __builtin_amdgcn_readlane(incl, 55);
+    int t = s31 <= g ? 32 : 0;
+    t += (t ? s47 : s15) <= g ? 16 : 0;
+    const int c8 = t == 0 ? s7 : (t == 16 ? s23 : (t == 32 ? s39 : s55));
+    t += c8 <= g ? 8 : 0;
+    int n = 0;
 #pragma unroll
-    for (int step = 32; step > 0; step >>= 1)
-        if (__shfl(incl, t + step - 1) <= g) t += step;
-    return min(t, 63);
+    for (int k = 0; k < 7; ++k) n += __shfl(incl, t + k) <= g ? 1 : 0;
+    return t + n;
 }
 
 __device__ __forceinline__ int wave_min(int v)
